@@ -1,0 +1,242 @@
+"""Throughput of the hybrid rotation hot path on one MI355X.
+
+Workload (default): 28 qubits, complex128 (4 GiB state), 10 first-order
+Trotter steps of a 2,000-term JW-shaped Hamiltonian = 20,000 Pauli rotations,
+then <H> for the same 2,000 terms.  One timed step runs the whole path:
+encode the strings (a1), route them through the Pauli frame (a2, a3), reset
+the state, apply every rotation with the planned fused LDS passes (a4-a7) and
+reduce <H> (a8).  The plan (a4) is built once before timing: it is reusable
+across steps and owns device buffers.
+
+Also reported: the same rotations one HBM pass each (unfused), the complex64
+run and its error against complex128, the adjoint gradient (a9) time against
+its forward on the 20-qubit ansatz, and the CPU oracle on a bounded sample.
+
+Prints ONE JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_source_hash() -> str:
+    with open(os.path.join(ROOT, "paper_2602_09020_amd", "csrc", "kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def counter_traffic(name: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", name)
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=28)
+    ap.add_argument("--trotter-steps", type=int, default=10)
+    ap.add_argument("--no-extras", action="store_true", help="skip unfused/c64/adjoint/cpu legs")
+    ap.add_argument("--cpu-rotations", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: the state-vector path is single-device here "
+              "(sharding design only, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2602_09020_amd import cfh, hybrid
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = W.config(2, n=args.n, trotter_steps=args.trotter_steps)
+    n, K = w.n, w.n_rot
+    dtype = torch.complex128
+    enc0 = cfh.cfh_pauli_encode(w.rot)
+    frame0 = hybrid.Frame(n)
+    rot0 = frame0.conjugate(enc0)
+    t0 = time.perf_counter()
+    plan = hybrid.Plan(n, dtype, rot0)
+    ham = hybrid.Hamiltonian(n, dtype, frame0.conjugate(cfh.cfh_pauli_encode(w.ham)), w.coeff)
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    info = plan.info()
+    hinfo = ham.info()
+    theta = torch.tensor(w.theta, device=dev)
+    psi = torch.empty(1 << n, dtype=dtype, device=dev)
+    e_out = torch.zeros(2, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    ev_rot = []
+
+    def step(record):
+        # a1 encode, a2 frame (config has no Clifford prefix: identity frame), a3 conjugate
+        enc = cfh.cfh_pauli_encode(w.rot)
+        frame = hybrid.Frame(n)
+        frame.apply_gates(w.prefix)
+        rot = frame.conjugate(enc)
+        assert rot.shape[0] == K
+        cfh.cfh_state_set_basis(psi, n, w.init)
+        if record:
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+        plan.apply(psi, theta)
+        if record:
+            b.record(stream)
+            ev_rot.append((a, b))
+        ham.expval_async(psi, e_out)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed * 1e3 / args.steps
+    rot_ms = [a.elapsed_time(b) for a, b in ev_rot]
+    launches = info["n_passes"]
+    # the apply_plan region is one tiny angle kernel plus `launches` fused pass kernels
+    pass_ms = float(np.mean(rot_ms)) / launches
+    amp_b = 16
+    pass_bytes = 2.0 * (1 << n) * amp_b
+    achieved_gbs = pass_bytes / (pass_ms * 1e-3) / 1e9
+    energy = float(e_out[0].item())
+    value = K / (ms_per_step * 1e-3)
+    traffic = counter_traffic(f"k_pass_n{n}_c128_counters.json")
+
+    out = {
+        "metric": "Pauli rotations/s + HBM GB/s at n=28 c128; adjoint grad time vs forward",
+        "value": value,
+        "unit": "rotations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_qubits": n, "state": "complex128", "rotations": K,
+                   "hamiltonian_terms": int(w.ham.shape[0]), "trotter_steps": args.trotter_steps,
+                   "dt": 0.05, "coeff_sigma": 0.1, "seed": 0},
+        "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": f"k_pass<double2,{info['tile_bits']}>",
+                     "bytes_per_launch": pass_bytes, "avg_launch_ms": pass_ms},
+        "passes": launches,
+        "fusion_depth": K / launches,
+        "rotation_phase_ms": float(np.mean(rot_ms)),
+        "expval": {"value": energy, "passes": hinfo["n_passes"], "groups": hinfo["n_groups"]},
+        "plan_ms": plan_ms,
+    }
+
+    if not args.no_extras:
+        # unfused: one HBM pass per rotation, on a 1,000-rotation prefix
+        Ku = min(1000, K)
+        pu = hybrid.Plan(n, dtype, rot0[:Ku], {"unfused": 1})
+        th_u = theta[:Ku].contiguous()
+        cfh.cfh_state_set_basis(psi, n, w.init)
+        pu.apply(psi, th_u)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        pu.apply(psi, th_u)
+        b.record(stream)
+        torch.cuda.synchronize()
+        u_ms = a.elapsed_time(b)
+        out["unfused"] = {"rotations": Ku, "rotations_per_s": Ku / (u_ms * 1e-3),
+                          "avg_launch_ms": u_ms / Ku,
+                          "achieved_gbs": pass_bytes / (u_ms / Ku * 1e-3) / 1e9}
+        del pu
+
+        # complex64 storage, full workload, error against the complex128 result
+        cfh.cfh_state_set_basis(psi, n, w.init)
+        plan.apply(psi, theta)
+        p64 = hybrid.Plan(n, torch.complex64, rot0)
+        psi64 = torch.empty(1 << n, dtype=torch.complex64, device=dev)
+        cfh.cfh_state_set_basis(psi64, n, w.init)
+        p64.apply(psi64, theta)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        cfh.cfh_state_set_basis(psi64, n, w.init)
+        a.record(stream)
+        p64.apply(psi64, theta)
+        b.record(stream)
+        torch.cuda.synchronize()
+        c64_ms = a.elapsed_time(b)
+        err = float((psi64.to(torch.complex128) - psi).abs().max().item())
+        i64 = p64.info()
+        out["c64"] = {"rotations_per_s": K / (c64_ms * 1e-3), "passes": i64["n_passes"],
+                      "avg_launch_ms": c64_ms / i64["n_passes"],
+                      "achieved_gbs": 2.0 * (1 << n) * 8 / (c64_ms / i64["n_passes"] * 1e-3) / 1e9,
+                      "max_abs_err_vs_c128": err}
+        del psi64, p64
+        torch.cuda.empty_cache()
+
+        # adjoint gradient vs forward on the 20-qubit, 1,000-rotation ansatz
+        wa = W.config(3)
+        _, rot_a, terms_a, plan_a, ham_a = hybrid.prepare(wa, dtype)
+        th_a = torch.tensor(wa.theta, device=dev)
+        psi_a = torch.empty(1 << wa.n, dtype=dtype, device=dev)
+        lam = torch.empty_like(psi_a)
+        grad = torch.empty_like(th_a)
+        eo = torch.zeros(2, dtype=torch.float64, device=dev)
+        fw, bw = [], []
+        for it in range(4):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            cfh.cfh_state_set_basis(psi_a, wa.n, wa.init)
+            ev[0].record(stream)
+            plan_a.apply(psi_a, th_a)
+            ham_a.expval_async(psi_a, eo)
+            ev[1].record(stream)
+            cfh.cfh_adjoint_grad(plan_a.h, ham_a.h, psi_a, lam, th_a, grad)
+            ev[2].record(stream)
+            torch.cuda.synchronize()
+            if it:
+                fw.append(ev[0].elapsed_time(ev[1]))
+                bw.append(ev[1].elapsed_time(ev[2]))
+        out["adjoint"] = {"workload": wa.name, "n_qubits": wa.n, "rotations": wa.n_rot,
+                          "hamiltonian_terms": int(wa.ham.shape[0]),
+                          "forward_ms": float(np.median(fw)), "backward_ms": float(np.median(bw)),
+                          "backward_over_forward": float(np.median(bw) / np.median(fw)),
+                          "passes": plan_a.info()["n_passes"]}
+
+        # CPU oracle (ladder decomposition) on a bounded sample of the same workload
+        from oracle import sim
+        kc = args.cpu_rotations
+        v = np.zeros(1 << n, dtype=np.complex128)
+        v[w.init] = 1
+        t0 = time.perf_counter()
+        sim.rotations(v, n, w.rot[:kc], w.theta[:kc])
+        cpu_s = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": kc / cpu_s, "unit": "rotations/s", "cores": sim.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"first {kc} rotations of the {n}-qubit workload, dense complex128, "
+                                         f"gate-by-gate CNOT-ladder decomposition ({cpu_s:.1f} s)"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

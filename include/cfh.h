@@ -1,0 +1,252 @@
+/*
+ * cfh.h - C ABI of libcfh, the MI355X (gfx950) hot path of the
+ * Clifford-fullstate hybrid simulator (CFHS) of arXiv 2602.09020.
+ *
+ * The simulator state is a pair (F, Phi) (Sec. 4.2, Eq. cfhsstate): F is a
+ * Pauli frame (2n Pauli rows effZ_q = U^dag Z_q U, effX_q = U^dag X_q U, the
+ * backward interpretation of Sec. 4.1) standing for a Clifford unitary U, and
+ * Phi is a 2^n complex amplitude vector; the physical state is U Phi.
+ * Clifford gates only update F; a rotation exp(-i theta/2 P) of the physical
+ * circuit is applied to Phi as exp(-i theta/2 F(P)) with F(P) = U^dag P U
+ * (Eq. single_to_multirot, Eq. Fmap); expectation values are <Phi|F(P)|Phi>
+ * (Eq. chfsexp).
+ *
+ * Conventions used by every call:
+ *   - Pauli operators are (x, z, e): P = i^e (x)_j sigma(x_j, z_j) with
+ *     sigma(0,0)=I, sigma(1,0)=X, sigma(1,1)=Y, sigma(0,1)=Z (no hidden i in Y),
+ *     bit j of x/z = qubit j; in the paper's masks x = m_X|m_Y, z = m_Z|m_Y
+ *     (Sec. 2.2).  P is Hermitian iff e is even.
+ *   - Qubit j is bit j of an amplitude index; qubit 0 is the least
+ *     significant bit (Sec. 3).
+ *   - State vectors are device memory, 2^n interleaved (re, im) pairs:
+ *     CFH_C128 = two doubles (16 B per amplitude), CFH_C64 = two floats (8 B).
+ *     All amplitude arithmetic is done in double precision in registers;
+ *     CFH_C64 only changes the storage.
+ *   - Rotations are R_P(theta) = exp(-i theta/2 P) (Sec. 3).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Device work is enqueued on it and the call returns without waiting,
+ *     unless the description says it synchronizes.
+ *   - Every call returns a cfh_status; 0 is success.  No C++ exception
+ *     crosses this boundary.  On failure cfh_last_error() returns a
+ *     thread-local message.
+ *   - Host arrays passed in are copied before the call returns; device
+ *     pointers passed in stay owned by the caller, who keeps them alive until
+ *     the enqueued work has finished.  Handles (frames, plans, Hamiltonians,
+ *     batches) are owned by the library and freed by their destroy call.
+ */
+#ifndef CFH_H
+#define CFH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CFH_API_VERSION 1
+
+typedef int32_t cfh_status;
+enum {
+    CFH_OK = 0,
+    CFH_E_INVAL = -1,         /* null pointer, bad gate code, bad qubit, bad size */
+    CFH_E_RANGE = -2,         /* a mask has bits at or above n */
+    CFH_E_NOT_HERMITIAN = -3, /* odd phase exponent where a Hermitian operator is required */
+    CFH_E_NOMEM = -4,         /* host or device allocation failed */
+    CFH_E_HIP = -5,           /* a HIP runtime call failed; message in cfh_last_error() */
+    CFH_E_UNSUPPORTED = -6    /* n or dtype outside what the library supports */
+};
+
+typedef enum { CFH_C64 = 0, CFH_C128 = 1 } cfh_dtype;
+
+/* Clifford gate codes (Sec. 2.1 generators H, S, CNOT, plus their common
+ * products).  CNOT takes q0 = control, q1 = target. */
+typedef enum {
+    CFH_GATE_H = 0, CFH_GATE_S = 1, CFH_GATE_SDG = 2, CFH_GATE_X = 3, CFH_GATE_Y = 4,
+    CFH_GATE_Z = 5, CFH_GATE_CNOT = 6, CFH_GATE_CZ = 7, CFH_GATE_SWAP = 8
+} cfh_gate;
+
+/* P = i^e (x)_j sigma(x_j, z_j).  24 bytes, 8-byte aligned. */
+typedef struct cfh_pauli {
+    uint64_t x;
+    uint64_t z;
+    int32_t e;        /* phase exponent, taken mod 4 */
+    int32_t reserved; /* must be 0 */
+} cfh_pauli;
+
+/* Planner/kernel parameters.  A zero field means "library default". */
+typedef struct cfh_tuning {
+    int32_t tile_bits;     /* b: log2 amplitudes per LDS tile (a coset of a b-dim subspace) */
+    int32_t low_bits;      /* c: low index bits always inside a tile (coalescing) */
+    int32_t max_run;       /* most rotations in one fused pass (<= 32) */
+    int32_t lookahead;     /* rotations scanned for commuting reordering; -1 = in order only */
+    int32_t unfused;       /* 1 = one HBM pass per rotation (no LDS staging) */
+    int32_t block_threads; /* threads per workgroup (256 or 512) */
+    int32_t reserved[2];
+} cfh_tuning;
+
+typedef struct cfh_frame_s *cfh_frame;
+typedef struct cfh_plan_s *cfh_plan;
+typedef struct cfh_ham_s *cfh_ham;
+
+/* ------------------------------------------------------------------ misc */
+
+/* Library ABI version (CFH_API_VERSION). */
+int cfh_version(void);
+
+/* Thread-local message of the last failed call on this thread ("" if none).
+ * The pointer stays valid until the next failing call on the same thread. */
+const char *cfh_last_error(void);
+
+/* Number of HIP devices visible (0 when none); never fails. */
+int cfh_device_count(void);
+
+/* ------------------------------------------------ a1: encode Pauli strings */
+
+/* Letter strings -> (x, z, e) (Sec. 2.2 Pauli masks; Sec. 3 action on basis
+ * states).  `letters` is m rows of n bytes, row-major, column j = qubit j,
+ * codes 0=I 1=X 2=Y 3=Z.  out[i] gets e = 0 (so Y = sigma(1,1) exactly).
+ * Errors: CFH_E_INVAL (null, n outside 1..63, letter > 3). */
+cfh_status cfh_pauli_encode(const uint8_t *letters, int n, size_t m, cfh_pauli *out);
+
+/* ------------------------------------------------- a2: Pauli frame tracker */
+
+/* New frame F_origin on n qubits (effZ_q = Z_q, effX_q = X_q; Sec. 2.3,
+ * Eq. framemat).  1 <= n <= 63.  *out is owned by the caller until
+ * cfh_frame_destroy. */
+cfh_status cfh_frame_create(int n, cfh_frame *out);
+cfh_status cfh_frame_destroy(cfh_frame f);
+
+/* U <- G U for one Clifford gate G, updating the rows in the backward
+ * interpretation (Sec. 4.1): each gate rewrites O(1) rows, each new row a
+ * product of at most two old rows, bit-exact in x, z and the sign e.
+ * q1 must be -1 for one-qubit gates and a distinct qubit for CNOT/CZ/SWAP.
+ * Errors: CFH_E_INVAL (null frame, bad gate code or qubit). */
+cfh_status cfh_frame_apply_clifford(cfh_frame f, int gate, int q0, int q1);
+
+/* Same for m gates given as rows (code, q0, q1) of int32, first row first. */
+cfh_status cfh_frame_apply_gates(cfh_frame f, const int32_t *gates, size_t m);
+
+/* Copy row q: effZ_q = U^dag Z_q U and effX_q = U^dag X_q U. */
+cfh_status cfh_frame_row(cfh_frame f, int q, cfh_pauli *effZ, cfh_pauli *effX);
+
+/* ----------------------------------------------- a3: frame conjugation */
+
+/* out = F(P) = U^dag P U (Eq. Fmap, with the phase of each Y letter taken
+ * from effY_j = -i effZ_j effX_j of Eq. framemat), bit-exact.  Any e is
+ * accepted and its parity is preserved.  Errors: CFH_E_RANGE (bits >= n). */
+cfh_status cfh_frame_conjugate(cfh_frame f, const cfh_pauli *p, cfh_pauli *out);
+
+/* Host loop over m strings; in and out may alias. */
+cfh_status cfh_frame_conjugate_many(cfh_frame f, const cfh_pauli *in, cfh_pauli *out, size_t m);
+
+/* Device version (one thread per string, frame rows staged in LDS): in_dev
+ * and out_dev are device arrays of m cfh_pauli.  Asynchronous on `stream`.
+ * The frame is copied to the device at the call, so later frame updates do
+ * not affect already enqueued work. */
+cfh_status cfh_frame_conjugate_device(cfh_frame f, const cfh_pauli *in_dev, cfh_pauli *out_dev,
+                                      size_t m, void *stream);
+
+/* ------------------------------------------------------ state helpers */
+
+/* psi <- |index> (all zeros except amplitude `index` = 1). */
+cfh_status cfh_state_set_basis(void *psi, int n, int dtype, uint64_t index, void *stream);
+
+/* --------------------------------------- a5/a6: one Pauli rotation, one pass */
+
+/* psi <- exp(-i theta/2 P) psi with P = (x, z, e), e in {0, 2} (e = 2 is -P,
+ * the sign a frame conjugation can produce).  Amplitude pairs (y, y^x) are
+ * updated together (Sec. 3; App. B pair rule):
+ *   psi'[y] = cos(theta/2) psi[y] - i sin(theta/2) i^(e - |x&z|) (-1)^|y&z| psi[y^x];
+ * x = 0 is the diagonal case (App. B).  One read and one write of the state.
+ * Errors: CFH_E_RANGE, CFH_E_NOT_HERMITIAN, CFH_E_UNSUPPORTED (n outside
+ * 1..34), CFH_E_INVAL (null psi). */
+cfh_status cfh_apply_pauli_rotation(void *psi, int n, int dtype, uint64_t x, uint64_t z, int e,
+                                    double theta, void *stream);
+
+/* -------------------------------------------- a4/a7: planned rotation runs */
+
+/* Plan the in-order sequence of m rotations rot[0..m-1] (already conjugated
+ * through the frame) on an n-qubit state of the given dtype.  The planner
+ * splits the sequence into passes; a pass is a run of rotations whose x
+ * masks lie in the span of a b-dimensional subspace V (tile_bits), so that
+ * every coset y + V is closed under all of them and is updated in LDS with
+ * one HBM read and one write.  Rotations may move earlier only past
+ * rotations they commute with (Sec. 2.1, anticommutation flag), which leaves
+ * the product unchanged.  `tuning` may be NULL.  Allocates device memory for
+ * the plan (not the state).  Errors: CFH_E_RANGE, CFH_E_NOT_HERMITIAN,
+ * CFH_E_UNSUPPORTED, CFH_E_NOMEM, CFH_E_HIP. */
+cfh_status cfh_plan_create(int n, int dtype, const cfh_pauli *rot, size_t m,
+                           const cfh_tuning *tuning, cfh_plan *out);
+cfh_status cfh_plan_destroy(cfh_plan p);
+
+/* Host-only planning (no device memory, usable without a GPU): the pass
+ * schedule cfh_plan_create would build.  pass_start needs room for m+1
+ * entries and order for m; *n_passes receives the pass count P and
+ * pass_start[0..P] the prefix offsets into order.  For tools that compare
+ * tunings (the autotuner's cost model) and for tests of the planner. */
+cfh_status cfh_plan_dry_run(int n, int dtype, const cfh_pauli *rot, size_t m, const cfh_tuning *tuning,
+                            int64_t *n_passes, int64_t *pass_start, int64_t *order);
+
+/* Plan summary: passes, rotations, tile bits actually used and the number
+ * of HBM bytes one application moves (2 * 2^n * bytes per amplitude per
+ * pass).  Any pointer may be NULL. */
+cfh_status cfh_plan_info(cfh_plan p, int64_t *n_passes, int64_t *n_rot, int32_t *tile_bits,
+                         double *hbm_bytes);
+
+/* Pass boundaries and order: pass_start has n_passes+1 entries (prefix
+ * offsets into order), order has m rotation indices in application order. */
+cfh_status cfh_plan_schedule(cfh_plan p, int64_t *pass_start, int64_t *order);
+
+/* psi <- R_{m-1} ... R_0 psi with R_k = exp(-i theta_dev[k]/2 rot[k])
+ * (inverse = 0), or the inverse product R_0^dag ... R_{m-1}^dag psi
+ * (inverse = 1).  theta_dev: device array of m doubles.  Allocates nothing
+ * and never synchronizes; uses plan-owned scratch, so calls on one plan must
+ * not overlap in time. */
+cfh_status cfh_apply_plan(cfh_plan p, void *psi, const double *theta_dev, int inverse,
+                          void *stream);
+
+/* ----------------------------------------- a8: Hamiltonian expectation value */
+
+/* Prepare H = sum_j coeff[j] terms[j] (terms already conjugated through the
+ * frame, e even) for expectation values and H*psi on n-qubit states.  Terms
+ * are grouped by x mask and groups are packed into read-only LDS tile
+ * passes.  Allocates device memory.  Errors as cfh_plan_create. */
+cfh_status cfh_ham_create(int n, int dtype, const cfh_pauli *terms, const double *coeff, size_t m,
+                          const cfh_tuning *tuning, cfh_ham *out);
+cfh_status cfh_ham_destroy(cfh_ham h);
+cfh_status cfh_ham_info(cfh_ham h, int64_t *n_passes, int64_t *n_groups, double *hbm_bytes);
+
+/* out_dev[0] + i out_dev[1] = sum_j coeff_j <psi|P_j|psi> (Eq. chfsexp);
+ * the imaginary part is 0 up to rounding for Hermitian terms.  out_dev is
+ * device memory for 2 doubles.  Deterministic: fixed-order two-stage
+ * reduction.  Asynchronous; allocates nothing. */
+cfh_status cfh_expval_async(cfh_ham h, const void *psi, double *out_dev, void *stream);
+
+/* Convenience: builds a temporary Hamiltonian, runs cfh_expval_async and
+ * synchronizes `stream`; out_host gets 2 doubles (re, im). */
+cfh_status cfh_expval(const void *psi, int n, int dtype, const cfh_pauli *terms,
+                      const double *coeff, size_t m, double *out_host, void *stream);
+
+/* out <- H psi (out-of-place; out must not alias psi). */
+cfh_status cfh_ham_apply(cfh_ham h, const void *psi, void *out, void *stream);
+
+/* ------------------------------------------------- a9: adjoint gradient */
+
+/* Adjoint differentiation of E(theta) = <psi|H|psi>, psi = R_{m-1}..R_0 psi_0
+ * (the rotations of plan p with angles theta_dev).  On entry psi holds the
+ * final state psi_{m} = apply_plan(psi_0); lam is scratch for one state.
+ * Computes lam = H psi, then walks the passes backwards: for each rotation k
+ * (last first) grad_dev[k] = Im <lam_k| P_k |psi_k> and both vectors are
+ * rewound by R_k^dag, in the same LDS pass.  On return psi holds psi_0 again
+ * (up to rounding) and grad_dev (device, m doubles) holds dE/dtheta_k.
+ * Requires p and h on the same n and dtype.  Asynchronous; allocates
+ * nothing. */
+cfh_status cfh_adjoint_grad(cfh_plan p, cfh_ham h, void *psi, void *lam, const double *theta_dev,
+                            double *grad_dev, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CFH_H */

@@ -378,6 +378,26 @@ double orc_energy(const cplx *psi, int n, const uint8_t *letters, const int32_t 
     return e;
 }
 
+/* out = sum_j coeff_j i^phase_j P_j psi, each P_j applied letter by letter. */
+int orc_apply_pauli_sum(const cplx *psi, int n, const uint8_t *letters, const int32_t *phases,
+                        const double *coeff, int64_t m, cplx *out)
+{
+    const int64_t N = (int64_t)1 << n;
+    memset(out, 0, (size_t)N * sizeof(cplx));
+    for (int64_t j = 0; j < m; ++j) {
+        const uint8_t *P = letters + j * n;
+        cplx f = coeff[j] * ipow(phases ? phases[j] : 0);
+        /* out[t] += f * (P psi)[t]; P maps basis y to t = P(y) bijectively */
+#pragma omp parallel for schedule(static) if (n >= PAR_MIN_QUBITS)
+        for (int64_t y = 0; y < N; ++y) {
+            cplx a = psi[y];
+            uint64_t t = pauli_on_basis(P, n, (uint64_t)y, &a);
+            out[t] += f * a;
+        }
+    }
+    return 0;
+}
+
 /* ------------------------------------------------ sparse definition path */
 /* Open-addressing hash map uint64 index -> complex amplitude. */
 

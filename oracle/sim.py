@@ -42,6 +42,7 @@ def lib():
                                  C.POINTER(C.c_double)]
         L.orc_energy.argtypes = [_c128p, C.c_int, _u8p, C.c_void_p, _f64p, C.c_int64]
         L.orc_energy.restype = C.c_double
+        L.orc_apply_pauli_sum.argtypes = [_c128p, C.c_int, _u8p, C.c_void_p, _f64p, C.c_int64, _c128p]
         L.orc_sparse_rotations.argtypes = [C.c_int, _u64p, _c128p, C.c_int64, _u8p, C.c_void_p,
                                            _f64p, C.c_int64, _u64p, _c128p, C.c_int64]
         L.orc_sparse_rotations.restype = C.c_int64
@@ -142,6 +143,20 @@ def energy(psi: np.ndarray, n: int, ham: np.ndarray, coeff: np.ndarray,
         p = np.ascontiguousarray(phases, dtype=np.int32)
         pp = p.ctypes.data
     return float(lib().orc_energy(psi, n, h, pp, c, h.shape[0]))
+
+
+def apply_pauli_sum(psi: np.ndarray, n: int, ham: np.ndarray, coeff: np.ndarray,
+                    phases: Optional[np.ndarray] = None) -> np.ndarray:
+    """H psi with H = sum_j coeff_j i^phase_j P_j, letter by letter."""
+    h = np.ascontiguousarray(ham, dtype=np.uint8).reshape(-1, n)
+    c = np.ascontiguousarray(coeff, dtype=np.float64)
+    pp = None
+    if phases is not None:
+        p = np.ascontiguousarray(phases, dtype=np.int32)
+        pp = p.ctypes.data
+    out = np.empty_like(psi)
+    _check(lib().orc_apply_pauli_sum(psi, n, h, pp, c, h.shape[0], out), "apply_pauli_sum")
+    return out
 
 
 def simulate(w, n_rot: Optional[int] = None, theta: Optional[np.ndarray] = None):

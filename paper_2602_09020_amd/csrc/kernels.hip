@@ -1,0 +1,1162 @@
+// gfx950 kernels of libcfh and the C-ABI entry points that launch them.
+//
+// The hot loop is the multi-qubit Pauli rotation of Sec. 3 applied to Phi
+// (Sec. 4.2): amplitudes pair as (y, y ^ x) and each member of a pair gets the
+// sign (-1)^{|y & z|}; App. B gives the 2x2 pair rule.  All kernels stream
+// the state through HBM with 16-byte (c128) or 8-byte (c64) accesses;
+// arithmetic is double precision in registers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <vector>
+
+#include "cfh_internal.hpp"
+
+using namespace cfh;
+
+namespace {
+
+// ------------------------------------------------------------ storage
+__device__ __forceinline__ double2 ld(const double2 &p) { return p; }
+__device__ __forceinline__ double2 ld(const float2 &p) { return make_double2(p.x, p.y); }
+__device__ __forceinline__ void st(double2 &p, double2 v) { p = v; }
+__device__ __forceinline__ void st(float2 &p, double2 v) { p = make_float2((float)v.x, (float)v.y); }
+
+__device__ __forceinline__ int par32(uint32_t v) { return __builtin_popcount(v) & 1; }
+__device__ __forceinline__ int par64(uint64_t v) { return __builtin_popcountll(v) & 1; }
+
+// Spread the low bits of v over the set bits of mask (software pdep).
+__device__ __forceinline__ uint64_t deposit(uint64_t v, uint64_t mask)
+{
+    uint64_t r = 0;
+    for (uint64_t m = mask; m && v; m &= m - 1, v >>= 1)
+        if (v & 1) r |= m & (~m + 1);
+    return r;
+}
+
+// One pair update.  With beta = sr * (imag ? i : 1) the rotation is
+//   u' = c u + s0 beta v,  v' = c v + s1 beta u,  s0, s1 = +-1 folded into sr.
+__device__ __forceinline__ void rot_pair(double2 &u, double2 &v, double c, double s0, double s1, bool imag)
+{
+    double2 nu, nv;
+    if (imag) {
+        nu.x = c * u.x - s0 * v.y;
+        nu.y = c * u.y + s0 * v.x;
+        nv.x = c * v.x - s1 * u.y;
+        nv.y = c * v.y + s1 * u.x;
+    } else {
+        nu.x = c * u.x + s0 * v.x;
+        nu.y = c * u.y + s0 * v.y;
+        nv.x = c * v.x + s1 * u.x;
+        nv.y = c * v.y + s1 * u.y;
+    }
+    u = nu;
+    v = nv;
+}
+
+// Diagonal member update: u' = (c + s beta) u.
+__device__ __forceinline__ double2 rot_diag(double2 u, double c, double s, bool imag)
+{
+    if (imag) return make_double2(c * u.x - s * u.y, c * u.y + s * u.x);
+    return make_double2((c + s) * u.x, (c + s) * u.y);
+}
+
+constexpr int threads_for(int B) { return B - 1 >= 8 ? 256 : (1 << (B - 1)); }
+constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v >> 1); }
+
+// ------------------------------------------------------------ small kernels
+
+__global__ void k_coef(const double *__restrict__ theta, double2 *__restrict__ coef, int64_t m)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < m) {
+        double s, c;
+        sincos(0.5 * theta[k], &s, &c);
+        coef[k] = make_double2(c, s);
+    }
+}
+
+template <typename Amp>
+__global__ void k_set_basis(Amp *__restrict__ psi, uint64_t N, uint64_t index)
+{
+    for (uint64_t y = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; y < N;
+         y += (uint64_t)gridDim.x * blockDim.x)
+        st(psi[y], make_double2(y == index ? 1.0 : 0.0, 0.0));
+}
+
+__global__ void k_zero_d(double *__restrict__ p, int64_t cnt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) p[i] = 0.0;
+}
+
+// ---------------------------------------------- unfused rotation (one pass)
+// Pair q -> y0 = q with a zero inserted at bit hb (the top bit of x), y1 = y0 ^ x.
+// Consecutive lanes take consecutive q, so both members stream contiguously.
+constexpr int kR1Threads = 256;
+constexpr int kR1Pairs = 4;
+
+template <typename Amp>
+__global__ void __launch_bounds__(kR1Threads)
+k_rot_pairs(Amp *__restrict__ psi, uint64_t x, uint64_t z, int hb, int w, int dsign, double c_in,
+            double s_in, const double2 *__restrict__ coef, int k, double ssign, uint64_t npairs)
+{
+    double c = c_in, s = s_in;
+    if (coef) {
+        const double2 cs = coef[k];
+        c = cs.x;
+        s = cs.y * ssign;
+    }
+    const double sr = (w & 2) ? -s : s;
+    const bool imag = w & 1;
+    const uint64_t lowm = (1ull << hb) - 1;
+    const uint64_t q0 = (uint64_t)blockIdx.x * (kR1Threads * kR1Pairs) + threadIdx.x;
+    double2 u[kR1Pairs], v[kR1Pairs];
+    uint64_t ya[kR1Pairs];
+#pragma unroll
+    for (int j = 0; j < kR1Pairs; ++j) {
+        const uint64_t q = q0 + (uint64_t)j * kR1Threads;
+        ya[j] = ((q & ~lowm) << 1) | (q & lowm);
+        if (q < npairs) {
+            u[j] = ld(psi[ya[j]]);
+            v[j] = ld(psi[ya[j] ^ x]);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kR1Pairs; ++j) {
+        const uint64_t q = q0 + (uint64_t)j * kR1Threads;
+        if (q < npairs) {
+            const int sg0 = par64(ya[j] & z);
+            const double s0 = sg0 ? -sr : sr;
+            const double s1 = (sg0 ^ dsign) ? -sr : sr;
+            rot_pair(u[j], v[j], c, s0, s1, imag);
+            st(psi[ya[j]], u[j]);
+            st(psi[ya[j] ^ x], v[j]);
+        }
+    }
+}
+
+template <typename Amp>
+__global__ void __launch_bounds__(kR1Threads)
+k_rot_diag(Amp *__restrict__ psi, uint64_t z, int w, double c_in, double s_in,
+           const double2 *__restrict__ coef, int k, double ssign, uint64_t N)
+{
+    double c = c_in, s = s_in;
+    if (coef) {
+        const double2 cs = coef[k];
+        c = cs.x;
+        s = cs.y * ssign;
+    }
+    const double sr = (w & 2) ? -s : s;
+    const bool imag = w & 1;
+    const uint64_t y0 = (uint64_t)blockIdx.x * (kR1Threads * kR1Pairs) + threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < kR1Pairs; ++j) {
+        const uint64_t y = y0 + (uint64_t)j * kR1Threads;
+        if (y < N) {
+            const double sj = par64(y & z) ? -sr : sr;
+            st(psi[y], rot_diag(ld(psi[y]), c, sj, imag));
+        }
+    }
+}
+
+// -------------------------------------------------- fused LDS tile pass
+// One workgroup per coset base + V (see PassArgs).  Load the 2^B amplitudes of
+// the coset (coalesced: the low local bits are unit vectors of the low index
+// bits), apply the run of rotations in LDS, store once.
+template <typename Amp, int B>
+__global__ void __launch_bounds__(threads_for(B))
+k_pass(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs args)
+{
+    constexpr int T = threads_for(B);
+    constexpr int LT = ilog2c(T);
+    constexpr int N = 1 << B;
+    constexpr int E = N / T;
+    constexpr int NP = N / 2 / T;
+    __shared__ Amp tile[N];
+    const int t = threadIdx.x;
+    const uint64_t base = deposit((uint64_t)blockIdx.x + (uint64_t)args.tile_base, args.outer_mask);
+    uint64_t Lt = 0;
+#pragma unroll
+    for (int i = 0; i < LT; ++i)
+        if ((t >> i) & 1) Lt ^= args.v[i];
+    const uint64_t yb = base ^ Lt;
+    Amp r[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        uint64_t Lk = 0;
+#pragma unroll
+        for (int i = 0; i < B - LT; ++i)
+            if ((k >> i) & 1) Lk ^= args.v[LT + i];
+        r[k] = psi[yb ^ Lk];
+    }
+#pragma unroll
+    for (int k = 0; k < E; ++k) tile[t + k * T] = r[k];
+    __syncthreads();
+
+    for (int ri = 0; ri < args.nrot; ++ri) {
+        const RotDesc &d = args.rot[args.inverse ? args.nrot - 1 - ri : ri];
+        const double2 cs = coef[d.k];
+        const double c = cs.x;
+        double sr = args.inverse ? -cs.y : cs.y;
+        if (d.w & 2) sr = -sr;
+        const bool imag = d.w & 1;
+        const int so = par64(base & d.z);
+        if (d.xl == 0) {
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                const int a = t + k * T;
+                const double sj = (par32(a & d.zl) ^ so) ? -sr : sr;
+                st(tile[a], rot_diag(ld(tile[a]), c, sj, imag));
+            }
+        } else {
+            const uint32_t lowm = (1u << d.hb) - 1;
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                const uint32_t q = t + k * T;
+                const uint32_t a0 = ((q & ~lowm) << 1) | (q & lowm);
+                const uint32_t a1 = a0 ^ d.xl;
+                const int sg0 = par32(a0 & d.zl) ^ so;
+                const double s0 = sg0 ? -sr : sr;
+                const double s1 = (sg0 ^ d.dsign) ? -sr : sr;
+                double2 u = ld(tile[a0]), v = ld(tile[a1]);
+                rot_pair(u, v, c, s0, s1, imag);
+                st(tile[a0], u);
+                st(tile[a1], v);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < E; ++k) r[k] = tile[t + k * T];
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        uint64_t Lk = 0;
+#pragma unroll
+        for (int i = 0; i < B - LT; ++i)
+            if ((k >> i) & 1) Lk ^= args.v[LT + i];
+        psi[yb ^ Lk] = r[k];
+    }
+}
+
+// ------------------------------------------------ wave/block reductions
+// Sum over the first WIDTH lanes of a wave (WIDTH = min(block size, 64)).
+template <int WIDTH>
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = WIDTH / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, WIDTH);
+    return v;
+}
+
+// ------------------------------------------------ Hamiltonian passes
+// Read-only pass over cosets of a unit-vector subspace T (the qubits of the
+// pass).  For each x-group with x inside T and each of its terms j:
+//   sum_a conj(Phi[a]) * w_j * (-1)^{|y_a & z_j|} * Phi[a ^ xl],
+// w_j = coeff_j * i^{(e_j - |x&z_j|) mod 4}  (Eq. chfsexp with the pair rule).
+template <typename Amp, int B>
+__global__ void __launch_bounds__(threads_for(B))
+k_ham_expval(const Amp *__restrict__ psi, const HamPassArgs args, const HamGroupDev *__restrict__ groups,
+             const HamTermDev *__restrict__ terms, double2 *__restrict__ partial, uint64_t ntiles)
+{
+    constexpr int T = threads_for(B);
+    constexpr int LT = ilog2c(T);
+    constexpr int N = 1 << B;
+    constexpr int E = N / T;
+    constexpr int W = (T + 63) / 64;
+    __shared__ Amp tile[N];
+    __shared__ double red[2][W];
+    const int t = threadIdx.x;
+    uint64_t Lt = 0;
+#pragma unroll
+    for (int i = 0; i < LT; ++i)
+        if ((t >> i) & 1) Lt ^= args.v[i];
+    double accr = 0.0, acci = 0.0;
+    for (uint64_t tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+        const uint64_t base = deposit(tl, args.outer_mask);
+        const uint64_t yb = base ^ Lt;
+        Amp r[E];
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            uint64_t Lk = 0;
+#pragma unroll
+            for (int i = 0; i < B - LT; ++i)
+                if ((k >> i) & 1) Lk ^= args.v[LT + i];
+            r[k] = psi[yb ^ Lk];
+        }
+#pragma unroll
+        for (int k = 0; k < E; ++k) tile[t + k * T] = r[k];
+        __syncthreads();
+        for (int g = args.group_begin; g < args.group_begin + args.group_count; ++g) {
+            const HamGroupDev G = groups[g];
+            double pr[E], pi[E];
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                const int a = t + k * T;
+                const double2 u = ld(r[k]), v = ld(tile[a ^ G.xl]);
+                pr[k] = u.x * v.x + u.y * v.y;   // conj(u) * v
+                pi[k] = u.x * v.y - u.y * v.x;
+            }
+            for (int j = G.term_begin; j < G.term_begin + G.term_count; ++j) {
+                const HamTermDev tm = terms[j];
+                const int so = par64(base & tm.z);
+#pragma unroll
+                for (int k = 0; k < E; ++k) {
+                    const int a = t + k * T;
+                    const double sg = (par32(a & tm.zl) ^ so) ? -1.0 : 1.0;
+                    accr += sg * (tm.wre * pr[k] - tm.wim * pi[k]);
+                    acci += sg * (tm.wre * pi[k] + tm.wim * pr[k]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    accr = wave_sum<(T < 64 ? T : 64)>(accr);
+    acci = wave_sum<(T < 64 ? T : 64)>(acci);
+    if ((t & 63) == 0) {
+        red[0][t >> 6] = accr;
+        red[1][t >> 6] = acci;
+    }
+    __syncthreads();
+    if (t == 0) {
+        double sr = 0, si = 0;
+        for (int i = 0; i < W; ++i) {
+            sr += red[0][i];
+            si += red[1][i];
+        }
+        partial[blockIdx.x].x += sr;   // same block index -> same tiles in every pass
+        partial[blockIdx.x].y += si;
+    }
+}
+
+// out[y] (+)= sum_groups sum_terms w_j (-1)^{|y & z_j|} psi[y ^ x]  (H psi).
+template <typename Amp, int B>
+__global__ void __launch_bounds__(threads_for(B))
+k_ham_apply(const Amp *__restrict__ psi, Amp *__restrict__ out, const HamPassArgs args,
+            const HamGroupDev *__restrict__ groups, const HamTermDev *__restrict__ terms, int accumulate)
+{
+    constexpr int T = threads_for(B);
+    constexpr int LT = ilog2c(T);
+    constexpr int N = 1 << B;
+    constexpr int E = N / T;
+    __shared__ Amp tile[N];
+    const int t = threadIdx.x;
+    const uint64_t base = deposit((uint64_t)blockIdx.x, args.outer_mask);
+    uint64_t Lt = 0;
+#pragma unroll
+    for (int i = 0; i < LT; ++i)
+        if ((t >> i) & 1) Lt ^= args.v[i];
+    const uint64_t yb = base ^ Lt;
+    uint64_t yk[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        uint64_t Lk = 0;
+#pragma unroll
+        for (int i = 0; i < B - LT; ++i)
+            if ((k >> i) & 1) Lk ^= args.v[LT + i];
+        yk[k] = yb ^ Lk;
+        tile[t + k * T] = psi[yk[k]];
+    }
+    __syncthreads();
+    double ar[E], ai[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) ar[k] = ai[k] = 0.0;
+    for (int g = args.group_begin; g < args.group_begin + args.group_count; ++g) {
+        const HamGroupDev G = groups[g];
+        double vr[E], vi[E];
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            const double2 v = ld(tile[(t + k * T) ^ G.xl]);
+            vr[k] = v.x;
+            vi[k] = v.y;
+        }
+        for (int j = G.term_begin; j < G.term_begin + G.term_count; ++j) {
+            const HamTermDev tm = terms[j];
+            const int so = par64(base & tm.z);
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                const int a = t + k * T;
+                const double sg = (par32(a & tm.zl) ^ so) ? -1.0 : 1.0;
+                ar[k] += sg * (tm.wre * vr[k] - tm.wim * vi[k]);
+                ai[k] += sg * (tm.wre * vi[k] + tm.wim * vr[k]);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        double2 o = make_double2(ar[k], ai[k]);
+        if (accumulate) {
+            const double2 p = ld(out[yk[k]]);
+            o.x += p.x;
+            o.y += p.y;
+        }
+        st(out[yk[k]], o);
+    }
+}
+
+__global__ void k_reduce_partial(const double2 *__restrict__ partial, int cnt, double *__restrict__ out)
+{
+    __shared__ double sr[256], si[256];
+    const int t = threadIdx.x;
+    double a = 0, b = 0;
+    for (int i = t; i < cnt; i += 256) {
+        a += partial[i].x;
+        b += partial[i].y;
+    }
+    sr[t] = a;
+    si[t] = b;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) {
+            sr[t] += sr[t + s];
+            si[t] += si[t + s];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        out[0] = sr[0];
+        out[1] = si[0];
+    }
+}
+
+// ------------------------------------------------------ adjoint pass
+// Tiles of psi and lam share LDS.  Walking the run backwards, rotation k
+// contributes g_k = Im <lam| P_k |psi> on the coset and then both tiles are
+// rewound by R_k^dag.  Per-wave partial sums live in LDS and are combined in
+// a fixed order, so the result is bitwise reproducible.
+template <typename Amp, int B>
+__global__ void __launch_bounds__(threads_for(B))
+k_adjoint_pass(Amp *__restrict__ psi, Amp *__restrict__ lam, const double2 *__restrict__ coef,
+               const PassArgs args, double *__restrict__ partial, uint64_t ntiles)
+{
+    constexpr int T = threads_for(B);
+    constexpr int LT = ilog2c(T);
+    constexpr int N = 1 << B;
+    constexpr int E = N / T;
+    constexpr int NP = N / 2 / T;
+    constexpr int W = (T + 63) / 64;
+    __shared__ Amp tp[N];
+    __shared__ Amp tl[N];
+    __shared__ double wacc[kMaxRun][W];
+    const int t = threadIdx.x;
+    for (int i = t; i < kMaxRun * W; i += T) (&wacc[0][0])[i] = 0.0;
+    uint64_t Lt = 0;
+#pragma unroll
+    for (int i = 0; i < LT; ++i)
+        if ((t >> i) & 1) Lt ^= args.v[i];
+    __syncthreads();
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint64_t base = deposit(tile, args.outer_mask);
+        const uint64_t yb = base ^ Lt;
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            uint64_t Lk = 0;
+#pragma unroll
+            for (int i = 0; i < B - LT; ++i)
+                if ((k >> i) & 1) Lk ^= args.v[LT + i];
+            tp[t + k * T] = psi[yb ^ Lk];
+            tl[t + k * T] = lam[yb ^ Lk];
+        }
+        __syncthreads();
+        for (int ri = args.nrot - 1; ri >= 0; --ri) {
+            const RotDesc &d = args.rot[ri];
+            const double2 cs = coef[d.k];
+            const double c = cs.x;
+            double sr = -cs.y;             // R^dag: negated angle
+            if (d.w & 2) sr = -sr;
+            const bool imag = d.w & 1;
+            const int wp = (d.w + 1) & 3;  // P psi carries i^{(e - |x&z|)}
+            const int so = par64(base & d.z);
+            double g = 0.0;
+            if (d.xl == 0) {
+#pragma unroll
+                for (int k = 0; k < E; ++k) {
+                    const int a = t + k * T;
+                    const int sg = par32(a & d.zl) ^ so;
+                    const double2 u = ld(tp[a]), l = ld(tl[a]);
+                    const double zr = l.x * u.x + l.y * u.y, zi = l.x * u.y - l.y * u.x;
+                    const double im = (wp & 1) ? zr : zi;
+                    g += ((wp & 2) ? -im : im) * (sg ? -1.0 : 1.0);
+                    const double sj = sg ? -sr : sr;
+                    st(tp[a], rot_diag(u, c, sj, imag));
+                    st(tl[a], rot_diag(l, c, sj, imag));
+                }
+            } else {
+                const uint32_t lowm = (1u << d.hb) - 1;
+#pragma unroll
+                for (int k = 0; k < NP; ++k) {
+                    const uint32_t q = t + k * T;
+                    const uint32_t a0 = ((q & ~lowm) << 1) | (q & lowm);
+                    const uint32_t a1 = a0 ^ d.xl;
+                    const int sg0 = par32(a0 & d.zl) ^ so;
+                    const int sg1 = sg0 ^ d.dsign;
+                    double2 u0 = ld(tp[a0]), u1 = ld(tp[a1]);
+                    double2 l0 = ld(tl[a0]), l1 = ld(tl[a1]);
+                    // conj(l0) (P psi)[a0] + conj(l1) (P psi)[a1], (P psi)[a0] ~ psi[a1]
+                    const double z0r = l0.x * u1.x + l0.y * u1.y, z0i = l0.x * u1.y - l0.y * u1.x;
+                    const double z1r = l1.x * u0.x + l1.y * u0.y, z1i = l1.x * u0.y - l1.y * u0.x;
+                    const double zr = (sg0 ? -z0r : z0r) + (sg1 ? -z1r : z1r);
+                    const double zi = (sg0 ? -z0i : z0i) + (sg1 ? -z1i : z1i);
+                    const double im = (wp & 1) ? zr : zi;
+                    g += (wp & 2) ? -im : im;
+                    const double s0 = sg0 ? -sr : sr, s1 = sg1 ? -sr : sr;
+                    rot_pair(u0, u1, c, s0, s1, imag);
+                    rot_pair(l0, l1, c, s0, s1, imag);
+                    st(tp[a0], u0);
+                    st(tp[a1], u1);
+                    st(tl[a0], l0);
+                    st(tl[a1], l1);
+                }
+            }
+            g = wave_sum<(T < 64 ? T : 64)>(g);
+            if ((t & 63) == 0) wacc[ri][t >> 6] += g;
+            __syncthreads();
+        }
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            uint64_t Lk = 0;
+#pragma unroll
+            for (int i = 0; i < B - LT; ++i)
+                if ((k >> i) & 1) Lk ^= args.v[LT + i];
+            psi[yb ^ Lk] = tp[t + k * T];
+            lam[yb ^ Lk] = tl[t + k * T];
+        }
+        __syncthreads();
+    }
+    if (t < args.nrot) {
+        double s = 0.0;
+        for (int i = 0; i < W; ++i) s += wacc[t][i];
+        partial[(uint64_t)blockIdx.x * kMaxRun + t] = s;
+    }
+}
+
+__global__ void k_grad_reduce(const double *__restrict__ partial, int nblocks, const PassArgs args,
+                              double *__restrict__ grad)
+{
+    const int ri = blockIdx.x;
+    __shared__ double s[256];
+    double a = 0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) a += partial[(uint64_t)b * kMaxRun + ri];
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) grad[args.rot[ri].k] = s[0];
+}
+
+// ------------------------------------------------------ device frame map
+// One thread per string; the 2n frame rows are staged in LDS.
+struct FrameRowDev {
+    uint64_t x, z;
+    int32_t e, pad;
+};
+
+__device__ __forceinline__ void dmul(uint64_t &x, uint64_t &z, int &e, uint64_t bx, uint64_t bz, int be)
+{
+    const uint64_t rx = x ^ bx, rz = z ^ bz;
+    e = (e + be + __builtin_popcountll(x & z) + __builtin_popcountll(bx & bz) +
+         2 * __builtin_popcountll(z & bx) - __builtin_popcountll(rx & rz)) & 3;
+    x = rx;
+    z = rz;
+}
+
+__global__ void k_frame_conjugate(const FrameRowDev *__restrict__ rows, int n, const cfh_pauli *__restrict__ in,
+                                  cfh_pauli *__restrict__ out, uint64_t m)
+{
+    __shared__ FrameRowDev s[2 * kMaxFrameQubits];
+    for (int i = threadIdx.x; i < 2 * n; i += blockDim.x) s[i] = rows[i];
+    __syncthreads();
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const cfh_pauli p = in[i];
+    uint64_t x = 0, z = 0;
+    int e = p.e & 3;
+    uint64_t supp = p.x | p.z;
+    while (supp) {
+        const int j = __builtin_ctzll(supp);
+        supp &= supp - 1;
+        const bool xb = (p.x >> j) & 1, zb = (p.z >> j) & 1;
+        const FrameRowDev &Z = s[j], &X = s[n + j];
+        if (xb && zb) {           // i effX_j effZ_j
+            uint64_t yx = X.x, yz = X.z;
+            int ye = X.e;
+            dmul(yx, yz, ye, Z.x, Z.z, Z.e);
+            dmul(x, z, e, yx, yz, (ye + 1) & 3);
+        } else if (xb) {
+            dmul(x, z, e, X.x, X.z, X.e);
+        } else {
+            dmul(x, z, e, Z.x, Z.z, Z.e);
+        }
+    }
+    out[i] = cfh_pauli{x, z, e, 0};
+}
+
+// ------------------------------------------------------ launch helpers
+inline bool hip_ok(hipError_t e, const char *what, cfh_status *st)
+{
+    if (e == hipSuccess) return true;
+    *st = set_error(CFH_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    return false;
+}
+
+cfh_status last_launch(const char *what)
+{
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(CFH_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    return CFH_OK;
+}
+
+size_t amp_bytes(int dtype) { return dtype == CFH_C64 ? 8 : 16; }
+
+template <typename Amp, int B>
+constexpr bool fits_lds(int tiles) { return (size_t)tiles * sizeof(Amp) * ((size_t)1 << B) <= 160 * 1024; }
+
+template <typename Amp>
+cfh_status launch_pass(int b, uint64_t ntiles, hipStream_t s, Amp *psi, const double2 *coef, PassArgs a)
+{
+    // split grids larger than 2^30 blocks (never at supported sizes, kept for safety)
+    constexpr uint64_t kMaxGrid = 1ull << 30;
+    for (uint64_t off = 0; off < ntiles; off += kMaxGrid) {
+        a.tile_base = (int32_t)off;
+        const unsigned g = (unsigned)std::min<uint64_t>(kMaxGrid, ntiles - off);
+        switch (b) {
+#define CFH_PASS_CASE(BB)                                                                        \
+    case BB:                                                                                     \
+        if constexpr (fits_lds<Amp, BB>(1))                                                      \
+            hipLaunchKernelGGL((k_pass<Amp, BB>), dim3(g), dim3(threads_for(BB)), 0, s, psi, coef, a); \
+        else                                                                                     \
+            return set_error(CFH_E_UNSUPPORTED, "tile_bits too large for LDS");                  \
+        break;
+            CFH_PASS_CASE(1) CFH_PASS_CASE(2) CFH_PASS_CASE(3) CFH_PASS_CASE(4) CFH_PASS_CASE(5)
+            CFH_PASS_CASE(6) CFH_PASS_CASE(7) CFH_PASS_CASE(8) CFH_PASS_CASE(9) CFH_PASS_CASE(10)
+            CFH_PASS_CASE(11) CFH_PASS_CASE(12) CFH_PASS_CASE(13) CFH_PASS_CASE(14)
+#undef CFH_PASS_CASE
+        default:
+            return set_error(CFH_E_UNSUPPORTED, "tile_bits outside 1..14");
+        }
+    }
+    return last_launch("k_pass");
+}
+
+template <typename Amp>
+cfh_status launch_ham(int b, uint64_t ntiles, unsigned grid, hipStream_t s, const Amp *psi, Amp *out,
+                      const HamPassArgs &a, const HamGroupDev *gr, const HamTermDev *tm, double2 *partial,
+                      int accumulate)
+{
+    switch (b) {
+#define CFH_HAM_CASE(BB)                                                                                   \
+    case BB:                                                                                               \
+        if constexpr (fits_lds<Amp, BB>(1)) {                                                              \
+            if (out)                                                                                       \
+                hipLaunchKernelGGL((k_ham_apply<Amp, BB>), dim3((unsigned)ntiles), dim3(threads_for(BB)), 0, s, \
+                                   psi, out, a, gr, tm, accumulate);                                       \
+            else                                                                                           \
+                hipLaunchKernelGGL((k_ham_expval<Amp, BB>), dim3(grid), dim3(threads_for(BB)), 0, s, psi, a, \
+                                   gr, tm, partial, ntiles);                                               \
+        } else                                                                                             \
+            return set_error(CFH_E_UNSUPPORTED, "tile_bits too large for LDS");                            \
+        break;
+        CFH_HAM_CASE(1) CFH_HAM_CASE(2) CFH_HAM_CASE(3) CFH_HAM_CASE(4) CFH_HAM_CASE(5)
+        CFH_HAM_CASE(6) CFH_HAM_CASE(7) CFH_HAM_CASE(8) CFH_HAM_CASE(9) CFH_HAM_CASE(10)
+        CFH_HAM_CASE(11) CFH_HAM_CASE(12) CFH_HAM_CASE(13) CFH_HAM_CASE(14)
+#undef CFH_HAM_CASE
+    default:
+        return set_error(CFH_E_UNSUPPORTED, "tile_bits outside 1..14");
+    }
+    return last_launch("k_ham");
+}
+
+template <typename Amp>
+cfh_status launch_adjoint(int b, uint64_t ntiles, unsigned grid, hipStream_t s, Amp *psi, Amp *lam,
+                          const double2 *coef, const PassArgs &a, double *partial)
+{
+    switch (b) {
+#define CFH_ADJ_CASE(BB)                                                                          \
+    case BB:                                                                                      \
+        if constexpr (fits_lds<Amp, BB>(2))                                                       \
+            hipLaunchKernelGGL((k_adjoint_pass<Amp, BB>), dim3(grid), dim3(threads_for(BB)), 0, s, psi, lam, \
+                               coef, a, partial, ntiles);                                         \
+        else                                                                                      \
+            return set_error(CFH_E_UNSUPPORTED, "tile_bits too large for the adjoint's two LDS tiles"); \
+        break;
+        CFH_ADJ_CASE(1) CFH_ADJ_CASE(2) CFH_ADJ_CASE(3) CFH_ADJ_CASE(4) CFH_ADJ_CASE(5)
+        CFH_ADJ_CASE(6) CFH_ADJ_CASE(7) CFH_ADJ_CASE(8) CFH_ADJ_CASE(9) CFH_ADJ_CASE(10)
+        CFH_ADJ_CASE(11) CFH_ADJ_CASE(12) CFH_ADJ_CASE(13)
+#undef CFH_ADJ_CASE
+    default:
+        return set_error(CFH_E_UNSUPPORTED, "tile_bits outside 1..13 for the adjoint");
+    }
+    return last_launch("k_adjoint_pass");
+}
+
+cfh_status check_state_args(const void *psi, int n, int dtype, const char *what)
+{
+    if (!psi) return set_error(CFH_E_INVAL, std::string(what) + ": null state pointer");
+    if (n < 1 || n > kMaxStateQubits)
+        return set_error(CFH_E_UNSUPPORTED, std::string(what) + ": n must be in 1..34");
+    if (dtype != CFH_C64 && dtype != CFH_C128)
+        return set_error(CFH_E_UNSUPPORTED, std::string(what) + ": unknown dtype");
+    return CFH_OK;
+}
+
+template <typename Amp>
+cfh_status rot_one(Amp *psi, int n, uint64_t x, uint64_t z, int e, double c, double s,
+                   const double2 *coef, int k, double ssign, hipStream_t st)
+{
+    const int w = (e - popc(x & z) + 3) & 3;
+    const uint64_t per = (uint64_t)kR1Threads * kR1Pairs;
+    if (x == 0) {
+        const uint64_t N = 1ull << n;
+        hipLaunchKernelGGL((k_rot_diag<Amp>), dim3((unsigned)((N + per - 1) / per)), dim3(kR1Threads), 0, st,
+                           psi, z, w, c, s, coef, k, ssign, N);
+        return last_launch("k_rot_diag");
+    }
+    const int hb = 63 - __builtin_clzll(x);
+    const uint64_t np = 1ull << (n - 1);
+    hipLaunchKernelGGL((k_rot_pairs<Amp>), dim3((unsigned)((np + per - 1) / per)), dim3(kR1Threads), 0, st,
+                       psi, x, z, hb, w, popc(x & z) & 1, c, s, coef, k, ssign, np);
+    return last_launch("k_rot_pairs");
+}
+
+} // namespace
+
+// ============================================================ plan object
+struct cfh_plan_s {
+    int n = 0, dtype = 0;
+    TuningResolved tu{};
+    std::vector<Pauli> rot;
+    std::vector<PassPlan> passes;
+    std::vector<PassArgs> args;
+    double2 *coef = nullptr;     // device, m entries
+    double *gpart = nullptr;     // device, adj_grid * kMaxRun
+    unsigned adj_grid = 0;
+    ~cfh_plan_s()
+    {
+        if (coef) (void)hipFree(coef);
+        if (gpart) (void)hipFree(gpart);
+    }
+};
+
+struct cfh_ham_s {
+    int n = 0, dtype = 0;
+    TuningResolved tu{};
+    std::vector<HamPass> passes;
+    std::vector<HamPassArgs> args;
+    HamGroupDev *groups = nullptr;
+    HamTermDev *terms = nullptr;
+    double2 *partial = nullptr;  // grid entries
+    unsigned grid = 0;
+    int64_t n_groups = 0;
+    ~cfh_ham_s()
+    {
+        if (groups) (void)hipFree(groups);
+        if (terms) (void)hipFree(terms);
+        if (partial) (void)hipFree(partial);
+    }
+};
+
+namespace {
+
+unsigned persistent_grid(uint64_t ntiles)
+{
+    return (unsigned)std::min<uint64_t>(ntiles, 2048);
+}
+
+cfh_status build_pass_args(cfh_plan_s *p)
+{
+    p->args.resize(p->passes.size());
+    for (size_t i = 0; i < p->passes.size(); ++i) {
+        const PassPlan &pp = p->passes[i];
+        PassArgs &a = p->args[i];
+        std::memset(&a, 0, sizeof(a));
+        a.outer_mask = pp.outer_mask;
+        for (int j = 0; j < pp.b; ++j) a.v[j] = pp.v[j];
+        a.b = pp.b;
+        a.nrot = (int)pp.rots.size();
+        for (int j = 0; j < a.nrot; ++j) {
+            const int k = pp.rots[j];
+            bool in_span = false;
+            local_coords(pp.v, p->rot[k].x, &in_span);
+            if (!in_span) return set_error(CFH_E_INVAL, "planner produced a rotation outside its tile span");
+            a.rot[j] = make_rot_desc(pp, p->rot[k], k);
+        }
+    }
+    return CFH_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+int cfh_device_count(void)
+{
+    int c = 0;
+    if (hipGetDeviceCount(&c) != hipSuccess) return 0;
+    return c;
+}
+
+cfh_status cfh_state_set_basis(void *psi, int n, int dtype, uint64_t index, void *stream)
+{
+    cfh_status st = check_state_args(psi, n, dtype, "cfh_state_set_basis");
+    if (st) return st;
+    const uint64_t N = 1ull << n;
+    if (index >= N) return set_error(CFH_E_RANGE, "cfh_state_set_basis: index >= 2^n");
+    const unsigned grid = (unsigned)std::min<uint64_t>((N + 255) / 256, 1u << 20);
+    if (dtype == CFH_C128)
+        hipLaunchKernelGGL((k_set_basis<double2>), dim3(grid), dim3(256), 0, (hipStream_t)stream,
+                           (double2 *)psi, N, index);
+    else
+        hipLaunchKernelGGL((k_set_basis<float2>), dim3(grid), dim3(256), 0, (hipStream_t)stream,
+                           (float2 *)psi, N, index);
+    return last_launch("k_set_basis");
+}
+
+cfh_status cfh_apply_pauli_rotation(void *psi, int n, int dtype, uint64_t x, uint64_t z, int e, double theta,
+                                    void *stream)
+{
+    cfh_status st = check_state_args(psi, n, dtype, "cfh_apply_pauli_rotation");
+    if (st) return st;
+    st = check_pauli(cfh_pauli{x, z, e, 0}, n, true, "cfh_apply_pauli_rotation");
+    if (st) return st;
+    const double c = std::cos(0.5 * theta), s = std::sin(0.5 * theta);
+    if (dtype == CFH_C128)
+        return rot_one((double2 *)psi, n, x, z, e, c, s, nullptr, 0, 1.0, (hipStream_t)stream);
+    return rot_one((float2 *)psi, n, x, z, e, c, s, nullptr, 0, 1.0, (hipStream_t)stream);
+}
+
+cfh_status cfh_plan_create(int n, int dtype, const cfh_pauli *rot, size_t m, const cfh_tuning *tuning,
+                           cfh_plan *out)
+{
+    if (!out || (m && !rot)) return set_error(CFH_E_INVAL, "cfh_plan_create: null argument");
+    if (n < 1 || n > kMaxStateQubits) return set_error(CFH_E_UNSUPPORTED, "cfh_plan_create: n must be in 1..34");
+    if (dtype != CFH_C64 && dtype != CFH_C128) return set_error(CFH_E_UNSUPPORTED, "cfh_plan_create: dtype");
+    if (m > (size_t)INT32_MAX) return set_error(CFH_E_INVAL, "cfh_plan_create: too many rotations");
+    for (size_t i = 0; i < m; ++i) {
+        cfh_status st = check_pauli(rot[i], n, true, "cfh_plan_create");
+        if (st) return st;
+    }
+    std::unique_ptr<cfh_plan_s> p(new (std::nothrow) cfh_plan_s);
+    if (!p) return set_error(CFH_E_NOMEM, "cfh_plan_create: host memory");
+    p->n = n;
+    p->dtype = dtype;
+    p->tu = resolve_tuning(tuning, n, dtype, false);
+    if (tuning && (tuning->block_threads != 0 && tuning->block_threads != 256))
+        return set_error(CFH_E_UNSUPPORTED, "cfh_plan_create: block_threads must be 256");
+    p->rot.resize(m);
+    for (size_t i = 0; i < m; ++i) p->rot[i] = Pauli{rot[i].x, rot[i].z, rot[i].e & 3};
+    if (!p->tu.unfused) {
+        p->passes = plan_rotations(n, p->rot, p->tu);
+        cfh_status st = build_pass_args(p.get());
+        if (st) return st;
+    }
+    cfh_status st = CFH_OK;
+    if (m && !hip_ok(hipMalloc(&p->coef, m * sizeof(double2)), "cfh_plan_create: hipMalloc", &st)) return st;
+    // adjoint partial sums: one row of kMaxRun per persistent workgroup
+    int bmax = 0;
+    for (auto &pp : p->passes) bmax = std::max(bmax, pp.b);
+    const int bmin = p->passes.empty() ? n : p->passes[0].b;
+    p->adj_grid = persistent_grid(1ull << (n - std::min(bmin, n)));
+    if (!hip_ok(hipMalloc(&p->gpart, (size_t)p->adj_grid * kMaxRun * sizeof(double)), "cfh_plan_create: hipMalloc",
+                &st))
+        return st;
+    *out = p.release();
+    return CFH_OK;
+}
+
+cfh_status cfh_plan_destroy(cfh_plan p)
+{
+    delete p;
+    return CFH_OK;
+}
+
+cfh_status cfh_plan_info(cfh_plan p, int64_t *n_passes, int64_t *n_rot, int32_t *tile_bits, double *hbm_bytes)
+{
+    if (!p) return set_error(CFH_E_INVAL, "cfh_plan_info: null plan");
+    const int64_t np = p->tu.unfused ? (int64_t)p->rot.size() : (int64_t)p->passes.size();
+    if (n_passes) *n_passes = np;
+    if (n_rot) *n_rot = (int64_t)p->rot.size();
+    if (tile_bits) *tile_bits = p->tu.unfused ? 0 : p->tu.tile_bits;
+    if (hbm_bytes) *hbm_bytes = 2.0 * (double)np * (double)(1ull << p->n) * (double)amp_bytes(p->dtype);
+    return CFH_OK;
+}
+
+cfh_status cfh_plan_schedule(cfh_plan p, int64_t *pass_start, int64_t *order)
+{
+    if (!p || !pass_start || !order) return set_error(CFH_E_INVAL, "cfh_plan_schedule: null argument");
+    if (p->tu.unfused) {
+        for (size_t i = 0; i <= p->rot.size(); ++i) pass_start[i] = (int64_t)i;
+        for (size_t i = 0; i < p->rot.size(); ++i) order[i] = (int64_t)i;
+        return CFH_OK;
+    }
+    int64_t o = 0;
+    for (size_t i = 0; i < p->passes.size(); ++i) {
+        pass_start[i] = o;
+        for (int k : p->passes[i].rots) order[o++] = k;
+    }
+    pass_start[p->passes.size()] = o;
+    return CFH_OK;
+}
+
+cfh_status cfh_apply_plan(cfh_plan p, void *psi, const double *theta_dev, int inverse, void *stream)
+{
+    if (!p || !psi || (!theta_dev && !p->rot.empty())) return set_error(CFH_E_INVAL, "cfh_apply_plan: null argument");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t m = (int64_t)p->rot.size();
+    if (m == 0) return CFH_OK;
+    hipLaunchKernelGGL(k_coef, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, theta_dev, p->coef, m);
+    cfh_status st = last_launch("k_coef");
+    if (st) return st;
+    const double ssign = inverse ? -1.0 : 1.0;
+    if (p->tu.unfused) {
+        for (int64_t i = 0; i < m; ++i) {
+            const int64_t k = inverse ? m - 1 - i : i;
+            const Pauli &r = p->rot[k];
+            st = p->dtype == CFH_C128
+                     ? rot_one((double2 *)psi, p->n, r.x, r.z, r.e, 0, 0, p->coef, (int)k, ssign, s)
+                     : rot_one((float2 *)psi, p->n, r.x, r.z, r.e, 0, 0, p->coef, (int)k, ssign, s);
+            if (st) return st;
+        }
+        return CFH_OK;
+    }
+    const int64_t np = (int64_t)p->args.size();
+    for (int64_t i = 0; i < np; ++i) {
+        PassArgs a = p->args[inverse ? np - 1 - i : i];
+        a.inverse = inverse ? 1 : 0;
+        const uint64_t ntiles = 1ull << (p->n - a.b);
+        st = p->dtype == CFH_C128 ? launch_pass(a.b, ntiles, s, (double2 *)psi, p->coef, a)
+                                  : launch_pass(a.b, ntiles, s, (float2 *)psi, p->coef, a);
+        if (st) return st;
+    }
+    return CFH_OK;
+}
+
+// ------------------------------------------------------------- Hamiltonians
+cfh_status cfh_ham_create(int n, int dtype, const cfh_pauli *terms, const double *coeff, size_t m,
+                          const cfh_tuning *tuning, cfh_ham *out)
+{
+    if (!out || (m && (!terms || !coeff))) return set_error(CFH_E_INVAL, "cfh_ham_create: null argument");
+    if (n < 1 || n > kMaxStateQubits) return set_error(CFH_E_UNSUPPORTED, "cfh_ham_create: n must be in 1..34");
+    if (dtype != CFH_C64 && dtype != CFH_C128) return set_error(CFH_E_UNSUPPORTED, "cfh_ham_create: dtype");
+    for (size_t i = 0; i < m; ++i) {
+        cfh_status st = check_pauli(terms[i], n, true, "cfh_ham_create");
+        if (st) return st;
+    }
+    std::unique_ptr<cfh_ham_s> h(new (std::nothrow) cfh_ham_s);
+    if (!h) return set_error(CFH_E_NOMEM, "cfh_ham_create: host memory");
+    h->n = n;
+    h->dtype = dtype;
+    h->tu = resolve_tuning(tuning, n, dtype, false);
+    // group terms by x mask (first-appearance order)
+    std::map<uint64_t, int> gid;
+    std::vector<HamGroup> groups;
+    for (size_t i = 0; i < m; ++i) {
+        auto it = gid.find(terms[i].x);
+        if (it == gid.end()) {
+            gid[terms[i].x] = (int)groups.size();
+            groups.push_back(HamGroup{terms[i].x, {(int)i}});
+        } else {
+            groups[it->second].terms.push_back((int)i);
+        }
+    }
+    h->n_groups = (int64_t)groups.size();
+    h->passes = plan_hamiltonian(n, groups, h->tu);
+    std::vector<HamGroupDev> gdev;
+    std::vector<HamTermDev> tdev;
+    for (const HamPass &hp : h->passes) {
+        HamPassArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.outer_mask = hp.outer_mask;
+        for (int j = 0; j < hp.b; ++j) a.v[j] = hp.v[j];
+        a.b = hp.b;
+        a.group_begin = (int32_t)gdev.size();
+        a.group_count = (int32_t)hp.groups.size();
+        for (int g : hp.groups) {
+            bool in_span = false;
+            HamGroupDev gd;
+            gd.xl = local_coords(hp.v, groups[g].x, &in_span);
+            if (!in_span) return set_error(CFH_E_INVAL, "Hamiltonian planner produced a group outside its tile");
+            gd.hb = gd.xl ? 31 - __builtin_clz(gd.xl) : -1;
+            gd.term_begin = (int32_t)tdev.size();
+            gd.term_count = (int32_t)groups[g].terms.size();
+            for (int i : groups[g].terms) {
+                HamTermDev td;
+                td.z = terms[i].z;
+                td.zl = local_zmask(hp.v, terms[i].z);
+                td.pad = 0;
+                const int wp = (terms[i].e - popc(terms[i].x & terms[i].z)) & 3;  // i^wp
+                const double c = coeff[i];
+                td.wre = (wp == 0) ? c : (wp == 2) ? -c : 0.0;
+                td.wim = (wp == 1) ? c : (wp == 3) ? -c : 0.0;
+                tdev.push_back(td);
+            }
+            gdev.push_back(gd);
+        }
+        h->args.push_back(a);
+    }
+    cfh_status st = CFH_OK;
+    if (!gdev.empty()) {
+        if (!hip_ok(hipMalloc(&h->groups, gdev.size() * sizeof(HamGroupDev)), "cfh_ham_create: hipMalloc", &st) ||
+            !hip_ok(hipMemcpy(h->groups, gdev.data(), gdev.size() * sizeof(HamGroupDev), hipMemcpyHostToDevice),
+                    "cfh_ham_create: hipMemcpy", &st) ||
+            !hip_ok(hipMalloc(&h->terms, tdev.size() * sizeof(HamTermDev)), "cfh_ham_create: hipMalloc", &st) ||
+            !hip_ok(hipMemcpy(h->terms, tdev.data(), tdev.size() * sizeof(HamTermDev), hipMemcpyHostToDevice),
+                    "cfh_ham_create: hipMemcpy", &st))
+            return st;
+    }
+    h->grid = persistent_grid(1ull << (n - h->tu.tile_bits));
+    if (!hip_ok(hipMalloc(&h->partial, (size_t)h->grid * sizeof(double2)), "cfh_ham_create: hipMalloc", &st))
+        return st;
+    *out = h.release();
+    return CFH_OK;
+}
+
+cfh_status cfh_ham_destroy(cfh_ham h)
+{
+    delete h;
+    return CFH_OK;
+}
+
+cfh_status cfh_ham_info(cfh_ham h, int64_t *n_passes, int64_t *n_groups, double *hbm_bytes)
+{
+    if (!h) return set_error(CFH_E_INVAL, "cfh_ham_info: null");
+    if (n_passes) *n_passes = (int64_t)h->args.size();
+    if (n_groups) *n_groups = h->n_groups;
+    if (hbm_bytes) *hbm_bytes = (double)h->args.size() * (double)(1ull << h->n) * (double)amp_bytes(h->dtype);
+    return CFH_OK;
+}
+
+cfh_status cfh_expval_async(cfh_ham h, const void *psi, double *out_dev, void *stream)
+{
+    if (!h || !psi || !out_dev) return set_error(CFH_E_INVAL, "cfh_expval_async: null argument");
+    hipStream_t s = (hipStream_t)stream;
+    const int cnt = (int)h->grid * 2;
+    hipLaunchKernelGGL(k_zero_d, dim3((cnt + 255) / 256), dim3(256), 0, s, (double *)h->partial, (int64_t)cnt);
+    cfh_status st = last_launch("k_zero_d");
+    if (st) return st;
+    for (const HamPassArgs &a : h->args) {
+        const uint64_t ntiles = 1ull << (h->n - a.b);
+        st = h->dtype == CFH_C128
+                 ? launch_ham(a.b, ntiles, h->grid, s, (const double2 *)psi, (double2 *)nullptr, a, h->groups,
+                              h->terms, h->partial, 0)
+                 : launch_ham(a.b, ntiles, h->grid, s, (const float2 *)psi, (float2 *)nullptr, a, h->groups,
+                              h->terms, h->partial, 0);
+        if (st) return st;
+    }
+    hipLaunchKernelGGL(k_reduce_partial, dim3(1), dim3(256), 0, s, h->partial, (int)h->grid, out_dev);
+    return last_launch("k_reduce_partial");
+}
+
+cfh_status cfh_ham_apply(cfh_ham h, const void *psi, void *out, void *stream)
+{
+    if (!h || !psi || !out) return set_error(CFH_E_INVAL, "cfh_ham_apply: null argument");
+    if (psi == out) return set_error(CFH_E_INVAL, "cfh_ham_apply: out must not alias psi");
+    hipStream_t s = (hipStream_t)stream;
+    if (h->args.empty()) {
+        const uint64_t cnt = (1ull << h->n) * amp_bytes(h->dtype) / 8;
+        hipLaunchKernelGGL(k_zero_d, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, (double *)out,
+                           (int64_t)cnt);
+        return last_launch("k_zero_d");
+    }
+    for (size_t i = 0; i < h->args.size(); ++i) {
+        const HamPassArgs &a = h->args[i];
+        const uint64_t ntiles = 1ull << (h->n - a.b);
+        cfh_status st = h->dtype == CFH_C128
+                            ? launch_ham(a.b, ntiles, 0, s, (const double2 *)psi, (double2 *)out, a, h->groups,
+                                         h->terms, nullptr, i > 0)
+                            : launch_ham(a.b, ntiles, 0, s, (const float2 *)psi, (float2 *)out, a, h->groups,
+                                         h->terms, nullptr, i > 0);
+        if (st) return st;
+    }
+    return CFH_OK;
+}
+
+cfh_status cfh_expval(const void *psi, int n, int dtype, const cfh_pauli *terms, const double *coeff, size_t m,
+                      double *out_host, void *stream)
+{
+    if (!out_host) return set_error(CFH_E_INVAL, "cfh_expval: null output");
+    cfh_status st = check_state_args(psi, n, dtype, "cfh_expval");
+    if (st) return st;
+    cfh_ham h = nullptr;
+    st = cfh_ham_create(n, dtype, terms, coeff, m, nullptr, &h);
+    if (st) return st;
+    double *d = nullptr;
+    if (!hip_ok(hipMalloc(&d, 2 * sizeof(double)), "cfh_expval: hipMalloc", &st)) {
+        cfh_ham_destroy(h);
+        return st;
+    }
+    st = cfh_expval_async(h, psi, d, stream);
+    if (!st && hip_ok(hipStreamSynchronize((hipStream_t)stream), "cfh_expval: sync", &st))
+        hip_ok(hipMemcpy(out_host, d, 2 * sizeof(double), hipMemcpyDeviceToHost), "cfh_expval: copy", &st);
+    (void)hipFree(d);
+    cfh_ham_destroy(h);
+    return st;
+}
+
+// ------------------------------------------------------------- adjoint
+cfh_status cfh_adjoint_grad(cfh_plan p, cfh_ham h, void *psi, void *lam, const double *theta_dev, double *grad_dev,
+                            void *stream)
+{
+    if (!p || !h || !psi || !lam || !grad_dev || (!theta_dev && !p->rot.empty()))
+        return set_error(CFH_E_INVAL, "cfh_adjoint_grad: null argument");
+    if (p->n != h->n || p->dtype != h->dtype)
+        return set_error(CFH_E_INVAL, "cfh_adjoint_grad: plan and Hamiltonian differ in n or dtype");
+    if (p->tu.unfused) return set_error(CFH_E_UNSUPPORTED, "cfh_adjoint_grad: needs a fused plan");
+    hipStream_t s = (hipStream_t)stream;
+    cfh_status st = cfh_ham_apply(h, psi, lam, stream);
+    if (st) return st;
+    const int64_t m = (int64_t)p->rot.size();
+    if (m == 0) return CFH_OK;
+    hipLaunchKernelGGL(k_coef, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, theta_dev, p->coef, m);
+    if ((st = last_launch("k_coef"))) return st;
+    for (int64_t i = (int64_t)p->args.size() - 1; i >= 0; --i) {
+        const PassArgs &a = p->args[i];
+        const uint64_t ntiles = 1ull << (p->n - a.b);
+        const unsigned grid = (unsigned)std::min<uint64_t>(ntiles, p->adj_grid);
+        st = p->dtype == CFH_C128
+                 ? launch_adjoint(a.b, ntiles, grid, s, (double2 *)psi, (double2 *)lam, p->coef, a, p->gpart)
+                 : launch_adjoint(a.b, ntiles, grid, s, (float2 *)psi, (float2 *)lam, p->coef, a, p->gpart);
+        if (st) return st;
+        hipLaunchKernelGGL(k_grad_reduce, dim3(a.nrot), dim3(256), 0, s, p->gpart, (int)grid, a, grad_dev);
+        if ((st = last_launch("k_grad_reduce"))) return st;
+    }
+    return CFH_OK;
+}
+
+// ------------------------------------------------------- device frame map
+cfh_status cfh_frame_conjugate_device(cfh_frame f, const cfh_pauli *in_dev, cfh_pauli *out_dev, size_t m,
+                                      void *stream)
+{
+    if (!f || (m && (!in_dev || !out_dev))) return set_error(CFH_E_INVAL, "cfh_frame_conjugate_device: null");
+    if (m == 0) return CFH_OK;
+    std::vector<FrameRowDev> rows(2 * f->n);
+    for (int q = 0; q < f->n; ++q) {
+        rows[q] = FrameRowDev{f->zf[q].x, f->zf[q].z, f->zf[q].e, 0};
+        rows[f->n + q] = FrameRowDev{f->xf[q].x, f->xf[q].z, f->xf[q].e, 0};
+    }
+    FrameRowDev *d = nullptr;
+    cfh_status st = CFH_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (!hip_ok(hipMalloc((void **)&d, rows.size() * sizeof(FrameRowDev)), "hipMalloc", &st)) return st;
+    if (!hip_ok(hipMemcpy(d, rows.data(), rows.size() * sizeof(FrameRowDev), hipMemcpyHostToDevice), "hipMemcpy",
+                &st)) {
+        (void)hipFree(d);
+        return st;
+    }
+    hipLaunchKernelGGL(k_frame_conjugate, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, d, f->n, in_dev,
+                       out_dev, (uint64_t)m);
+    st = last_launch("k_frame_conjugate");
+    // the row copy is freed only after the kernel that reads it has finished
+    cfh_status st2 = CFH_OK;
+    hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize", &st2);
+    (void)hipFree(d);
+    return st ? st : st2;
+}
+
+} // extern "C"

@@ -1,0 +1,261 @@
+// Host-side planning for libcfh: tuning defaults, the fusion planner that
+// packs rotations into LDS tile passes, and the grouping of Hamiltonian terms
+// into read-only passes.
+#include <algorithm>
+#include <numeric>
+
+#include "cfh_internal.hpp"
+
+namespace cfh {
+
+TuningResolved resolve_tuning(const cfh_tuning *t, int n, int dtype, bool adjoint_tiles)
+{
+    TuningResolved r;
+    const bool c64 = dtype == CFH_C64;
+    // 64 KiB of LDS per tile by default (two workgroups per CU on 160 KiB),
+    // half that when a tile of the state and one of the adjoint vector share LDS.
+    int b = c64 ? 13 : 12;
+    if (adjoint_tiles) b -= 1;
+    r.tile_bits = (t && t->tile_bits > 0) ? t->tile_bits : b;
+    r.low_bits = (t && t->low_bits > 0) ? t->low_bits : (c64 ? 6 : 5);
+    r.max_run = (t && t->max_run > 0) ? t->max_run : kMaxRun;
+    r.lookahead = (t && t->lookahead != 0) ? t->lookahead : 512;
+    r.unfused = (t && t->unfused) ? 1 : 0;
+    r.block_threads = (t && t->block_threads > 0) ? t->block_threads : 256;
+    r.max_run = std::min(r.max_run, kMaxRun);
+    r.tile_bits = std::min(r.tile_bits, std::min(n, kMaxTileBits));
+    r.low_bits = std::min(r.low_bits, r.tile_bits);
+    // keep one free dimension so every pass can take at least one rotation/group
+    if (r.tile_bits < n) r.low_bits = std::min(r.low_bits, r.tile_bits - 1);
+    return r;
+}
+
+namespace {
+
+// Subspace of GF(2)^64 in reduced echelon form (each vector owns a pivot bit
+// that no other vector has set).
+struct Span {
+    std::vector<uint64_t> v;
+    std::vector<int> piv;
+    uint64_t pivmask = 0;
+
+    uint64_t reduce(uint64_t x) const
+    {
+        for (size_t i = 0; i < v.size(); ++i)
+            if ((x >> piv[i]) & 1) x ^= v[i];
+        return x;
+    }
+    void add(uint64_t r)  // r must be reduced and nonzero
+    {
+        const int p = 63 - __builtin_clzll(r);
+        for (auto &w : v)
+            if ((w >> p) & 1) w ^= r;
+        v.push_back(r);
+        piv.push_back(p);
+        pivmask |= 1ull << p;
+    }
+    int dim() const { return (int)v.size(); }
+};
+
+uint64_t full_mask(int n) { return n >= 64 ? ~0ull : ((1ull << n) - 1); }
+
+// Complete to dimension b with unit vectors of the lowest free bits and order
+// the basis so that unit vectors come first by bit position: then the low
+// local index bits address contiguous amplitudes.
+void finish_basis(Span &s, int n, int b, std::vector<uint64_t> &v_out, uint64_t &outer)
+{
+    for (int j = 0; j < n && s.dim() < b; ++j) {
+        const uint64_t e = 1ull << j;
+        const uint64_t r = s.reduce(e);
+        if (r) s.add(r);
+    }
+    std::vector<int> idx(s.dim());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) {
+        const bool ua = __builtin_popcountll(s.v[a]) == 1, uc = __builtin_popcountll(s.v[c]) == 1;
+        if (ua != uc) return ua;
+        return s.piv[a] < s.piv[c];
+    });
+    v_out.clear();
+    for (int i : idx) v_out.push_back(s.v[i]);
+    outer = full_mask(n) & ~s.pivmask;
+}
+
+} // namespace
+
+uint32_t local_coords(const std::vector<uint64_t> &v, uint64_t x, bool *in_span)
+{
+    // In reduced echelon form bit i of the local coordinates is the pivot bit
+    // of v[i] in x; the pivot of v[i] is its highest bit not shared with any
+    // other basis vector.  Recompute pivots from the vectors themselves.
+    uint32_t xl = 0;
+    uint64_t acc = 0;
+    uint64_t others_or = 0;
+    (void)others_or;
+    for (size_t i = 0; i < v.size(); ++i) {
+        uint64_t own = v[i];
+        for (size_t j = 0; j < v.size(); ++j)
+            if (j != i) own &= ~v[j];
+        const int p = 63 - __builtin_clzll(own);
+        if ((x >> p) & 1) {
+            xl |= 1u << i;
+            acc ^= v[i];
+        }
+    }
+    if (in_span) *in_span = (acc == x);
+    return xl;
+}
+
+uint32_t local_zmask(const std::vector<uint64_t> &v, uint64_t z)
+{
+    uint32_t zl = 0;
+    for (size_t i = 0; i < v.size(); ++i)
+        if (popc(v[i] & z) & 1) zl |= 1u << i;
+    return zl;
+}
+
+RotDesc make_rot_desc(const PassPlan &pp, const Pauli &p, int k)
+{
+    RotDesc d{};
+    bool ok = true;
+    d.xl = local_coords(pp.v, p.x, &ok);
+    d.zl = local_zmask(pp.v, p.z);
+    d.z = p.z;
+    d.hb = d.xl ? 31 - __builtin_clz(d.xl) : -1;
+    d.k = k;
+    d.w = (p.e - popc(p.x & p.z) + 3) & 3;
+    d.dsign = popc(p.x & p.z) & 1;
+    return d;
+}
+
+std::vector<PassPlan> plan_rotations(int n, const std::vector<Pauli> &rot, const TuningResolved &tu)
+{
+    const int m = (int)rot.size();
+    const int b = tu.tile_bits, c = tu.low_bits;
+    std::vector<PassPlan> out;
+    std::vector<char> taken(m, 0);
+    std::vector<int> skipped;
+    int first = 0;
+    while (first < m) {
+        Span s;
+        for (int j = 0; j < c; ++j) s.add(1ull << j);
+        PassPlan pp;
+        skipped.clear();
+        int scanned = 0;
+        for (int j = first; j < m && (int)pp.rots.size() < tu.max_run; ++j) {
+            if (taken[j]) continue;
+            if (tu.lookahead >= 0 && scanned > tu.lookahead) break;
+            ++scanned;
+            const uint64_t r = s.reduce(rot[j].x);
+            bool ok = (r == 0) || s.dim() < b;
+            if (ok) {
+                // may move ahead of the skipped rotations only if it commutes with all of them
+                for (int q : skipped)
+                    if (anticommute(rot[q].x, rot[q].z, rot[j].x, rot[j].z)) { ok = false; break; }
+            }
+            if (ok) {
+                if (r) s.add(r);
+                pp.rots.push_back(j);
+                taken[j] = 1;
+            } else {
+                skipped.push_back(j);
+                if (tu.lookahead < 0) break;
+            }
+        }
+        finish_basis(s, n, b, pp.v, pp.outer_mask);
+        pp.b = b;
+        out.push_back(std::move(pp));
+        while (first < m && taken[first]) ++first;
+    }
+    return out;
+}
+
+std::vector<HamPass> plan_hamiltonian(int n, const std::vector<HamGroup> &groups, const TuningResolved &tu)
+{
+    const int b = tu.tile_bits, c = tu.low_bits;
+    const int G = (int)groups.size();
+    std::vector<char> done(G, 0);
+    int left = G;
+    std::vector<HamPass> out;
+    while (left > 0) {
+        // Grow a b-dimensional subspace greedily.  Sparse x masks (JW strings)
+        // are covered best by whole qubits (unit vectors: one tile then holds
+        // every group inside those qubits); a dense x that would need too many
+        // qubits is added as one vector.  Every group fits some pass, since a
+        // single x adds at most one dimension.
+        Span s;
+        for (int j = 0; j < c; ++j) s.add(1ull << j);
+        std::vector<int> chosen;
+        std::vector<char> in(G, 0);
+        auto sweep = [&]() {
+            for (int g = 0; g < G && (int)chosen.size() < kMaxGroupsPerPass; ++g)
+                if (!done[g] && !in[g] && s.reduce(groups[g].x) == 0) { in[g] = 1; chosen.push_back(g); }
+        };
+        sweep();
+        while ((int)chosen.size() < kMaxGroupsPerPass && s.dim() < b) {
+            int best = -1, best_cost = 1 << 30;
+            uint64_t best_r = 0;
+            for (int g = 0; g < G; ++g) {
+                if (done[g] || in[g]) continue;
+                const uint64_t r = s.reduce(groups[g].x);
+                const int cost = popc(r);
+                if (cost < best_cost) { best_cost = cost; best = g; best_r = r; }
+            }
+            if (best < 0) break;
+            if (best_cost <= b - s.dim()) {
+                for (uint64_t r = best_r; r; r &= r - 1) {
+                    const uint64_t e = s.reduce(r & (~r + 1));
+                    if (e) s.add(e);
+                }
+            } else {
+                s.add(best_r);
+            }
+            sweep();
+        }
+        HamPass hp;
+        hp.b = b;
+        finish_basis(s, n, b, hp.v, hp.outer_mask);
+        for (int g : chosen) { done[g] = 1; --left; }
+        hp.groups = std::move(chosen);
+        out.push_back(std::move(hp));
+    }
+    return out;
+}
+
+} // namespace cfh
+
+using namespace cfh;
+
+extern "C" cfh_status cfh_plan_dry_run(int n, int dtype, const cfh_pauli *rot, size_t m, const cfh_tuning *tuning,
+                                       int64_t *n_passes, int64_t *pass_start, int64_t *order)
+{
+    if (!n_passes || !pass_start || (m && (!rot || !order)))
+        return set_error(CFH_E_INVAL, "cfh_plan_dry_run: null argument");
+    if (n < 1 || n > kMaxStateQubits) return set_error(CFH_E_UNSUPPORTED, "cfh_plan_dry_run: n must be in 1..34");
+    if (dtype != CFH_C64 && dtype != CFH_C128) return set_error(CFH_E_UNSUPPORTED, "cfh_plan_dry_run: dtype");
+    std::vector<Pauli> r(m);
+    for (size_t i = 0; i < m; ++i) {
+        cfh_status st = check_pauli(rot[i], n, true, "cfh_plan_dry_run");
+        if (st) return st;
+        r[i] = Pauli{rot[i].x, rot[i].z, rot[i].e & 3};
+    }
+    const TuningResolved tu = resolve_tuning(tuning, n, dtype, false);
+    int64_t o = 0;
+    if (tu.unfused) {
+        for (size_t i = 0; i < m; ++i) {
+            pass_start[i] = (int64_t)i;
+            order[i] = (int64_t)i;
+        }
+        pass_start[m] = (int64_t)m;
+        *n_passes = (int64_t)m;
+        return CFH_OK;
+    }
+    const std::vector<PassPlan> passes = plan_rotations(n, r, tu);
+    for (size_t i = 0; i < passes.size(); ++i) {
+        pass_start[i] = o;
+        for (int k : passes[i].rots) order[o++] = k;
+    }
+    pass_start[passes.size()] = o;
+    *n_passes = (int64_t)passes.size();
+    return CFH_OK;
+}
