@@ -54,7 +54,11 @@ def main():
     ap.add_argument("--n", type=int, default=28)
     ap.add_argument("--trotter-steps", type=int, default=10)
     ap.add_argument("--no-extras", action="store_true", help="skip unfused/c64/adjoint/cpu legs")
-    ap.add_argument("--cpu-rotations", type=int, default=2)
+    ap.add_argument("--cpu-rotations", type=int, default=20)
+    ap.add_argument("--mode", choices=["full", "passes", "copy"], default="full",
+                    help="passes: apply the plan of the first --rotations rotations once (for counter runs); "
+                         "copy: a plain device copy of the same state size (counter and bandwidth calibration)")
+    ap.add_argument("--rotations", type=int, default=150)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the state-vector path is single-device here "
@@ -69,7 +73,35 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.mode == "copy":
+        # read 2^n * 16 bytes, write as many: the traffic of one fused pass
+        src = torch.ones((1 << args.n) * 2, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        a.record()
+        for _ in range(reps):
+            dst.copy_(src)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        nbytes = 2.0 * src.numel() * 8
+        print(json.dumps({"mode": "copy", "bytes_per_launch": nbytes, "avg_ms": ms,
+                          "achieved_gbs": nbytes / (ms * 1e-3) / 1e9}), flush=True)
+        return
     w = W.config(2, n=args.n, trotter_steps=args.trotter_steps)
+    if args.mode == "passes":
+        frame = hybrid.Frame(w.n)
+        rot = frame.conjugate(cfh.cfh_pauli_encode(w.rot[:args.rotations]))
+        plan = hybrid.Plan(w.n, torch.complex128, rot)
+        theta = torch.tensor(w.theta[:args.rotations], device=dev)
+        psi = hybrid.new_state(w.n, torch.complex128, index=w.init)
+        plan.apply(psi, theta)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "passes", "rotations": args.rotations, **plan.info()}), flush=True)
+        return
     n, K = w.n, w.n_rot
     dtype = torch.complex128
     enc0 = cfh.cfh_pauli_encode(w.rot)
@@ -123,7 +155,9 @@ def main():
     achieved_gbs = pass_bytes / (pass_ms * 1e-3) / 1e9
     energy = float(e_out[0].item())
     value = K / (ms_per_step * 1e-3)
-    traffic = counter_traffic(f"k_pass_n{n}_c128_counters.json")
+    kname = f"k_pass2<double2,{info['tile_bits']}>" if info["tile_bits"] >= 8 else \
+        f"k_pass<double2,{info['tile_bits']}>"
+    traffic = counter_traffic(f"{kname.split('<')[0]}_n{n}_c128_counters.json")
 
     out = {
         "metric": "Pauli rotations/s + HBM GB/s at n=28 c128; adjoint grad time vs forward",
@@ -143,7 +177,7 @@ def main():
                    "dt": 0.05, "coeff_sigma": 0.1, "seed": 0},
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": f"k_pass<double2,{info['tile_bits']}>",
+                     "kernel": kname,
                      "bytes_per_launch": pass_bytes, "avg_launch_ms": pass_ms},
         "passes": launches,
         "fusion_depth": K / launches,
@@ -170,6 +204,24 @@ def main():
                           "avg_launch_ms": u_ms / Ku,
                           "achieved_gbs": pass_bytes / (u_ms / Ku * 1e-3) / 1e9}
         del pu
+
+        # the LDS-staged fused kernel (every rotation through LDS) on a 2,000-rotation prefix
+        Kl = min(2000, K)
+        pl = hybrid.Plan(n, dtype, rot0[:Kl], {"variant": 1, "tile_bits": 11})
+        th_l = theta[:Kl].contiguous()
+        cfh.cfh_state_set_basis(psi, n, w.init)
+        pl.apply(psi, th_l)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        pl.apply(psi, th_l)
+        b.record(stream)
+        torch.cuda.synchronize()
+        l_ms = a.elapsed_time(b)
+        lp = pl.info()["n_passes"]
+        out["lds_staged"] = {"rotations": Kl, "passes": lp, "rotations_per_s": Kl / (l_ms * 1e-3),
+                             "avg_launch_ms": l_ms / lp, "achieved_gbs": pass_bytes / (l_ms / lp * 1e-3) / 1e9}
+        del pl
 
         # complex64 storage, full workload, error against the complex128 result
         cfh.cfh_state_set_basis(psi, n, w.init)

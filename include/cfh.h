@@ -81,8 +81,12 @@ typedef struct cfh_tuning {
     int32_t max_run;       /* most rotations in one fused pass (<= 32) */
     int32_t lookahead;     /* rotations scanned for commuting reordering; -1 = in order only */
     int32_t unfused;       /* 1 = one HBM pass per rotation (no LDS staging) */
-    int32_t block_threads; /* threads per workgroup (256 or 512) */
-    int32_t reserved[2];
+    int32_t block_threads; /* threads per workgroup of the LDS-staged kernel (256) */
+    int32_t variant;       /* fused kernel: 0 = default, 1 = LDS-staged (every rotation through LDS),
+                              2 = register-tiled (micro-groups of 4 dimensions in registers, LDS
+                              only between micro-groups, next coset prefetched into registers;
+                              needs tile_bits >= 8), 3 = register-tiled without the prefetch */
+    int32_t reserved;
 } cfh_tuning;
 
 typedef struct cfh_frame_s *cfh_frame;

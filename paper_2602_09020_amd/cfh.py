@@ -33,7 +33,7 @@ class cfh_pauli(C.Structure):
 class cfh_tuning(C.Structure):
     _fields_ = [("tile_bits", C.c_int32), ("low_bits", C.c_int32), ("max_run", C.c_int32),
                 ("lookahead", C.c_int32), ("unfused", C.c_int32), ("block_threads", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("variant", C.c_int32), ("reserved", C.c_int32)]
 
 
 class CfhError(RuntimeError):

@@ -71,6 +71,48 @@ struct PassArgs {
     RotDesc rot[kMaxRun];
 };
 
+// Register-tiled form of a pass.  Inside the coset, a run is split into
+// micro-groups: consecutive rotations whose local x masks span at most
+// kRegDims dimensions U = span(u_0..u_3).  During a micro-group every thread
+// holds the 16 amplitudes base_t ^ U[j] (j = 0..15) of one coset of U in
+// registers, so each rotation pairs register j with register j ^ cx.  Between
+// micro-groups the tile is transposed through LDS.  base_t deposits the
+// thread index into the non-pivot local bits `npiv` of the micro-group.
+constexpr int kRegDims = 4;
+constexpr int kRegs = 1 << kRegDims;
+constexpr int kMaxMG = 8;
+
+struct RotDesc2 {
+    uint32_t zl;     // local z parity mask
+    uint16_t msign;  // bit j = parity(U[j] & zl)
+    uint8_t cx;      // partner mask in register coordinates, 0 = diagonal
+    uint8_t flags;   // bit 0: beta imaginary (w odd); bit 1: negate (w & 2)
+    uint64_t z;      // global z (coset base sign)
+    int32_t k;       // rotation index
+    int32_t pad[3];
+};
+
+struct MGDesc2 {
+    uint32_t U[kRegs];  // local offset of register j
+    uint32_t npiv;      // local bits that enumerate threads
+    int32_t rot_begin;
+    int32_t rot_count;
+    int32_t pad;
+};
+
+struct PassArgs2 {
+    uint64_t outer_mask;
+    uint64_t v[kMaxTileBits];        // local -> global basis
+    uint64_t LU_first[kRegs];        // global offset of register j, first micro-group layout
+    uint64_t LU_last[kRegs];         // same for the last micro-group layout
+    int32_t b;
+    int32_t nmg;
+    int32_t inverse;                 // negate angles (order already reversed on the host)
+    int32_t pad;
+    MGDesc2 mg[kMaxMG];
+    RotDesc2 rot[kMaxRun];
+};
+
 // One x-group of a read-only Hamiltonian pass (device memory).
 struct HamGroupDev {
     uint32_t xl;
@@ -103,10 +145,11 @@ struct PassPlan {
 };
 
 struct TuningResolved {
-    int tile_bits, low_bits, max_run, lookahead, unfused, block_threads;
+    int tile_bits, low_bits, max_run, lookahead, unfused, block_threads, variant;
 };
 
-TuningResolved resolve_tuning(const cfh_tuning *t, int n, int dtype, bool adjoint_tiles);
+enum { kTuneForward = 0, kTuneAdjoint = 1, kTuneHamiltonian = 2 };
+TuningResolved resolve_tuning(const cfh_tuning *t, int n, int dtype, int kind);
 
 // Builds the passes of a rotation sequence (the fusion planner).
 std::vector<PassPlan> plan_rotations(int n, const std::vector<Pauli> &rot, const TuningResolved &tu);
@@ -126,6 +169,9 @@ std::vector<HamPass> plan_hamiltonian(int n, const std::vector<HamGroup> &groups
 
 // Fill a kernel descriptor for one rotation inside pass `pp`.
 RotDesc make_rot_desc(const PassPlan &pp, const Pauli &p, int k);
+// Register-tiled kernel arguments for one pass (forward or inverse order);
+// false if the pass does not fit (more than kMaxMG micro-groups, b < kRegDims).
+bool build_pass_args2(const PassPlan &pp, const std::vector<Pauli> &rot, bool inverse, PassArgs2 &a);
 uint32_t local_coords(const std::vector<uint64_t> &v, uint64_t x, bool *in_span);
 uint32_t local_zmask(const std::vector<uint64_t> &v, uint64_t z);
 

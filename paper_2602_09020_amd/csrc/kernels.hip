@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <memory>
 #include <new>
 #include <vector>
@@ -241,6 +242,157 @@ k_pass(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs a
         for (int i = 0; i < B - LT; ++i)
             if ((k >> i) & 1) Lk ^= args.v[LT + i];
         psi[yb ^ Lk] = r[k];
+    }
+}
+
+// ------------------------------------------ register-tiled fused pass (v2)
+// Thread t of a workgroup holds, during micro-group g, the 16 amplitudes
+// a = base_t ^ U_g[j] of the coset, base_t = deposit(t, npiv_g).  A rotation
+// of the micro-group pairs registers j and j ^ cx (cx known only at run time
+// but uniform, so it selects one of 15 unrolled bodies).  Member j of the
+// pair gets the sign (-1)^{parity(y & z)} = (-1)^{st ^ msign_j}, with st the
+// thread/coset part and msign_j the register part precomputed on the host.
+// Workgroups are persistent: the loads of the next coset are issued before
+// the current one is processed, so HBM traffic overlaps the arithmetic.
+
+__device__ __forceinline__ uint32_t deposit32(uint32_t v, uint32_t mask)
+{
+    uint32_t r = 0;
+    for (uint32_t m = mask; m && v; m &= m - 1, v >>= 1)
+        if (v & 1) r |= m & (~m + 1);
+    return r;
+}
+
+// v with its sign flipped when the (wave-uniform) bit is set: one XOR of the
+// high word instead of a select between two registers.
+__device__ __forceinline__ double flip_if(double v, uint32_t bit)
+{
+    return __longlong_as_double(__double_as_longlong(v) ^ ((unsigned long long)(bit & 1) << 63));
+}
+
+template <int CX, bool IMAG>
+__device__ __forceinline__ void mg_rot(double2 (&r)[kRegs], double c, double srA, uint32_t msign)
+{
+#pragma unroll
+    for (int j = 0; j < kRegs; ++j) {
+        if ((j ^ CX) > j) {
+            const double s0 = flip_if(srA, msign >> j);
+            const double s1 = flip_if(srA, msign >> (j ^ CX));
+            rot_pair(r[j], r[j ^ CX], c, s0, s1, IMAG);
+            // pairs one after another: the scheduler would otherwise keep the
+            // temporaries of all eight pairs live at once
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+template <bool IMAG>
+__device__ __forceinline__ void mg_diag(double2 (&r)[kRegs], double c, double srA, uint32_t msign)
+{
+#pragma unroll
+    for (int j = 0; j < kRegs; ++j) r[j] = rot_diag(r[j], c, flip_if(srA, msign >> j), IMAG);
+}
+
+
+template <bool IMAG>
+__device__ __forceinline__ void mg_dispatch(int cx, double2 (&r)[kRegs], double c, double srA, uint32_t msign)
+{
+    switch (cx) {
+    case 0: mg_diag<IMAG>(r, c, srA, msign); break;
+    case 1: mg_rot<1, IMAG>(r, c, srA, msign); break;
+    case 2: mg_rot<2, IMAG>(r, c, srA, msign); break;
+    case 3: mg_rot<3, IMAG>(r, c, srA, msign); break;
+    case 4: mg_rot<4, IMAG>(r, c, srA, msign); break;
+    case 5: mg_rot<5, IMAG>(r, c, srA, msign); break;
+    case 6: mg_rot<6, IMAG>(r, c, srA, msign); break;
+    case 7: mg_rot<7, IMAG>(r, c, srA, msign); break;
+    case 8: mg_rot<8, IMAG>(r, c, srA, msign); break;
+    case 9: mg_rot<9, IMAG>(r, c, srA, msign); break;
+    case 10: mg_rot<10, IMAG>(r, c, srA, msign); break;
+    case 11: mg_rot<11, IMAG>(r, c, srA, msign); break;
+    case 12: mg_rot<12, IMAG>(r, c, srA, msign); break;
+    case 13: mg_rot<13, IMAG>(r, c, srA, msign); break;
+    case 14: mg_rot<14, IMAG>(r, c, srA, msign); break;
+    default: mg_rot<15, IMAG>(r, c, srA, msign); break;
+    }
+}
+
+// MODE bit 0: prefetch the next coset into registers.
+template <typename Amp, int B, int MODE>
+__global__ void __launch_bounds__(1 << (B - kRegDims))
+k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2 args, uint64_t ntiles)
+{
+    constexpr bool PF = MODE & 1;
+    extern __shared__ unsigned char lds_raw[];
+    Amp *lds = reinterpret_cast<Amp *>(lds_raw);
+    const uint32_t t = threadIdx.x;
+    const int last = args.nmg - 1;
+    uint64_t Lb0 = 0, LbL = 0;
+    {
+        const uint32_t b0 = deposit32(t, args.mg[0].npiv), bL = deposit32(t, args.mg[last].npiv);
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            if ((b0 >> i) & 1) Lb0 ^= args.v[i];
+            if ((bL >> i) & 1) LbL ^= args.v[i];
+        }
+    }
+    Amp pf[kRegs];
+    uint64_t tile = blockIdx.x;
+    if (PF && tile < ntiles) {
+        const uint64_t y0 = deposit(tile, args.outer_mask) ^ Lb0;
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) pf[j] = psi[y0 ^ args.LU_first[j]];
+    }
+    for (; tile < ntiles; tile += gridDim.x) {
+        // keep the 2 x 16 per-register address terms from being hoisted out of
+        // the loop as 64 live VGPRs: recomputing them is two scalar-operand XORs
+        asm volatile("" : "+v"(Lb0), "+v"(LbL));
+        const uint64_t tb = deposit(tile, args.outer_mask);
+        double2 r[kRegs];
+        if (PF) {
+#pragma unroll
+            for (int j = 0; j < kRegs; ++j) r[j] = ld(pf[j]);
+            const uint64_t nt = tile + gridDim.x;
+            if (nt < ntiles) {
+                const uint64_t y0 = deposit(nt, args.outer_mask) ^ Lb0;
+#pragma unroll
+                for (int j = 0; j < kRegs; ++j) pf[j] = psi[y0 ^ args.LU_first[j]];
+            }
+        } else {
+            const uint64_t y0 = tb ^ Lb0;
+#pragma unroll
+            for (int j = 0; j < kRegs; ++j) r[j] = ld(psi[y0 ^ args.LU_first[j]]);
+        }
+        uint32_t bprev = 0;
+        for (int g = 0; g <= last; ++g) {
+            const MGDesc2 &m = args.mg[g];
+            const uint32_t bt = deposit32(t, m.npiv);
+            if (g > 0) {
+                const MGDesc2 &mp = args.mg[g - 1];
+#pragma unroll
+                for (int j = 0; j < kRegs; ++j) st(lds[bprev ^ mp.U[j]], r[j]);
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < kRegs; ++j) r[j] = ld(lds[bt ^ m.U[j]]);
+                __syncthreads();
+            }
+            bprev = bt;
+            for (int ri = m.rot_begin; ri < m.rot_begin + m.rot_count; ++ri) {
+                const RotDesc2 &d = args.rot[ri];
+                const double2 cs = coef[d.k];
+                double sr = args.inverse ? -cs.y : cs.y;
+                if (d.flags & 2) sr = -sr;
+                const int sg = par32(bt & d.zl) ^ par64(tb & d.z);
+                const double srA = sg ? -sr : sr;
+                if (d.flags & 1)
+                    mg_dispatch<true>(d.cx, r, cs.x, srA, d.msign);
+                else
+                    mg_dispatch<false>(d.cx, r, cs.x, srA, d.msign);
+            }
+        }
+        const uint64_t yL = tb ^ LbL;
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) st(psi[yL ^ args.LU_last[j]], r[j]);
     }
 }
 
@@ -645,6 +797,65 @@ cfh_status launch_pass(int b, uint64_t ntiles, hipStream_t s, Amp *psi, const do
     return last_launch("k_pass");
 }
 
+// Persistent grid: as many workgroups as can be resident at once (cached per
+// kernel, LDS size and device).
+unsigned resident_grid(const void *fn, int threads, size_t lds)
+{
+    static std::map<std::tuple<const void *, size_t, int>, unsigned> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const auto key = std::make_tuple(fn, lds, dev);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+    const unsigned g = (unsigned)(per_cu * cus);
+    cache[key] = g;
+    return g;
+}
+
+template <typename Amp, int B, int MODE>
+cfh_status launch_pass2_b(uint64_t ntiles, hipStream_t s, Amp *psi, const double2 *coef, const PassArgs2 &a)
+{
+    if constexpr (((size_t)1 << B) * sizeof(Amp) > 160 * 1024) {
+        return set_error(CFH_E_UNSUPPORTED, "tile_bits too large for LDS");
+    } else {
+        constexpr int T = 1 << (B - kRegDims);
+        const size_t lds = a.nmg > 1 ? ((size_t)1 << B) * sizeof(Amp) : 0;
+        const void *fn = reinterpret_cast<const void *>(&k_pass2<Amp, B, MODE>);
+        static bool attr = false;
+        if (!attr) {
+            (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            attr = true;
+        }
+        const unsigned grid = (unsigned)std::min<uint64_t>(ntiles, resident_grid(fn, T, lds));
+        hipLaunchKernelGGL((k_pass2<Amp, B, MODE>), dim3(grid), dim3(T), lds, s, psi, coef, a, ntiles);
+        return last_launch("k_pass2");
+    }
+}
+
+template <typename Amp, int B>
+cfh_status launch_pass2_m(uint64_t ntiles, hipStream_t s, Amp *psi, const double2 *coef, const PassArgs2 &a, int mode)
+{
+    return (mode & 1) ? launch_pass2_b<Amp, B, 1>(ntiles, s, psi, coef, a)
+                      : launch_pass2_b<Amp, B, 0>(ntiles, s, psi, coef, a);
+}
+
+// Workgroups of 2^(b-4) threads: b >= 10 keeps them at one full wave or more.
+template <typename Amp>
+cfh_status launch_pass2(uint64_t ntiles, hipStream_t s, Amp *psi, const double2 *coef, const PassArgs2 &a, int mode)
+{
+    switch (a.b) {
+    case 10: return launch_pass2_m<Amp, 10>(ntiles, s, psi, coef, a, mode);
+    case 11: return launch_pass2_m<Amp, 11>(ntiles, s, psi, coef, a, mode);
+    case 12: return launch_pass2_m<Amp, 12>(ntiles, s, psi, coef, a, mode);
+    case 13: return launch_pass2_m<Amp, 13>(ntiles, s, psi, coef, a, mode);
+    default: return set_error(CFH_E_UNSUPPORTED, "register-tiled pass needs tile_bits in 10..13");
+    }
+}
+
 template <typename Amp>
 cfh_status launch_ham(int b, uint64_t ntiles, unsigned grid, hipStream_t s, const Amp *psi, Amp *out,
                       const HamPassArgs &a, const HamGroupDev *gr, const HamTermDev *tm, double2 *partial,
@@ -734,9 +945,14 @@ struct cfh_plan_s {
     std::vector<Pauli> rot;
     std::vector<PassPlan> passes;
     std::vector<PassArgs> args;
+    bool v2 = false;                      // register-tiled kernel for the forward/inverse sweep
+    int mode2 = 0;                        // its prefetch / non-temporal mode bits
+    std::vector<PassArgs2> args2, args2_inv;
     double2 *coef = nullptr;     // device, m entries
     double *gpart = nullptr;     // device, adj_grid * kMaxRun
     unsigned adj_grid = 0;
+    std::vector<PassArgs> adj_args;       // passes of the adjoint sweep (two LDS tiles)
+    int adj_b = 0;
     ~cfh_plan_s()
     {
         if (coef) (void)hipFree(coef);
@@ -769,12 +985,13 @@ unsigned persistent_grid(uint64_t ntiles)
     return (unsigned)std::min<uint64_t>(ntiles, 2048);
 }
 
-cfh_status build_pass_args(cfh_plan_s *p)
+cfh_status build_pass_args(const std::vector<PassPlan> &passes, const std::vector<Pauli> &rot,
+                           std::vector<PassArgs> &out)
 {
-    p->args.resize(p->passes.size());
-    for (size_t i = 0; i < p->passes.size(); ++i) {
-        const PassPlan &pp = p->passes[i];
-        PassArgs &a = p->args[i];
+    out.resize(passes.size());
+    for (size_t i = 0; i < passes.size(); ++i) {
+        const PassPlan &pp = passes[i];
+        PassArgs &a = out[i];
         std::memset(&a, 0, sizeof(a));
         a.outer_mask = pp.outer_mask;
         for (int j = 0; j < pp.b; ++j) a.v[j] = pp.v[j];
@@ -783,9 +1000,9 @@ cfh_status build_pass_args(cfh_plan_s *p)
         for (int j = 0; j < a.nrot; ++j) {
             const int k = pp.rots[j];
             bool in_span = false;
-            local_coords(pp.v, p->rot[k].x, &in_span);
+            local_coords(pp.v, rot[k].x, &in_span);
             if (!in_span) return set_error(CFH_E_INVAL, "planner produced a rotation outside its tile span");
-            a.rot[j] = make_rot_desc(pp, p->rot[k], k);
+            a.rot[j] = make_rot_desc(pp, rot[k], k);
         }
     }
     return CFH_OK;
@@ -846,23 +1063,62 @@ cfh_status cfh_plan_create(int n, int dtype, const cfh_pauli *rot, size_t m, con
     if (!p) return set_error(CFH_E_NOMEM, "cfh_plan_create: host memory");
     p->n = n;
     p->dtype = dtype;
-    p->tu = resolve_tuning(tuning, n, dtype, false);
+    p->tu = resolve_tuning(tuning, n, dtype, kTuneForward);
     if (tuning && (tuning->block_threads != 0 && tuning->block_threads != 256))
         return set_error(CFH_E_UNSUPPORTED, "cfh_plan_create: block_threads must be 256");
     p->rot.resize(m);
     for (size_t i = 0; i < m; ++i) p->rot[i] = Pauli{rot[i].x, rot[i].z, rot[i].e & 3};
     if (!p->tu.unfused) {
         p->passes = plan_rotations(n, p->rot, p->tu);
-        cfh_status st = build_pass_args(p.get());
+        cfh_status st = build_pass_args(p->passes, p->rot, p->args);
         if (st) return st;
+        const int b = p->tu.tile_bits;
+        if (p->tu.variant < 0 || p->tu.variant > 3)
+            return set_error(CFH_E_INVAL, "cfh_plan_create: unknown kernel variant");
+        if (p->tu.variant >= 2 && (b < 10 || b > 13))
+            return set_error(CFH_E_UNSUPPORTED, "cfh_plan_create: the register-tiled kernel needs tile_bits in 10..13");
+        // default: register-tiled (no prefetch) for complex128 where it applies,
+        // LDS-staged otherwise (measured faster for complex64 storage)
+        int v = p->tu.variant;
+        if (v == 0) v = (dtype == CFH_C128 && b >= 10 && b <= 13) ? 3 : 1;
+        p->tu.variant = v;
+        p->mode2 = v == 2 ? 1 : 0;
+        if (v >= 2) {
+            p->v2 = true;
+            p->args2.resize(p->passes.size());
+            p->args2_inv.resize(p->passes.size());
+            for (size_t i = 0; i < p->passes.size() && p->v2; ++i)
+                p->v2 = build_pass_args2(p->passes[i], p->rot, false, p->args2[i]) &&
+                        build_pass_args2(p->passes[i], p->rot, true, p->args2_inv[i]);
+            if (!p->v2) {
+                if (p->tu.variant >= 2)
+                    return set_error(CFH_E_INVAL, "cfh_plan_create: a pass does not fit the register-tiled kernel");
+                p->args2.clear();
+                p->args2_inv.clear();
+            }
+        }
+    }
+    // The adjoint sweep keeps a tile of the state and one of lam in LDS, so it
+    // has its own pass list on tiles of at most 2^12 (c128) / 2^13 (c64).
+    {
+        TuningResolved ta = resolve_tuning(tuning, n, dtype, kTuneAdjoint);
+        ta.unfused = 0;
+        const int bcap = dtype == CFH_C128 ? 12 : 13;
+        if (ta.tile_bits > bcap) ta.tile_bits = bcap;
+        if (ta.tile_bits < n) ta.low_bits = std::min(ta.low_bits, ta.tile_bits - 1);
+        if (!p->tu.unfused && ta.tile_bits == p->tu.tile_bits && ta.low_bits == p->tu.low_bits &&
+            ta.max_run == p->tu.max_run && ta.lookahead == p->tu.lookahead) {
+            p->adj_args = p->args;
+        } else {
+            cfh_status st = build_pass_args(plan_rotations(n, p->rot, ta), p->rot, p->adj_args);
+            if (st) return st;
+        }
+        p->adj_b = ta.tile_bits;
     }
     cfh_status st = CFH_OK;
     if (m && !hip_ok(hipMalloc(&p->coef, m * sizeof(double2)), "cfh_plan_create: hipMalloc", &st)) return st;
     // adjoint partial sums: one row of kMaxRun per persistent workgroup
-    int bmax = 0;
-    for (auto &pp : p->passes) bmax = std::max(bmax, pp.b);
-    const int bmin = p->passes.empty() ? n : p->passes[0].b;
-    p->adj_grid = persistent_grid(1ull << (n - std::min(bmin, n)));
+    p->adj_grid = persistent_grid(1ull << (n - p->adj_b));
     if (!hip_ok(hipMalloc(&p->gpart, (size_t)p->adj_grid * kMaxRun * sizeof(double)), "cfh_plan_create: hipMalloc",
                 &st))
         return st;
@@ -926,6 +1182,16 @@ cfh_status cfh_apply_plan(cfh_plan p, void *psi, const double *theta_dev, int in
         return CFH_OK;
     }
     const int64_t np = (int64_t)p->args.size();
+    if (p->v2) {
+        for (int64_t i = 0; i < np; ++i) {
+            const PassArgs2 &a = inverse ? p->args2_inv[np - 1 - i] : p->args2[i];
+            const uint64_t ntiles = 1ull << (p->n - a.b);
+            st = p->dtype == CFH_C128 ? launch_pass2(ntiles, s, (double2 *)psi, p->coef, a, p->mode2)
+                                      : launch_pass2(ntiles, s, (float2 *)psi, p->coef, a, p->mode2);
+            if (st) return st;
+        }
+        return CFH_OK;
+    }
     for (int64_t i = 0; i < np; ++i) {
         PassArgs a = p->args[inverse ? np - 1 - i : i];
         a.inverse = inverse ? 1 : 0;
@@ -952,7 +1218,7 @@ cfh_status cfh_ham_create(int n, int dtype, const cfh_pauli *terms, const double
     if (!h) return set_error(CFH_E_NOMEM, "cfh_ham_create: host memory");
     h->n = n;
     h->dtype = dtype;
-    h->tu = resolve_tuning(tuning, n, dtype, false);
+    h->tu = resolve_tuning(tuning, n, dtype, kTuneHamiltonian);
     // group terms by x mask (first-appearance order)
     std::map<uint64_t, int> gid;
     std::vector<HamGroup> groups;
@@ -1107,7 +1373,6 @@ cfh_status cfh_adjoint_grad(cfh_plan p, cfh_ham h, void *psi, void *lam, const d
         return set_error(CFH_E_INVAL, "cfh_adjoint_grad: null argument");
     if (p->n != h->n || p->dtype != h->dtype)
         return set_error(CFH_E_INVAL, "cfh_adjoint_grad: plan and Hamiltonian differ in n or dtype");
-    if (p->tu.unfused) return set_error(CFH_E_UNSUPPORTED, "cfh_adjoint_grad: needs a fused plan");
     hipStream_t s = (hipStream_t)stream;
     cfh_status st = cfh_ham_apply(h, psi, lam, stream);
     if (st) return st;
@@ -1115,8 +1380,8 @@ cfh_status cfh_adjoint_grad(cfh_plan p, cfh_ham h, void *psi, void *lam, const d
     if (m == 0) return CFH_OK;
     hipLaunchKernelGGL(k_coef, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, theta_dev, p->coef, m);
     if ((st = last_launch("k_coef"))) return st;
-    for (int64_t i = (int64_t)p->args.size() - 1; i >= 0; --i) {
-        const PassArgs &a = p->args[i];
+    for (int64_t i = (int64_t)p->adj_args.size() - 1; i >= 0; --i) {
+        const PassArgs &a = p->adj_args[i];
         const uint64_t ntiles = 1ull << (p->n - a.b);
         const unsigned grid = (unsigned)std::min<uint64_t>(ntiles, p->adj_grid);
         st = p->dtype == CFH_C128

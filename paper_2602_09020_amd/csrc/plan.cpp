@@ -2,26 +2,34 @@
 // packs rotations into LDS tile passes, and the grouping of Hamiltonian terms
 // into read-only passes.
 #include <algorithm>
+#include <cstring>
 #include <numeric>
 
 #include "cfh_internal.hpp"
 
 namespace cfh {
 
-TuningResolved resolve_tuning(const cfh_tuning *t, int n, int dtype, bool adjoint_tiles)
+TuningResolved resolve_tuning(const cfh_tuning *t, int n, int dtype, int kind)
 {
     TuningResolved r;
     const bool c64 = dtype == CFH_C64;
-    // 64 KiB of LDS per tile by default (two workgroups per CU on 160 KiB),
-    // half that when a tile of the state and one of the adjoint vector share LDS.
-    int b = c64 ? 13 : 12;
-    if (adjoint_tiles) b -= 1;
+    // Defaults measured on MI355X at 28 qubits: complex128 runs best with the
+    // register-tiled kernel on 2^13-amplitude tiles, complex64 with the
+    // LDS-staged kernel on 2^12; 16 contiguous amplitudes per chunk.  Small
+    // states keep at least 512 tiles per pass so every CU gets work.  The
+    // adjoint holds two tiles in LDS and uses 2^11 (c128) / 2^12 (c64).
+    // The read-only Hamiltonian passes use 2^12 / 2^13 tiles with 32-amplitude chunks.
+    int b = c64 ? 12 : 13;
+    if (kind == kTuneAdjoint) b = c64 ? 12 : 11;
+    if (kind == kTuneHamiltonian) b = c64 ? 13 : 12;
+    b = std::max(std::min(b, n - 9), std::min(n, 10));
     r.tile_bits = (t && t->tile_bits > 0) ? t->tile_bits : b;
-    r.low_bits = (t && t->low_bits > 0) ? t->low_bits : (c64 ? 6 : 5);
+    r.low_bits = (t && t->low_bits > 0) ? t->low_bits : (kind == kTuneHamiltonian ? 5 : 4);
     r.max_run = (t && t->max_run > 0) ? t->max_run : kMaxRun;
     r.lookahead = (t && t->lookahead != 0) ? t->lookahead : 512;
     r.unfused = (t && t->unfused) ? 1 : 0;
     r.block_threads = (t && t->block_threads > 0) ? t->block_threads : 256;
+    r.variant = t ? t->variant : 0;
     r.max_run = std::min(r.max_run, kMaxRun);
     r.tile_bits = std::min(r.tile_bits, std::min(n, kMaxTileBits));
     r.low_bits = std::min(r.low_bits, r.tile_bits);
@@ -170,6 +178,96 @@ std::vector<PassPlan> plan_rotations(int n, const std::vector<Pauli> &rot, const
     return out;
 }
 
+bool build_pass_args2(const PassPlan &pp, const std::vector<Pauli> &rot, bool inverse, PassArgs2 &a)
+{
+    std::memset(&a, 0, sizeof(a));
+    const int b = pp.b;
+    if (b < kRegDims || b > kMaxTileBits) return false;
+    a.outer_mask = pp.outer_mask;
+    for (int j = 0; j < b; ++j) a.v[j] = pp.v[j];
+    a.b = b;
+    a.inverse = inverse ? 1 : 0;
+    std::vector<int> order = pp.rots;
+    if (inverse) std::reverse(order.begin(), order.end());
+    const int D = (int)order.size();
+    std::vector<uint32_t> xl(D), zl(D);
+    for (int i = 0; i < D; ++i) {
+        bool ok = false;
+        xl[i] = local_coords(pp.v, rot[order[i]].x, &ok);
+        if (!ok) return false;
+        zl[i] = local_zmask(pp.v, rot[order[i]].z);
+    }
+    // split into micro-groups of at most kRegDims local dimensions
+    std::vector<Span> spans;
+    std::vector<std::vector<int>> members;
+    for (int i = 0; i < D; ++i) {
+        uint64_t r = spans.empty() ? xl[i] : spans.back().reduce(xl[i]);
+        if (spans.empty() || (r && spans.back().dim() == kRegDims)) {
+            spans.emplace_back();
+            members.emplace_back();
+            r = xl[i];
+        }
+        if (r) spans.back().add(r);
+        members.back().push_back(i);
+    }
+    if ((int)spans.size() > kMaxMG) return false;
+    const uint32_t full = (uint32_t)((1ull << b) - 1);
+    int ri = 0;
+    for (size_t g = 0; g < spans.size(); ++g) {
+        Span &s = spans[g];
+        // pad with the highest free local unit vectors: pivots stay above the lane bits
+        for (int bit = b - 1; bit >= 0 && s.dim() < kRegDims; --bit) {
+            const uint64_t e = s.reduce(1ull << bit);
+            if (e) s.add(e);
+        }
+        if (s.dim() != kRegDims) return false;
+        MGDesc2 &m = a.mg[g];
+        m.npiv = full & ~(uint32_t)s.pivmask;
+        for (int j = 0; j < kRegs; ++j) {
+            uint64_t u = 0;
+            for (int i = 0; i < kRegDims; ++i)
+                if ((j >> i) & 1) u ^= s.v[i];
+            m.U[j] = (uint32_t)u;
+        }
+        m.rot_begin = ri;
+        m.rot_count = (int)members[g].size();
+        for (int i : members[g]) {
+            const Pauli &p = rot[order[i]];
+            RotDesc2 &d = a.rot[ri++];
+            uint32_t cx = 0;
+            uint64_t chk = 0;
+            for (int q = 0; q < kRegDims; ++q)
+                if ((xl[i] >> s.piv[q]) & 1) {
+                    cx |= 1u << q;
+                    chk ^= s.v[q];
+                }
+            if (chk != xl[i]) return false;
+            d.cx = (uint8_t)cx;
+            d.zl = zl[i];
+            uint32_t ms = 0;
+            for (int j = 0; j < kRegs; ++j)
+                if (popc(m.U[j] & zl[i]) & 1) ms |= 1u << j;
+            d.msign = (uint16_t)ms;
+            const int w = (p.e - popc(p.x & p.z) + 3) & 3;
+            d.flags = (uint8_t)((w & 1) | ((w & 2) ? 2 : 0));
+            d.z = p.z;
+            d.k = order[i];
+        }
+    }
+    a.nmg = (int)spans.size();
+    auto Lmap = [&](uint32_t loc) {
+        uint64_t y = 0;
+        for (int i = 0; i < b; ++i)
+            if ((loc >> i) & 1) y ^= pp.v[i];
+        return y;
+    };
+    for (int j = 0; j < kRegs; ++j) {
+        a.LU_first[j] = Lmap(a.mg[0].U[j]);
+        a.LU_last[j] = Lmap(a.mg[a.nmg - 1].U[j]);
+    }
+    return true;
+}
+
 std::vector<HamPass> plan_hamiltonian(int n, const std::vector<HamGroup> &groups, const TuningResolved &tu)
 {
     const int b = tu.tile_bits, c = tu.low_bits;
@@ -239,7 +337,7 @@ extern "C" cfh_status cfh_plan_dry_run(int n, int dtype, const cfh_pauli *rot, s
         if (st) return st;
         r[i] = Pauli{rot[i].x, rot[i].z, rot[i].e & 3};
     }
-    const TuningResolved tu = resolve_tuning(tuning, n, dtype, false);
+    const TuningResolved tu = resolve_tuning(tuning, n, dtype, kTuneForward);
     int64_t o = 0;
     if (tu.unfused) {
         for (size_t i = 0; i < m; ++i) {

@@ -120,7 +120,9 @@ def test_rotation_errors():
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("tuning", [None, {"unfused": 1}, {"tile_bits": 4, "low_bits": 2},
                                     {"tile_bits": 7, "low_bits": 3, "max_run": 3},
-                                    {"tile_bits": 9, "low_bits": 1, "lookahead": -1}])
+                                    {"tile_bits": 9, "low_bits": 1, "lookahead": -1},
+                                    {"variant": 1}, {"variant": 2, "tile_bits": 10, "low_bits": 2},
+                                    {"variant": 3, "max_run": 5}, {"variant": 2, "lookahead": -1}])
 def test_config0_full_state_vs_oracle(dtype, tuning):
     """n = 10, 50-gate Clifford prefix, 200 JW rotations: Phi = C^dag psi."""
     w = W.config(0)
@@ -130,22 +132,36 @@ def test_config0_full_state_vs_oracle(dtype, tuning):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("n,tb,lb", [(14, 12, 5), (14, 13, 6), (13, 9, 4), (15, 11, 3), (5, 4, 2), (3, 3, 1)])
-def test_ragged_tiles_vs_oracle(dtype, n, tb, lb):
+@pytest.mark.parametrize("variant", [1, 0])
+@pytest.mark.parametrize("n,tb,lb", [(14, 12, 5), (14, 13, 6), (13, 9, 4), (15, 11, 3), (16, 14, 4), (5, 4, 2),
+                                     (3, 3, 1)])
+def test_ragged_tiles_vs_oracle(dtype, variant, n, tb, lb):
     """Several tiles per pass, a single whole-state tile, and tiny states."""
     w = W.make_workload("ragged", n, seed=n, n_prefix=3 * n, n_rot=120 if n >= 4 else 0, n_ham=0)
     if n < 4:
         rng = np.random.default_rng(1)
         w.rot = rng.integers(0, 4, size=(40, n)).astype(np.uint8)
         w.theta = rng.uniform(-3, 3, size=40)
-    psi, *_ = run_workload(w, dtype, {"tile_bits": tb, "low_bits": lb})
+    if dtype == torch.complex128 and tb > 13:
+        pytest.skip("2^14 complex128 amplitudes exceed one workgroup's LDS")
+    psi, *_ = run_workload(w, dtype, {"tile_bits": tb, "low_bits": lb, "variant": variant})
     _, phi_ref = sim.simulate(w)
     assert maxdiff(psi, phi_ref) <= TOL[dtype]
 
 
-def test_fused_equals_unfused_and_inverse_roundtrip():
+def test_plan_rejects_unsupported_tuning():
+    rot = cfh.cfh_pauli_encode(np.array([[1, 3, 1, 0, 0, 0, 0, 0, 0, 0]], np.uint8))
+    for tu, code in [({"variant": 2, "tile_bits": 8}, cfh.CFH_E_UNSUPPORTED), ({"variant": 7}, cfh.CFH_E_INVAL),
+                     ({"block_threads": 512}, cfh.CFH_E_UNSUPPORTED)]:
+        with pytest.raises(cfh.CfhError) as e:
+            hybrid.Plan(10, torch.complex128, rot, tu)
+        assert e.value.code == code
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3])
+def test_fused_equals_unfused_and_inverse_roundtrip(variant):
     w = W.config(3, n=18, n_rot=400, n_ham=10)
-    psi_f, _, rot, _, plan, _, theta = run_workload(w, torch.complex128)
+    psi_f, _, rot, _, plan, _, theta = run_workload(w, torch.complex128, {"variant": variant})
     psi_u, *_ = run_workload(w, torch.complex128, {"unfused": 1})
     assert (psi_f - psi_u).abs().max().item() <= 1e-12
     plan.apply(psi_f, theta, inverse=True)
