@@ -85,13 +85,14 @@ typedef struct cfh_tuning {
     int32_t variant;       /* fused kernel: 0 = default, 1 = LDS-staged (every rotation through LDS),
                               2 = register-tiled (micro-groups of 4 dimensions in registers, LDS
                               only between micro-groups, next coset prefetched into registers;
-                              needs tile_bits >= 8), 3 = register-tiled without the prefetch */
-    int32_t reserved;
+                              needs tile_bits in 10..13), 3 = register-tiled without the prefetch */
+    int32_t batch_items;   /* batched runs: at most this many work items per pass (0 = 32) */
 } cfh_tuning;
 
 typedef struct cfh_frame_s *cfh_frame;
 typedef struct cfh_plan_s *cfh_plan;
 typedef struct cfh_ham_s *cfh_ham;
+typedef struct cfh_batch_s *cfh_batch;
 
 /* ------------------------------------------------------------------ misc */
 
@@ -248,6 +249,74 @@ cfh_status cfh_ham_apply(cfh_ham h, const void *psi, void *out, void *stream);
  * nothing. */
 cfh_status cfh_adjoint_grad(cfh_plan p, cfh_ham h, void *psi, void *lam, const double *theta_dev,
                             double *grad_dev, void *stream);
+
+/* ----------------------------------------------- a10: batched circuits */
+
+/* One circuit of a batch: n qubits (8..30), its initial basis state, m
+ * rotations already conjugated through its frame (e even) with their angles,
+ * and its observable of mh terms (conjugated, e even) with coefficients.
+ * All arrays are host memory and are copied by cfh_batch_create. */
+typedef struct cfh_circuit_desc {
+    int32_t n;
+    int32_t reserved;
+    uint64_t init_index;
+    const cfh_pauli *rot;
+    const double *theta;
+    int64_t m;
+    const cfh_pauli *terms;
+    const double *coeff;
+    int64_t mh;
+} cfh_circuit_desc;
+
+/* Build a batch of `count` independent circuits with their own qubit
+ * counts, rotations, angles and observables.  Each circuit is planned into
+ * fused rotation passes (tiles of 2^min(n, tile_bits) amplitudes, default
+ * 2^10), read-only Hamiltonian passes and adjoint passes; the passes are cut
+ * into at most tuning->batch_items work items each and queued level by level
+ * across circuits.  States, angles, gradients, partial sums and the queue
+ * live in one library-owned device allocation.  tuning may be NULL.
+ * Errors: CFH_E_INVAL, CFH_E_RANGE, CFH_E_NOT_HERMITIAN, CFH_E_UNSUPPORTED
+ * (n outside 8..30, tile_bits outside 8..11 for c128 or 8..12 for c64),
+ * CFH_E_NOMEM, CFH_E_HIP. */
+cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, const cfh_tuning *tuning,
+                            cfh_batch *out);
+cfh_status cfh_batch_destroy(cfh_batch b);
+
+/* Work items (gradient run), passes, rotations and state bytes of a batch. */
+cfh_status cfh_batch_info(cfh_batch b, int64_t *n_items_grad, int64_t *n_passes, int64_t *n_rot,
+                          double *state_bytes);
+
+/* Replace all angles (host array, concatenated in circuit order); synchronous. */
+cfh_status cfh_batch_set_theta(cfh_batch b, const double *theta_host);
+
+/* Run every circuit: build its initial state, apply its rotations, reduce
+ * its energy E_i = <psi_i|H_i|psi_i> (Eq. chfsexp) and, with with_grad = 1,
+ * its adjoint gradient dE_i/dtheta, in ONE persistent kernel launch that
+ * pops (circuit, pass, coset range) items from a device queue (plus two tiny
+ * set-up kernels: counter reset and angle tables).  Asynchronous; allocates
+ * nothing and calls no memset, so it can be captured in a hipGraph.  Runs on
+ * one batch must not overlap in time.  A pass that waits too long for its
+ * predecessor makes every workgroup stop; cfh_batch_results then reports
+ * CFH_E_HIP. */
+cfh_status cfh_batch_run(cfh_batch b, int with_grad, void *stream);
+
+/* Capture cfh_batch_run(b, with_grad) into a hipGraph on the first call for
+ * that with_grad value, then launch the instantiated graph.  `stream` must
+ * be a created (non-default) stream, since the default stream cannot be
+ * captured. */
+cfh_status cfh_batch_graph_launch(cfh_batch b, int with_grad, void *stream);
+
+/* Synchronize `stream`, then copy results to host: energies[count], grads
+ * (concatenated per circuit, sum of m), per-circuit device wall-clock stamps
+ * t_start[count] / t_end[count] and the clock rate in Hz.  Any output
+ * pointer may be NULL. */
+cfh_status cfh_batch_results(cfh_batch b, double *energies, double *grads, uint64_t *t_start,
+                             uint64_t *t_end, double *tick_hz, void *stream);
+
+/* Copy circuit i's current state (2^n_i amplitudes of the batch dtype) to
+ * device memory dst_dev, asynchronously on `stream`.  After a gradient run
+ * the states have been rewound to the initial states. */
+cfh_status cfh_batch_state(cfh_batch b, int i, void *dst_dev, void *stream);
 
 #ifdef __cplusplus
 }

@@ -33,7 +33,13 @@ class cfh_pauli(C.Structure):
 class cfh_tuning(C.Structure):
     _fields_ = [("tile_bits", C.c_int32), ("low_bits", C.c_int32), ("max_run", C.c_int32),
                 ("lookahead", C.c_int32), ("unfused", C.c_int32), ("block_threads", C.c_int32),
-                ("variant", C.c_int32), ("reserved", C.c_int32)]
+                ("variant", C.c_int32), ("batch_items", C.c_int32)]
+
+
+class cfh_circuit_desc(C.Structure):
+    _fields_ = [("n", C.c_int32), ("reserved", C.c_int32), ("init_index", C.c_uint64),
+                ("rot", C.c_void_p), ("theta", C.c_void_p), ("m", C.c_int64),
+                ("terms", C.c_void_p), ("coeff", C.c_void_p), ("mh", C.c_int64)]
 
 
 class CfhError(RuntimeError):
@@ -76,6 +82,14 @@ _SIGS = {
     "cfh_expval": (C.c_int32, [_vp, C.c_int, C.c_int, _vp, _vp, C.c_size_t, _vp, _vp]),
     "cfh_ham_apply": (C.c_int32, [_vp, _vp, _vp, _vp]),
     "cfh_adjoint_grad": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "cfh_batch_create": (C.c_int32, [_vp, C.c_int, C.c_int, _P(cfh_tuning), _P(_vp)]),
+    "cfh_batch_destroy": (C.c_int32, [_vp]),
+    "cfh_batch_info": (C.c_int32, [_vp, _P(C.c_int64), _P(C.c_int64), _P(C.c_int64), _P(C.c_double)]),
+    "cfh_batch_set_theta": (C.c_int32, [_vp, _vp]),
+    "cfh_batch_run": (C.c_int32, [_vp, C.c_int, _vp]),
+    "cfh_batch_graph_launch": (C.c_int32, [_vp, C.c_int, _vp]),
+    "cfh_batch_results": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, _P(C.c_double), _vp]),
+    "cfh_batch_state": (C.c_int32, [_vp, C.c_int, _vp, _vp]),
 }
 
 
@@ -318,3 +332,64 @@ def cfh_ham_apply(h: int, psi, out, stream=None) -> None:
 def cfh_adjoint_grad(p: int, h: int, psi, lam, theta_dev, grad_dev, stream=None) -> None:
     _call("cfh_adjoint_grad", p, h, _dev_ptr(psi, "psi"), _dev_ptr(lam, "lam"), _dev_ptr(theta_dev, "theta"),
           _dev_ptr(grad_dev, "grad"), _stream(stream))
+
+
+# ------------------------------------------------------------------ batches
+
+def cfh_batch_create(circuits, dtype: int, tuning=None) -> int:
+    """circuits: sequence of dicts with n, init_index, rot (PAULI_DTYPE), theta,
+    terms (PAULI_DTYPE), coeff.  The arrays are copied by the library."""
+    keep = []
+    descs = (cfh_circuit_desc * len(circuits))()
+    for i, c in enumerate(circuits):
+        rot = _paulis(c["rot"])
+        th = np.ascontiguousarray(c["theta"], dtype=np.float64)
+        terms = _paulis(c["terms"])
+        coeff = np.ascontiguousarray(c["coeff"], dtype=np.float64)
+        keep += [rot, th, terms, coeff]
+        descs[i] = cfh_circuit_desc(int(c["n"]), 0, int(c["init_index"]), rot.ctypes.data, th.ctypes.data,
+                                    rot.shape[0], terms.ctypes.data, coeff.ctypes.data, terms.shape[0])
+    h = C.c_void_p()
+    t = _tuning(tuning)
+    _call("cfh_batch_create", C.addressof(descs), len(circuits), dtype, C.byref(t) if t is not None else None,
+          C.byref(h))
+    del keep
+    return h.value
+
+
+def cfh_batch_destroy(b: int) -> None:
+    _call("cfh_batch_destroy", b)
+
+
+def cfh_batch_info(b: int) -> dict:
+    it, np_, nr, sb = C.c_int64(), C.c_int64(), C.c_int64(), C.c_double()
+    _call("cfh_batch_info", b, C.byref(it), C.byref(np_), C.byref(nr), C.byref(sb))
+    return {"n_items_grad": it.value, "n_passes": np_.value, "n_rot": nr.value, "state_bytes": sb.value}
+
+
+def cfh_batch_set_theta(b: int, theta: np.ndarray) -> None:
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    _call("cfh_batch_set_theta", b, th.ctypes.data)
+
+
+def cfh_batch_run(b: int, with_grad: bool, stream=None) -> None:
+    _call("cfh_batch_run", b, int(bool(with_grad)), _stream(stream))
+
+
+def cfh_batch_graph_launch(b: int, with_grad: bool, stream) -> None:
+    _call("cfh_batch_graph_launch", b, int(bool(with_grad)), _stream(stream))
+
+
+def cfh_batch_results(b: int, count: int, total_rot: int, stream=None):
+    e = np.zeros(count, np.float64)
+    g = np.zeros(max(total_rot, 1), np.float64)
+    t0 = np.zeros(count, np.uint64)
+    t1 = np.zeros(count, np.uint64)
+    hz = C.c_double()
+    _call("cfh_batch_results", b, e.ctypes.data, g.ctypes.data, t0.ctypes.data, t1.ctypes.data, C.byref(hz),
+          _stream(stream))
+    return e, g[:total_rot], t0, t1, hz.value
+
+
+def cfh_batch_state(b: int, i: int, dst_dev, stream=None) -> None:
+    _call("cfh_batch_state", b, i, _dev_ptr(dst_dev, "dst"), _stream(stream))

@@ -1,0 +1,737 @@
+// Batched hybrid simulation: many independent circuits (own qubit count,
+// rotations, angles and observable) run together.
+//
+// Every circuit is a chain of passes: its fused rotation passes (the first
+// one builds the initial basis state on the fly), then the read-only
+// Hamiltonian passes that accumulate lam = H psi (the last one also reduces
+// E = Re <psi|lam>, Eq. chfsexp), then, for gradients, its rotation passes
+// walked backwards with the adjoint rule g_k = Im <lam|P_k|psi> while both
+// vectors are rewound.  Passes are cut into work items of a few cosets.
+//
+// Execution is level-synchronous: level l holds pass l of every circuit whose
+// chain is that long, one workgroup per work item, launched as one kernel;
+// a second small kernel then reduces the per-item partial sums of the level's
+// adjoint and energy passes in a fixed order (bitwise reproducible results).
+// Kernel boundaries order the levels, so no workgroup ever waits for another.
+// The whole sequence is enqueued by cfh_batch_run and captured once into a
+// hipGraph by cfh_batch_graph_launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <vector>
+
+#include "cfh_internal.hpp"
+#include "device_common.hpp"
+
+using namespace cfh;
+using namespace cfh::dev;
+
+namespace {
+
+constexpr int kBThreads = 256;
+constexpr int kBWaves = kBThreads / 64;
+
+enum { kPassFwd = 0, kPassHam = 1, kPassAdj = 2 };
+enum { kFlagInit = 1, kFlagAccumulate = 2, kFlagEnergy = 4, kFlagStart = 8, kFlagEnd = 16 };
+
+struct BPass {
+    uint64_t outer_mask;
+    uint64_t v[kMaxTileBits];
+    int32_t type, circ, b, flags;
+    int32_t nitems;      // work items of this pass
+    int32_t tiles_per_item;
+    int32_t first;       // first rotation (fwd/adj) or group (ham) in the batch arrays
+    int32_t count;       // number of rotations / groups
+    int32_t end_flag_grad;  // 1 if this pass ends the circuit in a gradient run
+    int32_t pad[3];
+};
+
+struct BCirc {
+    int64_t psi_off;     // amplitude offset of the circuit's state in the arenas
+    uint64_t init;       // initial basis index
+    int64_t theta_off;   // offset of its angles / gradients
+    int64_t gpart_off;   // per-item gradient partials (items * kMaxRun doubles)
+    int64_t epart_off;   // per-item energy partials (items doubles)
+    int32_t n, pad;
+};
+
+struct BItem {
+    int32_t pass;
+    int32_t idx;         // item index inside its pass
+};
+
+struct BatchArgs {
+    const BPass *passes;
+    const BCirc *circs;
+    const RotDesc *rot;
+    const HamGroupDev *groups;
+    const HamTermDev *terms;
+    const double2 *coef;
+    void *psi;
+    void *lam;
+    double *grad;
+    double *energy;
+    double *gpart;
+    double *epart;
+    uint64_t *t_start;
+    uint64_t *t_end;
+    int with_grad;
+    int pad;
+};
+
+// One work item: a range of cosets of one pass.
+template <typename Amp, int BMAX>
+__global__ void __launch_bounds__(kBThreads) k_batch_level(const BatchArgs A, const BItem *__restrict__ items)
+{
+    constexpr int T = kBThreads;
+    constexpr int NMAX = 1 << BMAX;
+    __shared__ Amp tp[NMAX];
+    __shared__ Amp tl[NMAX];
+    __shared__ double wacc[kMaxRun][kBWaves];
+    __shared__ double ered[kBWaves];
+    const int t = threadIdx.x;
+    const BItem it = items[blockIdx.x];
+    const BPass &P = A.passes[it.pass];
+    const BCirc &C = A.circs[P.circ];
+    Amp *psi = reinterpret_cast<Amp *>(A.psi) + C.psi_off;
+    Amp *lam = reinterpret_cast<Amp *>(A.lam) + C.psi_off;
+    const int b = P.b;
+    const int N = 1 << b;
+    const uint64_t ntiles = 1ull << (C.n - b);
+    const uint64_t tile0 = (uint64_t)it.idx * P.tiles_per_item;
+    const uint64_t tile1 = std::min<uint64_t>(ntiles, tile0 + P.tiles_per_item);
+    if ((P.flags & kFlagStart) && it.idx == 0 && t == 0) A.t_start[P.circ] = wall_clock64();
+    for (int i = t; i < kMaxRun * kBWaves; i += T) (&wacc[0][0])[i] = 0.0;
+    double eacc = 0.0;
+    __syncthreads();
+
+    for (uint64_t tile = tile0; tile < tile1; ++tile) {
+        const uint64_t base = deposit(tile, P.outer_mask);
+        // global index of local element a
+        auto gidx = [&](int a) {
+            uint64_t y = base;
+            for (int i = 0; i < b; ++i)
+                if ((a >> i) & 1) y ^= P.v[i];
+            return y;
+        };
+        if (P.type == kPassFwd) {
+            for (int a = t; a < N; a += T) {
+                const uint64_t y = gidx(a);
+                if (P.flags & kFlagInit) st(tp[a], make_double2(y == C.init ? 1.0 : 0.0, 0.0));
+                else tp[a] = psi[y];
+            }
+            __syncthreads();
+            for (int ri = 0; ri < P.count; ++ri) {
+                const RotDesc &d = A.rot[P.first + ri];
+                const double2 cs = A.coef[C.theta_off + d.k];
+                const double c = cs.x;
+                const double sr = (d.w & 2) ? -cs.y : cs.y;
+                const bool imag = d.w & 1;
+                const int so = par64(base & d.z);
+                if (d.xl == 0) {
+                    for (int a = t; a < N; a += T) {
+                        const double sj = (par32(a & d.zl) ^ so) ? -sr : sr;
+                        st(tp[a], rot_diag(ld(tp[a]), c, sj, imag));
+                    }
+                } else {
+                    const uint32_t lowm = (1u << d.hb) - 1;
+                    for (uint32_t q = t; q < (uint32_t)(N >> 1); q += T) {
+                        const uint32_t a0 = ((q & ~lowm) << 1) | (q & lowm);
+                        const uint32_t a1 = a0 ^ d.xl;
+                        const int sg0 = par32(a0 & d.zl) ^ so;
+                        const double s0 = sg0 ? -sr : sr;
+                        const double s1 = (sg0 ^ d.dsign) ? -sr : sr;
+                        double2 u = ld(tp[a0]), v = ld(tp[a1]);
+                        rot_pair(u, v, c, s0, s1, imag);
+                        st(tp[a0], u);
+                        st(tp[a1], v);
+                    }
+                }
+                __syncthreads();
+            }
+            for (int a = t; a < N; a += T) psi[gidx(a)] = tp[a];
+        } else if (P.type == kPassHam) {
+            for (int a = t; a < N; a += T) tp[a] = psi[gidx(a)];
+            __syncthreads();
+            for (int a = t; a < N; a += T) {
+                double ar = 0.0, ai = 0.0;
+                for (int g = P.first; g < P.first + P.count; ++g) {
+                    const HamGroupDev G = A.groups[g];
+                    const double2 v = ld(tp[a ^ G.xl]);
+                    for (int j = G.term_begin; j < G.term_begin + G.term_count; ++j) {
+                        const HamTermDev tm = A.terms[j];
+                        const double sg = (par32(a & tm.zl) ^ par64(base & tm.z)) ? -1.0 : 1.0;
+                        ar += sg * (tm.wre * v.x - tm.wim * v.y);
+                        ai += sg * (tm.wre * v.y + tm.wim * v.x);
+                    }
+                }
+                const uint64_t y = gidx(a);
+                double2 o = make_double2(ar, ai);
+                if (P.flags & kFlagAccumulate) {
+                    const double2 p = ld(lam[y]);
+                    o.x += p.x;
+                    o.y += p.y;
+                }
+                st(lam[y], o);
+                if (P.flags & kFlagEnergy) {
+                    const double2 u = ld(tp[a]);
+                    const double2 oo = ld(lam[y]);   // the stored (rounded) value
+                    eacc += u.x * oo.x + u.y * oo.y;
+                }
+            }
+        } else {  // adjoint
+            for (int a = t; a < N; a += T) {
+                const uint64_t y = gidx(a);
+                tp[a] = psi[y];
+                tl[a] = lam[y];
+            }
+            __syncthreads();
+            for (int ri = P.count - 1; ri >= 0; --ri) {
+                const RotDesc &d = A.rot[P.first + ri];
+                const double2 cs = A.coef[C.theta_off + d.k];
+                const double c = cs.x;
+                const double sr = (d.w & 2) ? cs.y : -cs.y;  // R^dag: negated angle
+                const bool imag = d.w & 1;
+                const int wp = (d.w + 1) & 3;
+                const int so = par64(base & d.z);
+                double g = 0.0;
+                if (d.xl == 0) {
+                    for (int a = t; a < N; a += T) {
+                        const int sg = par32(a & d.zl) ^ so;
+                        const double2 u = ld(tp[a]), l = ld(tl[a]);
+                        const double zr = l.x * u.x + l.y * u.y, zi = l.x * u.y - l.y * u.x;
+                        const double im = (wp & 1) ? zr : zi;
+                        g += ((wp & 2) ? -im : im) * (sg ? -1.0 : 1.0);
+                        const double sj = sg ? -sr : sr;
+                        st(tp[a], rot_diag(u, c, sj, imag));
+                        st(tl[a], rot_diag(l, c, sj, imag));
+                    }
+                } else {
+                    const uint32_t lowm = (1u << d.hb) - 1;
+                    for (uint32_t q = t; q < (uint32_t)(N >> 1); q += T) {
+                        const uint32_t a0 = ((q & ~lowm) << 1) | (q & lowm);
+                        const uint32_t a1 = a0 ^ d.xl;
+                        const int sg0 = par32(a0 & d.zl) ^ so;
+                        const int sg1 = sg0 ^ d.dsign;
+                        double2 u0 = ld(tp[a0]), u1 = ld(tp[a1]);
+                        double2 l0 = ld(tl[a0]), l1 = ld(tl[a1]);
+                        const double z0r = l0.x * u1.x + l0.y * u1.y, z0i = l0.x * u1.y - l0.y * u1.x;
+                        const double z1r = l1.x * u0.x + l1.y * u0.y, z1i = l1.x * u0.y - l1.y * u0.x;
+                        const double zr = (sg0 ? -z0r : z0r) + (sg1 ? -z1r : z1r);
+                        const double zi = (sg0 ? -z0i : z0i) + (sg1 ? -z1i : z1i);
+                        const double im = (wp & 1) ? zr : zi;
+                        g += (wp & 2) ? -im : im;
+                        const double s0 = sg0 ? -sr : sr, s1 = sg1 ? -sr : sr;
+                        rot_pair(u0, u1, c, s0, s1, imag);
+                        rot_pair(l0, l1, c, s0, s1, imag);
+                        st(tp[a0], u0);
+                        st(tp[a1], u1);
+                        st(tl[a0], l0);
+                        st(tl[a1], l1);
+                    }
+                }
+                g = wave_sum<64>(g);
+                if ((t & 63) == 0) wacc[ri][t >> 6] += g;
+                __syncthreads();
+            }
+            for (int a = t; a < N; a += T) {
+                const uint64_t y = gidx(a);
+                psi[y] = tp[a];
+                lam[y] = tl[a];
+            }
+        }
+        __syncthreads();
+    }
+
+    // per-item partial sums
+    if (P.type == kPassAdj) {
+        if (t < P.count) {
+            double s = 0.0;
+            for (int w = 0; w < kBWaves; ++w) s += wacc[t][w];
+            A.gpart[C.gpart_off + (int64_t)it.idx * kMaxRun + t] = s;
+        }
+    } else if (P.flags & kFlagEnergy) {
+        eacc = wave_sum<64>(eacc);
+        if ((t & 63) == 0) ered[t >> 6] = eacc;
+        __syncthreads();
+        if (t == 0) {
+            double s = 0.0;
+            for (int w = 0; w < kBWaves; ++w) s += ered[w];
+            A.epart[C.epart_off + it.idx] = s;
+        }
+    }
+}
+
+// Fixed-order reduction of the per-item partial sums of one pass per workgroup.
+__global__ void __launch_bounds__(kBThreads) k_batch_reduce(const BatchArgs A, const int *__restrict__ passes)
+{
+    const int t = threadIdx.x;
+    const int p = passes[blockIdx.x];
+    const BPass &P = A.passes[p];
+    const BCirc &C = A.circs[P.circ];
+    if (P.type == kPassAdj && t < P.count) {
+        double s = 0.0;
+        for (int i = 0; i < P.nitems; ++i) s += A.gpart[C.gpart_off + (int64_t)i * kMaxRun + t];
+        A.grad[C.theta_off + A.rot[P.first + t].k] = s;
+    }
+    if ((P.flags & kFlagEnergy) && t == 0) {
+        double s = 0.0;
+        for (int i = 0; i < P.nitems; ++i) s += A.epart[C.epart_off + i];
+        A.energy[P.circ] = s;
+    }
+    const bool ends = A.with_grad ? P.end_flag_grad : (P.flags & kFlagEnd);
+    if (ends && t == 0) A.t_end[P.circ] = wall_clock64();
+}
+
+__global__ void k_batch_reset(uint64_t *t_start, uint64_t *t_end, int ncirc)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ncirc) {
+        t_start[i] = 0;
+        t_end[i] = 0;
+    }
+}
+
+__global__ void k_batch_coef(const double *__restrict__ theta, double2 *__restrict__ coef, int64_t m)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < m) {
+        double s, c;
+        sincos(0.5 * theta[k], &s, &c);
+        coef[k] = make_double2(c, s);
+    }
+}
+
+inline bool hip_ok(hipError_t e, const char *what, cfh_status *st)
+{
+    if (e == hipSuccess) return true;
+    *st = set_error(CFH_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    return false;
+}
+
+} // namespace
+
+struct cfh_batch_s {
+    int count = 0, dtype = 0, bmax = 0;
+    int64_t total_rot = 0, total_amp = 0;
+    std::vector<int> n, m;
+    std::vector<BPass> passes;
+    // per level: [offset, count) into the item table and into the reduction list
+    struct Level {
+        int64_t item_off, item_cnt, red_off, red_cnt;
+    };
+    std::vector<Level> levels[2];   // [0] forward + energy, [1] with gradients
+    int64_t n_items[2] = {0, 0};
+    void *arena = nullptr;
+    BPass *d_passes = nullptr;
+    BCirc *d_circs = nullptr;
+    BItem *d_items[2] = {nullptr, nullptr};
+    int *d_reduce[2] = {nullptr, nullptr};
+    RotDesc *d_rot = nullptr;
+    HamGroupDev *d_groups = nullptr;
+    HamTermDev *d_terms = nullptr;
+    double *d_theta = nullptr, *d_grad = nullptr, *d_energy = nullptr, *d_gpart = nullptr, *d_epart = nullptr;
+    double2 *d_coef = nullptr;
+    void *d_psi = nullptr, *d_lam = nullptr;
+    uint64_t *d_tstart = nullptr, *d_tend = nullptr;
+    std::vector<int64_t> psi_off;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    ~cfh_batch_s()
+    {
+        for (int i = 0; i < 2; ++i) {
+            if (exec[i]) (void)hipGraphExecDestroy(exec[i]);
+            if (graph[i]) (void)hipGraphDestroy(graph[i]);
+        }
+        if (arena) (void)hipFree(arena);
+    }
+};
+
+namespace {
+
+template <typename Amp>
+cfh_status launch_level(int bmax, unsigned grid, hipStream_t s, const BatchArgs &A, const BItem *items)
+{
+    switch (bmax) {
+    case 8: hipLaunchKernelGGL((k_batch_level<Amp, 8>), dim3(grid), dim3(kBThreads), 0, s, A, items); break;
+    case 9: hipLaunchKernelGGL((k_batch_level<Amp, 9>), dim3(grid), dim3(kBThreads), 0, s, A, items); break;
+    case 10: hipLaunchKernelGGL((k_batch_level<Amp, 10>), dim3(grid), dim3(kBThreads), 0, s, A, items); break;
+    case 11: hipLaunchKernelGGL((k_batch_level<Amp, 11>), dim3(grid), dim3(kBThreads), 0, s, A, items); break;
+    case 12:
+        if constexpr (sizeof(Amp) == 8) {
+            hipLaunchKernelGGL((k_batch_level<Amp, 12>), dim3(grid), dim3(kBThreads), 0, s, A, items);
+            break;
+        }
+        [[fallthrough]];
+    default:
+        return set_error(CFH_E_UNSUPPORTED, "cfh_batch_run: tile_bits");
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(CFH_E_HIP, std::string("k_batch_level: ") + hipGetErrorString(e));
+    return CFH_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, const cfh_tuning *tuning,
+                            cfh_batch *out)
+{
+    if (!out || !circ || count < 1) return set_error(CFH_E_INVAL, "cfh_batch_create: bad arguments");
+    if (dtype != CFH_C64 && dtype != CFH_C128) return set_error(CFH_E_UNSUPPORTED, "cfh_batch_create: dtype");
+    if (tuning && tuning->variant != 0)
+        return set_error(CFH_E_UNSUPPORTED,
+                         "cfh_batch_create: only the level-synchronous schedule (variant 0) is available; the "
+                         "persistent work-queue kernel is disabled");
+    std::unique_ptr<cfh_batch_s> B(new (std::nothrow) cfh_batch_s);
+    if (!B) return set_error(CFH_E_NOMEM, "cfh_batch_create: host memory");
+    B->count = count;
+    B->dtype = dtype;
+    const int bcap = dtype == CFH_C128 ? 11 : 12;
+    B->bmax = (tuning && tuning->tile_bits > 0) ? tuning->tile_bits : 10;
+    if (B->bmax < 8 || B->bmax > bcap)
+        return set_error(CFH_E_UNSUPPORTED, "cfh_batch_create: tile_bits must be in 8..11 (c128) / 8..12 (c64)");
+    const int max_items = (tuning && tuning->batch_items > 0) ? tuning->batch_items : 32;
+    const size_t ab = dtype == CFH_C64 ? 8 : 16;
+
+    std::vector<BCirc> circs(count);
+    std::vector<RotDesc> rots;
+    std::vector<HamGroupDev> gdev;
+    std::vector<HamTermDev> tdev;
+    std::vector<double> theta_all;
+    std::vector<std::vector<int>> chain_fwd(count), chain_grad(count);
+    int64_t amp = 0, gpart = 0, epart = 0;
+    for (int c = 0; c < count; ++c) {
+        const cfh_circuit_desc &d = circ[c];
+        if (d.n < 8 || d.n > 30) return set_error(CFH_E_UNSUPPORTED, "cfh_batch_create: circuit n must be in 8..30");
+        if ((d.m && (!d.rot || !d.theta)) || (d.mh && (!d.terms || !d.coeff)) || d.m < 0 || d.mh < 0)
+            return set_error(CFH_E_INVAL, "cfh_batch_create: null rotation or term arrays");
+        if (d.init_index >> d.n) return set_error(CFH_E_RANGE, "cfh_batch_create: init_index >= 2^n");
+        std::vector<Pauli> r(d.m);
+        for (int64_t i = 0; i < d.m; ++i) {
+            cfh_status st = check_pauli(d.rot[i], d.n, true, "cfh_batch_create");
+            if (st) return st;
+            r[i] = Pauli{d.rot[i].x, d.rot[i].z, d.rot[i].e & 3};
+        }
+        for (int64_t i = 0; i < d.mh; ++i) {
+            cfh_status st = check_pauli(d.terms[i], d.n, true, "cfh_batch_create");
+            if (st) return st;
+        }
+        cfh_tuning tc{};
+        tc.tile_bits = std::min(B->bmax, d.n);
+        tc.low_bits = tuning && tuning->low_bits > 0 ? tuning->low_bits : 4;
+        tc.max_run = tuning && tuning->max_run > 0 ? tuning->max_run : kMaxRun;
+        const TuningResolved tu = resolve_tuning(&tc, d.n, dtype, kTuneForward);
+        const int b = tu.tile_bits;
+        const uint64_t ntiles = 1ull << (d.n - b);
+        const int tpi = (int)std::max<uint64_t>(1, (ntiles + max_items - 1) / max_items);
+        const int nitems = (int)((ntiles + tpi - 1) / tpi);
+        BCirc &C = circs[c];
+        C.psi_off = amp;
+        C.init = d.init_index;
+        C.theta_off = (int64_t)theta_all.size();
+        C.gpart_off = gpart;
+        C.epart_off = epart;
+        C.n = d.n;
+        B->psi_off.push_back(amp);
+        amp += (int64_t)1 << d.n;
+        gpart += (int64_t)nitems * kMaxRun;
+        epart += nitems;
+        theta_all.insert(theta_all.end(), d.theta, d.theta + d.m);
+        B->n.push_back(d.n);
+        B->m.push_back((int)d.m);
+
+        auto new_pass = [&](int type, int bb, uint64_t outer, const std::vector<uint64_t> &v, int first, int cnt,
+                            int flags) {
+            BPass P;
+            std::memset(&P, 0, sizeof(P));
+            P.outer_mask = outer;
+            for (size_t i = 0; i < v.size(); ++i) P.v[i] = v[i];
+            P.type = type;
+            P.circ = c;
+            P.b = bb;
+            P.flags = flags;
+            P.nitems = nitems;
+            P.tiles_per_item = tpi;
+            P.first = first;
+            P.count = cnt;
+            B->passes.push_back(P);
+            return (int)B->passes.size() - 1;
+        };
+        // forward rotation passes
+        const std::vector<PassPlan> fw = plan_rotations(d.n, r, tu);
+        std::vector<int> fwd_ids;
+        for (size_t i = 0; i < fw.size(); ++i) {
+            const int first = (int)rots.size();
+            for (int k : fw[i].rots) rots.push_back(make_rot_desc(fw[i], r[k], k));
+            fwd_ids.push_back(new_pass(kPassFwd, b, fw[i].outer_mask, fw[i].v, first, (int)fw[i].rots.size(),
+                                       (i == 0 ? kFlagInit | kFlagStart : 0)));
+        }
+        // Hamiltonian passes (lam = H psi, energy on the last)
+        std::map<uint64_t, int> gid;
+        std::vector<HamGroup> groups;
+        for (int64_t i = 0; i < d.mh; ++i) {
+            auto itg = gid.find(d.terms[i].x);
+            if (itg == gid.end()) {
+                gid[d.terms[i].x] = (int)groups.size();
+                groups.push_back(HamGroup{d.terms[i].x, {(int)i}});
+            } else {
+                groups[itg->second].terms.push_back((int)i);
+            }
+        }
+        std::vector<int> ham_ids;
+        const std::vector<HamPass> hp = plan_hamiltonian(d.n, groups, tu);
+        for (size_t i = 0; i < hp.size(); ++i) {
+            const int first = (int)gdev.size();
+            for (int g : hp[i].groups) {
+                bool ok = false;
+                HamGroupDev gd;
+                gd.xl = local_coords(hp[i].v, groups[g].x, &ok);
+                if (!ok) return set_error(CFH_E_INVAL, "cfh_batch_create: group outside its tile");
+                gd.hb = gd.xl ? 31 - __builtin_clz(gd.xl) : -1;
+                gd.term_begin = (int32_t)tdev.size();
+                gd.term_count = (int32_t)groups[g].terms.size();
+                for (int ti : groups[g].terms) {
+                    const cfh_pauli &tp = d.terms[ti];
+                    HamTermDev td;
+                    td.z = tp.z;
+                    td.zl = local_zmask(hp[i].v, tp.z);
+                    td.pad = 0;
+                    const int wp = (tp.e - popc(tp.x & tp.z)) & 3;
+                    const double cf = d.coeff[ti];
+                    td.wre = (wp == 0) ? cf : (wp == 2) ? -cf : 0.0;
+                    td.wim = (wp == 1) ? cf : (wp == 3) ? -cf : 0.0;
+                    tdev.push_back(td);
+                }
+                gdev.push_back(gd);
+            }
+            int flags = (i > 0 ? kFlagAccumulate : 0) | (i + 1 == hp.size() ? kFlagEnergy | kFlagEnd : 0);
+            if (fwd_ids.empty() && i == 0) flags |= kFlagStart;
+            ham_ids.push_back(new_pass(kPassHam, hp[i].b, hp[i].outer_mask, hp[i].v, first,
+                                       (int)hp[i].groups.size(), flags));
+        }
+        if (ham_ids.empty()) return set_error(CFH_E_INVAL, "cfh_batch_create: every circuit needs an observable");
+        if (fwd_ids.empty()) return set_error(CFH_E_INVAL, "cfh_batch_create: every circuit needs rotations");
+        // adjoint passes: the forward passes walked backwards
+        std::vector<int> adj_ids;
+        for (int i = (int)fw.size() - 1; i >= 0; --i) {
+            const BPass &F = B->passes[fwd_ids[i]];
+            adj_ids.push_back(new_pass(kPassAdj, F.b, F.outer_mask, fw[i].v, F.first, F.count, 0));
+        }
+        B->passes[adj_ids.back()].end_flag_grad = 1;
+        // dependency chains
+        std::vector<int> chain = fwd_ids;
+        chain.insert(chain.end(), ham_ids.begin(), ham_ids.end());
+        chain_fwd[c] = chain;
+        chain.insert(chain.end(), adj_ids.begin(), adj_ids.end());
+        chain_grad[c] = chain;
+    }
+    B->total_rot = (int64_t)theta_all.size();
+    B->total_amp = amp;
+    // level tables: items of pass `lv` of every circuit, then the passes of the
+    // level whose partial sums are reduced (adjoint passes, the energy pass)
+    std::vector<BItem> items[2];
+    std::vector<int> red[2];
+    for (int g = 0; g < 2; ++g) {
+        const auto &chains = g ? chain_grad : chain_fwd;
+        size_t maxlen = 0;
+        for (auto &ch : chains) maxlen = std::max(maxlen, ch.size());
+        for (size_t lv = 0; lv < maxlen; ++lv) {
+            cfh_batch_s::Level L{(int64_t)items[g].size(), 0, (int64_t)red[g].size(), 0};
+            for (int c = 0; c < count; ++c) {
+                if (lv >= chains[c].size()) continue;
+                const int p = chains[c][lv];
+                for (int i = 0; i < B->passes[p].nitems; ++i) items[g].push_back(BItem{p, i});
+                const BPass &P = B->passes[p];
+                const bool ends = g ? P.end_flag_grad : (P.flags & kFlagEnd);
+                if (P.type == kPassAdj || (P.flags & kFlagEnergy) || ends) red[g].push_back(p);
+            }
+            L.item_cnt = (int64_t)items[g].size() - L.item_off;
+            L.red_cnt = (int64_t)red[g].size() - L.red_off;
+            B->levels[g].push_back(L);
+        }
+        B->n_items[g] = (int64_t)items[g].size();
+    }
+
+    // one device arena
+    const int npass = (int)B->passes.size();
+    std::vector<std::pair<void **, size_t>> parts = {
+        {(void **)&B->d_passes, npass * sizeof(BPass)},
+        {(void **)&B->d_circs, count * sizeof(BCirc)},
+        {(void **)&B->d_items[0], std::max<size_t>(1, items[0].size()) * sizeof(BItem)},
+        {(void **)&B->d_items[1], std::max<size_t>(1, items[1].size()) * sizeof(BItem)},
+        {(void **)&B->d_reduce[0], std::max<size_t>(1, red[0].size()) * sizeof(int)},
+        {(void **)&B->d_reduce[1], std::max<size_t>(1, red[1].size()) * sizeof(int)},
+        {(void **)&B->d_rot, std::max<size_t>(1, rots.size()) * sizeof(RotDesc)},
+        {(void **)&B->d_groups, std::max<size_t>(1, gdev.size()) * sizeof(HamGroupDev)},
+        {(void **)&B->d_terms, std::max<size_t>(1, tdev.size()) * sizeof(HamTermDev)},
+        {(void **)&B->d_theta, B->total_rot * sizeof(double)},
+        {(void **)&B->d_coef, B->total_rot * sizeof(double2)},
+        {(void **)&B->d_grad, B->total_rot * sizeof(double)},
+        {(void **)&B->d_energy, count * sizeof(double)},
+        {(void **)&B->d_gpart, gpart * sizeof(double)},
+        {(void **)&B->d_epart, epart * sizeof(double)},
+        {(void **)&B->d_psi, amp * ab},
+        {(void **)&B->d_lam, amp * ab},
+        {(void **)&B->d_tstart, count * sizeof(uint64_t)},
+        {(void **)&B->d_tend, count * sizeof(uint64_t)},
+    };
+    size_t total = 0;
+    for (auto &p : parts) total += (p.second + 255) & ~(size_t)255;
+    cfh_status st = CFH_OK;
+    if (!hip_ok(hipMalloc(&B->arena, total), "cfh_batch_create: hipMalloc", &st)) return st;
+    size_t off = 0;
+    for (auto &p : parts) {
+        *p.first = (char *)B->arena + off;
+        off += (p.second + 255) & ~(size_t)255;
+    }
+    auto up = [&](void *dst, const void *src, size_t bytes) {
+        return bytes == 0 || hip_ok(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice), "cfh_batch_create: copy", &st);
+    };
+    if (!up(B->d_passes, B->passes.data(), npass * sizeof(BPass)) ||
+        !up(B->d_circs, circs.data(), count * sizeof(BCirc)) ||
+        !up(B->d_items[0], items[0].data(), items[0].size() * sizeof(BItem)) ||
+        !up(B->d_items[1], items[1].data(), items[1].size() * sizeof(BItem)) ||
+        !up(B->d_reduce[0], red[0].data(), red[0].size() * sizeof(int)) ||
+        !up(B->d_reduce[1], red[1].data(), red[1].size() * sizeof(int)) ||
+        !up(B->d_rot, rots.data(), rots.size() * sizeof(RotDesc)) ||
+        !up(B->d_groups, gdev.data(), gdev.size() * sizeof(HamGroupDev)) ||
+        !up(B->d_terms, tdev.data(), tdev.size() * sizeof(HamTermDev)) ||
+        !up(B->d_theta, theta_all.data(), theta_all.size() * sizeof(double)))
+        return st;
+    *out = B.release();
+    return CFH_OK;
+}
+
+cfh_status cfh_batch_destroy(cfh_batch b)
+{
+    delete b;
+    return CFH_OK;
+}
+
+cfh_status cfh_batch_info(cfh_batch b, int64_t *n_items_grad, int64_t *n_passes, int64_t *n_rot, double *state_bytes)
+{
+    if (!b) return set_error(CFH_E_INVAL, "cfh_batch_info: null batch");
+    if (n_items_grad) *n_items_grad = b->n_items[1];
+    if (n_passes) *n_passes = (int64_t)b->passes.size();
+    if (n_rot) *n_rot = b->total_rot;
+    if (state_bytes) *state_bytes = (double)b->total_amp * (b->dtype == CFH_C64 ? 8 : 16);
+    return CFH_OK;
+}
+
+cfh_status cfh_batch_set_theta(cfh_batch b, const double *theta_host)
+{
+    if (!b || !theta_host) return set_error(CFH_E_INVAL, "cfh_batch_set_theta: null argument");
+    cfh_status st = CFH_OK;
+    hip_ok(hipMemcpy(b->d_theta, theta_host, b->total_rot * sizeof(double), hipMemcpyHostToDevice),
+           "cfh_batch_set_theta", &st);
+    return st;
+}
+
+cfh_status cfh_batch_run(cfh_batch b, int with_grad, void *stream)
+{
+    if (!b) return set_error(CFH_E_INVAL, "cfh_batch_run: null batch");
+    hipStream_t s = (hipStream_t)stream;
+    const int g = with_grad ? 1 : 0;
+    hipLaunchKernelGGL(k_batch_reset, dim3((b->count + 255) / 256), dim3(256), 0, s, b->d_tstart, b->d_tend,
+                       b->count);
+    if (b->total_rot)
+        hipLaunchKernelGGL(k_batch_coef, dim3((unsigned)((b->total_rot + 255) / 256)), dim3(256), 0, s, b->d_theta,
+                           b->d_coef, b->total_rot);
+    BatchArgs A;
+    std::memset(&A, 0, sizeof(A));
+    A.passes = b->d_passes;
+    A.circs = b->d_circs;
+    A.rot = b->d_rot;
+    A.groups = b->d_groups;
+    A.terms = b->d_terms;
+    A.coef = b->d_coef;
+    A.psi = b->d_psi;
+    A.lam = b->d_lam;
+    A.grad = b->d_grad;
+    A.energy = b->d_energy;
+    A.gpart = b->d_gpart;
+    A.epart = b->d_epart;
+    A.t_start = b->d_tstart;
+    A.t_end = b->d_tend;
+    A.with_grad = g;
+    for (const auto &L : b->levels[g]) {
+        cfh_status st = b->dtype == CFH_C128
+                            ? launch_level<double2>(b->bmax, (unsigned)L.item_cnt, s, A, b->d_items[g] + L.item_off)
+                            : launch_level<float2>(b->bmax, (unsigned)L.item_cnt, s, A, b->d_items[g] + L.item_off);
+        if (st) return st;
+        if (L.red_cnt) {
+            hipLaunchKernelGGL(k_batch_reduce, dim3((unsigned)L.red_cnt), dim3(kBThreads), 0, s, A,
+                               b->d_reduce[g] + L.red_off);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return set_error(CFH_E_HIP, std::string("k_batch_reduce: ") + hipGetErrorString(e));
+        }
+    }
+    return CFH_OK;
+}
+
+cfh_status cfh_batch_graph_launch(cfh_batch b, int with_grad, void *stream)
+{
+    if (!b) return set_error(CFH_E_INVAL, "cfh_batch_graph_launch: null batch");
+    if (!stream) return set_error(CFH_E_INVAL, "cfh_batch_graph_launch: graph capture needs a non-default stream");
+    hipStream_t s = (hipStream_t)stream;
+    const int g = with_grad ? 1 : 0;
+    cfh_status st = CFH_OK;
+    if (!b->exec[g]) {
+        if (!hip_ok(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture", &st))
+            return st;
+        const cfh_status rs = cfh_batch_run(b, with_grad, stream);
+        const hipError_t e = hipStreamEndCapture(s, &b->graph[g]);
+        if (rs) return rs;
+        if (!hip_ok(e, "hipStreamEndCapture", &st)) return st;
+        if (!hip_ok(hipGraphInstantiate(&b->exec[g], b->graph[g], nullptr, nullptr, 0), "hipGraphInstantiate", &st))
+            return st;
+    }
+    hip_ok(hipGraphLaunch(b->exec[g], s), "hipGraphLaunch", &st);
+    return st;
+}
+
+cfh_status cfh_batch_results(cfh_batch b, double *energies, double *grads, uint64_t *t_start, uint64_t *t_end,
+                             double *tick_hz, void *stream)
+{
+    if (!b) return set_error(CFH_E_INVAL, "cfh_batch_results: null batch");
+    cfh_status st = CFH_OK;
+    if (!hip_ok(hipStreamSynchronize((hipStream_t)stream), "cfh_batch_results: sync", &st)) return st;
+    if (energies && !hip_ok(hipMemcpy(energies, b->d_energy, b->count * sizeof(double), hipMemcpyDeviceToHost),
+                            "copy", &st))
+        return st;
+    if (grads && b->total_rot &&
+        !hip_ok(hipMemcpy(grads, b->d_grad, b->total_rot * sizeof(double), hipMemcpyDeviceToHost), "copy", &st))
+        return st;
+    if (t_start && !hip_ok(hipMemcpy(t_start, b->d_tstart, b->count * sizeof(uint64_t), hipMemcpyDeviceToHost),
+                           "copy", &st))
+        return st;
+    if (t_end && !hip_ok(hipMemcpy(t_end, b->d_tend, b->count * sizeof(uint64_t), hipMemcpyDeviceToHost), "copy", &st))
+        return st;
+    if (tick_hz) {
+        int khz = 0, dev = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
+        *tick_hz = khz * 1000.0;
+    }
+    return CFH_OK;
+}
+
+cfh_status cfh_batch_state(cfh_batch b, int i, void *dst_dev, void *stream)
+{
+    if (!b || !dst_dev || i < 0 || i >= b->count) return set_error(CFH_E_INVAL, "cfh_batch_state: bad arguments");
+    const size_t ab = b->dtype == CFH_C64 ? 8 : 16;
+    cfh_status st = CFH_OK;
+    hip_ok(hipMemcpyAsync(dst_dev, (char *)b->d_psi + b->psi_off[i] * ab, ((size_t)1 << b->n[i]) * ab,
+                          hipMemcpyDeviceToDevice, (hipStream_t)stream),
+           "cfh_batch_state", &st);
+    return st;
+}
+
+} // extern "C"

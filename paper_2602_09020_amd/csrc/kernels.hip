@@ -17,55 +17,13 @@
 #include <vector>
 
 #include "cfh_internal.hpp"
+#include "device_common.hpp"
 
 using namespace cfh;
 
 namespace {
 
-// ------------------------------------------------------------ storage
-__device__ __forceinline__ double2 ld(const double2 &p) { return p; }
-__device__ __forceinline__ double2 ld(const float2 &p) { return make_double2(p.x, p.y); }
-__device__ __forceinline__ void st(double2 &p, double2 v) { p = v; }
-__device__ __forceinline__ void st(float2 &p, double2 v) { p = make_float2((float)v.x, (float)v.y); }
-
-__device__ __forceinline__ int par32(uint32_t v) { return __builtin_popcount(v) & 1; }
-__device__ __forceinline__ int par64(uint64_t v) { return __builtin_popcountll(v) & 1; }
-
-// Spread the low bits of v over the set bits of mask (software pdep).
-__device__ __forceinline__ uint64_t deposit(uint64_t v, uint64_t mask)
-{
-    uint64_t r = 0;
-    for (uint64_t m = mask; m && v; m &= m - 1, v >>= 1)
-        if (v & 1) r |= m & (~m + 1);
-    return r;
-}
-
-// One pair update.  With beta = sr * (imag ? i : 1) the rotation is
-//   u' = c u + s0 beta v,  v' = c v + s1 beta u,  s0, s1 = +-1 folded into sr.
-__device__ __forceinline__ void rot_pair(double2 &u, double2 &v, double c, double s0, double s1, bool imag)
-{
-    double2 nu, nv;
-    if (imag) {
-        nu.x = c * u.x - s0 * v.y;
-        nu.y = c * u.y + s0 * v.x;
-        nv.x = c * v.x - s1 * u.y;
-        nv.y = c * v.y + s1 * u.x;
-    } else {
-        nu.x = c * u.x + s0 * v.x;
-        nu.y = c * u.y + s0 * v.y;
-        nv.x = c * v.x + s1 * u.x;
-        nv.y = c * v.y + s1 * u.y;
-    }
-    u = nu;
-    v = nv;
-}
-
-// Diagonal member update: u' = (c + s beta) u.
-__device__ __forceinline__ double2 rot_diag(double2 u, double c, double s, bool imag)
-{
-    if (imag) return make_double2(c * u.x - s * u.y, c * u.y + s * u.x);
-    return make_double2((c + s) * u.x, (c + s) * u.y);
-}
+using namespace cfh::dev;
 
 constexpr int threads_for(int B) { return B - 1 >= 8 ? 256 : (1 << (B - 1)); }
 constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v >> 1); }
@@ -397,14 +355,6 @@ k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2
 }
 
 // ------------------------------------------------ wave/block reductions
-// Sum over the first WIDTH lanes of a wave (WIDTH = min(block size, 64)).
-template <int WIDTH>
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = WIDTH / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, WIDTH);
-    return v;
-}
 
 // ------------------------------------------------ Hamiltonian passes
 // Read-only pass over cosets of a unit-vector subspace T (the qubits of the

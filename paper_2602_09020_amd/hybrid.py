@@ -144,3 +144,54 @@ def prepare(w, dtype=torch.complex128, tuning: Optional[dict] = None, ham_tuning
     plan = Plan(w.n, dtype, rot, tuning)
     ham = Hamiltonian(w.n, dtype, terms, w.coeff, ham_tuning) if terms.shape[0] else None
     return frame, rot, terms, plan, ham
+
+
+class Batch:
+    """Many independent circuits run by one persistent kernel (cfh_batch_*)."""
+
+    def __init__(self, workloads, dtype=torch.complex128, tuning: Optional[dict] = None):
+        self.dtype = state_dtype(dtype)
+        circuits = []
+        self.m = []
+        for w in workloads:
+            frame = Frame(w.n)
+            frame.apply_gates(w.prefix)
+            circuits.append({"n": w.n, "init_index": w.init,
+                             "rot": frame.conjugate(_c.cfh_pauli_encode(w.rot)),
+                             "theta": w.theta, "terms": frame.conjugate(_c.cfh_pauli_encode(w.ham)),
+                             "coeff": w.coeff})
+            self.m.append(w.n_rot)
+        self.count = len(circuits)
+        self.total_rot = int(sum(self.m))
+        self.n = [c["n"] for c in circuits]
+        self.h = _c.cfh_batch_create(circuits, self.dtype, tuning)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            _c.cfh_batch_destroy(h)
+            self.h = None
+
+    def info(self) -> dict:
+        return _c.cfh_batch_info(self.h)
+
+    def set_theta(self, theta: np.ndarray) -> None:
+        _c.cfh_batch_set_theta(self.h, theta)
+
+    def run(self, with_grad: bool = True, stream=None) -> None:
+        _c.cfh_batch_run(self.h, with_grad, stream)
+
+    def graph_launch(self, with_grad: bool, stream) -> None:
+        _c.cfh_batch_graph_launch(self.h, with_grad, stream)
+
+    def results(self, stream=None) -> dict:
+        e, g, t0, t1, hz = _c.cfh_batch_results(self.h, self.count, self.total_rot, stream)
+        off = np.concatenate([[0], np.cumsum(self.m)])
+        return {"energy": e, "grad": [g[off[i]:off[i + 1]] for i in range(self.count)],
+                "t_start": t0, "t_end": t1, "tick_hz": hz}
+
+    def state(self, i: int, stream=None) -> torch.Tensor:
+        out = torch.empty(1 << self.n[i], dtype=torch.complex128 if self.dtype == _c.CFH_C128 else torch.complex64,
+                          device="cuda")
+        _c.cfh_batch_state(self.h, i, out, stream)
+        return out

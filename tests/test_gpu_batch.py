@@ -1,0 +1,119 @@
+"""GPU tests of the batched persistent path (cfh_batch_*) against the oracle
+and against the single-circuit path, including hipGraph replays."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import sim
+from paper_2602_09020_amd import cfh, hybrid
+
+pytestmark = pytest.mark.gpu
+
+
+def small_batch(seed=0, count=6):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(rng.integers(8, 13))
+        out.append(W.make_workload(f"b{i}", n, seed=100 + i, n_prefix=int(rng.integers(0, 3 * n)),
+                                   n_rot=int(rng.integers(30, 120)), n_ham=int(rng.integers(5, 30))))
+    return out
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 1e-4)])
+def test_batch_states_and_energies_vs_oracle(dtype, tol):
+    ws = small_batch(1)
+    B = hybrid.Batch(ws, dtype, {"tile_bits": 8, "batch_items": 3})
+    B.run(with_grad=False)
+    r = B.results()
+    for i, w in enumerate(ws):
+        psi, phi = sim.simulate(w)
+        got = B.state(i).cpu().to(torch.complex128).numpy()
+        assert np.abs(got - phi).max() <= tol, i
+        assert abs(r["energy"][i] - sim.energy(psi, w.n, w.ham, w.coeff)) <= tol * np.abs(w.coeff).sum(), i
+        assert r["t_end"][i] >= r["t_start"][i] > 0
+
+
+def test_batch_gradients_vs_oracle_parameter_shift():
+    ws = [W.make_workload(f"g{i}", 8 + i, seed=7 + i, n_prefix=10, n_rot=20 + 5 * i, n_ham=12) for i in range(3)]
+    B = hybrid.Batch(ws, torch.complex128, {"tile_bits": 8, "batch_items": 2})
+    B.run(with_grad=True)
+    r = B.results()
+    for i, w in enumerate(ws):
+        ps = sim.param_shift_grad(w)
+        assert np.abs(r["grad"][i] - ps).max() <= 1e-10, i
+        assert abs(r["energy"][i] - sim.energy_of(w, w.theta)) <= 1e-12 * np.abs(w.coeff).sum()
+        # the gradient run rewinds every state to its initial basis state
+        st = B.state(i).cpu().numpy()
+        ref = np.zeros_like(st)
+        ref[w.init] = 1
+        assert np.abs(st - ref).max() <= 1e-12
+
+
+def test_batch_matches_single_circuit_path():
+    ws = W.batched_configs(seed=3, count=8, n_range=(12, 16), r_range=(100, 300), n_ham=40)
+    B = hybrid.Batch(ws, torch.complex128)
+    B.run(with_grad=True)
+    r = B.results()
+    for i, w in enumerate(ws):
+        frame, rot, terms, plan, ham = hybrid.prepare(w, torch.complex128)
+        psi0 = hybrid.new_state(w.n, torch.complex128, index=w.init)
+        theta = torch.tensor(w.theta, device="cuda", requires_grad=True)
+        e = hybrid.PauliEnergy.apply(theta, plan, ham, psi0)
+        e.backward()
+        assert abs(e.item() - r["energy"][i]) <= 1e-12 * np.abs(w.coeff).sum()
+        assert np.abs(theta.grad.cpu().numpy() - r["grad"][i]).max() <= 1e-11
+
+
+def test_batch_hipgraph_replays_are_deterministic():
+    ws = W.batched_configs(seed=5, count=12, n_range=(12, 15), r_range=(60, 200), n_ham=30)
+    B = hybrid.Batch(ws, torch.complex128)
+    s = torch.cuda.Stream()
+    B.run(with_grad=True, stream=s)
+    ref = B.results(stream=s)
+    for rep in range(3):
+        B.graph_launch(True, s)
+        got = B.results(stream=s)
+        assert np.array_equal(got["energy"], ref["energy"]), rep
+        for a, b in zip(got["grad"], ref["grad"]):
+            assert np.array_equal(a, b), rep
+        # eager work between replays
+        x = torch.randn(1 << 16, device="cuda")
+        (x * 2).sum().item()
+    B.graph_launch(False, s)
+    fwd = B.results(stream=s)
+    assert np.array_equal(fwd["energy"], ref["energy"])
+
+
+def test_batch_new_angles():
+    ws = small_batch(2, count=4)
+    B = hybrid.Batch(ws, torch.complex128, {"tile_bits": 8})
+    rng = np.random.default_rng(0)
+    new = [rng.uniform(-3, 3, size=w.n_rot) for w in ws]
+    B.set_theta(np.concatenate(new))
+    B.run(with_grad=False)
+    r = B.results()
+    for i, w in enumerate(ws):
+        assert abs(r["energy"][i] - sim.energy_of(w, new[i])) <= 1e-12 * np.abs(w.coeff).sum()
+
+
+def test_batch_rejects_bad_input():
+    w = W.make_workload("x", 6, seed=0, n_rot=5, n_ham=3)
+    with pytest.raises(cfh.CfhError) as e:
+        hybrid.Batch([w], torch.complex128)
+    assert e.value.code == cfh.CFH_E_UNSUPPORTED
+    w = W.make_workload("y", 10, seed=0, n_rot=5, n_ham=3)
+    with pytest.raises(cfh.CfhError) as e:
+        hybrid.Batch([w], torch.complex128, {"tile_bits": 12})
+    assert e.value.code == cfh.CFH_E_UNSUPPORTED
+
+
+@pytest.mark.skip(reason="the persistent work-queue batch kernel stalled on MI355X twice (completion flags published "
+                         "with atomic stores and polled with relaxed loads were not seen across XCD L2 caches); its "
+                         "code path is switched off and cfh_batch_create rejects it")
+def test_batch_persistent_work_queue_kernel():
+    ws = small_batch(1)
+    B = hybrid.Batch(ws, torch.complex128, {"variant": 1})
+    B.run(with_grad=False)
+    B.results()

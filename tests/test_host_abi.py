@@ -217,3 +217,14 @@ def test_planner_rejects_bad_input():
     with pytest.raises(cfh.CfhError) as e:
         cfh.cfh_plan_dry_run(35, cfh.CFH_C128, np.zeros(0, cfh.PAULI_DTYPE))
     assert e.value.code == cfh.CFH_E_UNSUPPORTED
+
+
+def test_batch_rejects_disabled_persistent_variant_without_device_work():
+    """The persistent work-queue batch schedule is switched off: asking for it
+    fails in argument checking, before any device allocation."""
+    import ctypes as C
+    rot = cfh.cfh_pauli_encode(np.array([[1, 3, 1, 0, 0, 0, 0, 0]], np.uint8))
+    circ = [{"n": 8, "init_index": 0, "rot": rot, "theta": np.array([0.3]), "terms": rot, "coeff": np.array([1.0])}]
+    with pytest.raises(cfh.CfhError) as e:
+        cfh.cfh_batch_create(circ, cfh.CFH_C128, {"variant": 1})
+    assert e.value.code == cfh.CFH_E_UNSUPPORTED
