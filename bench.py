@@ -275,6 +275,45 @@ def main():
                           "backward_over_forward": float(np.median(bw) / np.median(fw)),
                           "passes": plan_a.info()["n_passes"]}
 
+        # 256 independent circuits (n 12..20, 500..3,000 rotations, 200-term observables),
+        # forward + adjoint in one captured hipGraph launch, tile shape from the autotuner
+        from paper_2602_09020_amd import autotune
+        ws = W.batched_configs()
+        out["batched"] = {"circuits": len(ws), "rotations": int(sum(x.n_rot for x in ws)),
+                          "qubits": [int(min(x.n for x in ws)), int(max(x.n for x in ws))]}
+        for dt, tag, cands in ((torch.complex128, "c128", [{"tile_bits": 10, "batch_items": 32},
+                                                          {"tile_bits": 10, "batch_items": 128},
+                                                          {"tile_bits": 11, "batch_items": 64}]),
+                               (torch.complex64, "c64", [{"tile_bits": 11, "batch_items": 32},
+                                                        {"tile_bits": 11, "batch_items": 128},
+                                                        {"tile_bits": 12, "batch_items": 64}])):
+            t0 = time.perf_counter()
+            tu = autotune.tune_batch(ws, dt, candidates=cands, use_cache=False)
+            tune_s = time.perf_counter() - t0
+            B = hybrid.Batch(ws, dt, tu)
+            s2 = torch.cuda.Stream()
+            res = {}
+            for wg in (False, True):
+                B.graph_launch(wg, s2)
+                B.results(stream=s2)
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(s2)
+                B.graph_launch(wg, s2)
+                b.record(s2)
+                r = B.results(stream=s2)
+                ms = a.elapsed_time(b)
+                lat = (r["t_end"].astype(np.float64) - r["t_start"].astype(np.float64)) / r["tick_hz"] * 1e3
+                rots = out["batched"]["rotations"] * (2 if wg else 1)
+                res["forward_and_adjoint" if wg else "forward"] = {
+                    "ms": ms, "rotations_per_s": rots / (ms * 1e-3),
+                    "p50_circuit_ms": float(np.percentile(lat, 50)), "p99_circuit_ms": float(np.percentile(lat, 99))}
+            res["tuning"] = tu
+            res["tune_s"] = tune_s
+            res["state_gb"] = B.info()["state_bytes"] / 1e9
+            out["batched"][tag] = res
+            del B
+            torch.cuda.empty_cache()
+
         # CPU oracle (ladder decomposition) on a bounded sample of the same workload
         from oracle import sim
         kc = args.cpu_rotations

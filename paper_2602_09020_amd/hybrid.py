@@ -147,7 +147,8 @@ def prepare(w, dtype=torch.complex128, tuning: Optional[dict] = None, ham_tuning
 
 
 class Batch:
-    """Many independent circuits run by one persistent kernel (cfh_batch_*)."""
+    """Many independent circuits run together: one kernel launch per pass
+    level, all items of a level in one grid (cfh_batch_*)."""
 
     def __init__(self, workloads, dtype=torch.complex128, tuning: Optional[dict] = None):
         self.dtype = state_dtype(dtype)

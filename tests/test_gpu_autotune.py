@@ -1,0 +1,35 @@
+"""The autotuner picks a tuning that the library accepts and that is no
+slower than the default it was compared with; it caches per device/size."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from paper_2602_09020_amd import autotune, cfh, hybrid
+
+pytestmark = pytest.mark.gpu
+
+
+def test_tune_plan_and_cache(tmp_path, monkeypatch):
+    monkeypatch.setenv("CFH_TUNING_CACHE", str(tmp_path / "tune.json"))
+    w = W.config(2, n=20, n_rot=300, trotter_steps=1)
+    rot = hybrid.Frame(w.n).conjugate(cfh.cfh_pauli_encode(w.rot))
+    cands = [{"variant": 1, "tile_bits": 11, "low_bits": 4}, {"variant": 3, "tile_bits": 11, "low_bits": 4},
+             {"variant": 3, "tile_bits": 13, "low_bits": 4}]
+    best = autotune.tune_plan(w.n, torch.complex128, rot, w.theta, candidates=cands)
+    assert best in cands
+    d = json.load(open(tmp_path / "tune.json"))
+    assert any(v["tuning"] == best for v in d.values())
+    # second call is served from the cache
+    assert autotune.tune_plan(w.n, torch.complex128, rot, w.theta, candidates=[]) == best
+
+
+def test_tune_batch_returns_accepted_tuning(tmp_path, monkeypatch):
+    monkeypatch.setenv("CFH_TUNING_CACHE", str(tmp_path / "tune.json"))
+    ws = W.batched_configs(seed=1, count=6, n_range=(12, 14), r_range=(50, 100), n_ham=20)
+    cands = [{"tile_bits": 9, "batch_items": 8}, {"tile_bits": 10, "batch_items": 32}]
+    best = autotune.tune_batch(ws, torch.complex128, candidates=cands)
+    assert best in cands

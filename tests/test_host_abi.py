@@ -228,3 +228,16 @@ def test_batch_rejects_disabled_persistent_variant_without_device_work():
     with pytest.raises(cfh.CfhError) as e:
         cfh.cfh_batch_create(circ, cfh.CFH_C128, {"variant": 1})
     assert e.value.code == cfh.CFH_E_UNSUPPORTED
+
+
+def test_autotune_candidates_respect_kernel_limits():
+    import torch
+    from paper_2602_09020_amd import autotune
+    for n in (10, 16, 20, 28):
+        for dt in (torch.complex128, torch.complex64):
+            for tu in autotune.plan_candidates(n, dt):
+                assert tu["low_bits"] < tu["tile_bits"] <= n
+                if tu["variant"] == 3:
+                    assert 10 <= tu["tile_bits"] <= 13
+                if dt == torch.complex128:
+                    assert tu["tile_bits"] <= 13
