@@ -32,16 +32,16 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def counter_traffic(name: str):
+def counter_traffic(name: str, kernel: str):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source; else None."""
+    taken on the current kernel source for this kernel instance; else None."""
     path = os.path.join(ROOT, "profiles", name)
     try:
         with open(path) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+    if d.get("kernel_source_sha256_16") != kernel_source_hash() or d.get("kernel_short") != kernel:
         return None
     return d.get("traffic_bytes_per_launch")
 
@@ -59,6 +59,11 @@ def main():
                     help="passes: apply the plan of the first --rotations rotations once (for counter runs); "
                          "copy: a plain device copy of the same state size (counter and bandwidth calibration)")
     ap.add_argument("--rotations", type=int, default=150)
+    ap.add_argument("--chunk", type=int, default=2000, help="rotations planned per plan inside a step")
+    ap.add_argument("--dtype", choices=["c128", "c64"], default="c128", help="state storage for --mode passes")
+    ap.add_argument("--variant", type=int, default=0, help="fused kernel variant for --mode passes (0 = default)")
+    ap.add_argument("--tile-bits", type=int, default=0, help="tile bits for --mode passes (0 = default)")
+    ap.add_argument("--low-bits", type=int, default=0, help="contiguous low bits for --mode passes (0 = default)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the state-vector path is single-device here "
@@ -95,69 +100,81 @@ def main():
     if args.mode == "passes":
         frame = hybrid.Frame(w.n)
         rot = frame.conjugate(cfh.cfh_pauli_encode(w.rot[:args.rotations]))
-        plan = hybrid.Plan(w.n, torch.complex128, rot)
+        sdt = torch.complex128 if args.dtype == "c128" else torch.complex64
+        plan = hybrid.Plan(w.n, sdt, rot, {"variant": args.variant, "tile_bits": args.tile_bits,
+                                            "low_bits": args.low_bits})
         theta = torch.tensor(w.theta[:args.rotations], device=dev)
-        psi = hybrid.new_state(w.n, torch.complex128, index=w.init)
+        psi = hybrid.new_state(w.n, sdt, index=w.init)
         plan.apply(psi, theta)
         torch.cuda.synchronize()
         print(json.dumps({"mode": "passes", "rotations": args.rotations, **plan.info()}), flush=True)
         return
     n, K = w.n, w.n_rot
     dtype = torch.complex128
-    enc0 = cfh.cfh_pauli_encode(w.rot)
-    frame0 = hybrid.Frame(n)
-    rot0 = frame0.conjugate(enc0)
-    t0 = time.perf_counter()
-    plan = hybrid.Plan(n, dtype, rot0)
-    ham = hybrid.Hamiltonian(n, dtype, frame0.conjugate(cfh.cfh_pauli_encode(w.ham)), w.coeff)
-    plan_ms = (time.perf_counter() - t0) * 1e3
-    info = plan.info()
-    hinfo = ham.info()
+    chunk = max(1, args.chunk)
     theta = torch.tensor(w.theta, device=dev)
     psi = torch.empty(1 << n, dtype=dtype, device=dev)
     e_out = torch.zeros(2, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
 
-    ev_rot = []
-
-    def step(record):
-        # a1 encode, a2 frame (config has no Clifford prefix: identity frame), a3 conjugate
+    def step():
+        """One pass of the whole path: a1 encode, a2 frame tracking of the Clifford
+        prefix (empty here), a3 conjugation, a4 planning chunk by chunk (host work
+        overlapped with the device running the previous chunk), a5-a7 fused passes,
+        a8 expectation value.  Returns what must stay alive until the device is done."""
         enc = cfh.cfh_pauli_encode(w.rot)
         frame = hybrid.Frame(n)
         frame.apply_gates(w.prefix)
         rot = frame.conjugate(enc)
+        terms = frame.conjugate(cfh.cfh_pauli_encode(w.ham))
         assert rot.shape[0] == K
         cfh.cfh_state_set_basis(psi, n, w.init)
-        if record:
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-        plan.apply(psi, theta)
-        if record:
-            b.record(stream)
-            ev_rot.append((a, b))
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        plans = []
+        for lo in range(0, K, chunk):
+            p = hybrid.Plan(n, dtype, rot[lo:lo + chunk])
+            if lo == 0:
+                a.record(stream)  # device time of the passes; the first chunk's planning is host-only
+            p.apply(psi, theta[lo:lo + chunk])
+            plans.append(p)
+        b.record(stream)
+        ham = hybrid.Hamiltonian(n, dtype, terms, w.coeff)
         ham.expval_async(psi, e_out)
+        return plans, ham, (a, b)
 
     for _ in range(args.warmup):
-        step(False)
+        step()
     torch.cuda.synchronize()
+    keep = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step(True)
+        keep.append(step())
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed * 1e3 / args.steps
-    rot_ms = [a.elapsed_time(b) for a, b in ev_rot]
-    launches = info["n_passes"]
-    # the apply_plan region is one tiny angle kernel plus `launches` fused pass kernels
+    rot_ms = [a.elapsed_time(b) for _, _, (a, b) in keep]
+    plans, ham, _ = keep[-1]
+    infos = [p.info() for p in plans]
+    hinfo = ham.info()
+    launches = sum(i["n_passes"] for i in infos)
+    # the rotation region is one tiny angle kernel per chunk plus `launches` fused pass kernels
     pass_ms = float(np.mean(rot_ms)) / launches
     amp_b = 16
     pass_bytes = 2.0 * (1 << n) * amp_b
     achieved_gbs = pass_bytes / (pass_ms * 1e-3) / 1e9
     energy = float(e_out[0].item())
     value = K / (ms_per_step * 1e-3)
-    kname = f"k_pass2<double2,{info['tile_bits']}>" if info["tile_bits"] >= 8 else \
-        f"k_pass<double2,{info['tile_bits']}>"
-    traffic = counter_traffic(f"{kname.split('<')[0]}_n{n}_c128_counters.json")
+    tb, var = infos[0]["tile_bits"], infos[0]["variant"]
+    kname = f"k_pass2<double2,{tb},{2 if var == 4 else 1 if var == 2 else 0}>" if var >= 2 else \
+        f"k_pass<double2,{tb}>"
+    traffic = counter_traffic(f"{kname.split('<')[0]}_n{n}_c128_counters.json", kname)
+    del keep
+    # planning cost of the whole sequence in one plan (reported; inside the step
+    # it is spread over the chunks and overlapped with the device)
+    rot0 = hybrid.Frame(n).conjugate(cfh.cfh_pauli_encode(w.rot))
+    t0 = time.perf_counter()
+    plan = hybrid.Plan(n, dtype, rot0)
+    plan_ms = (time.perf_counter() - t0) * 1e3
 
     out = {
         "metric": "Pauli rotations/s + HBM GB/s at n=28 c128; adjoint grad time vs forward",
@@ -182,8 +199,9 @@ def main():
         "passes": launches,
         "fusion_depth": K / launches,
         "rotation_phase_ms": float(np.mean(rot_ms)),
+        "plan_chunk": chunk,
         "expval": {"value": energy, "passes": hinfo["n_passes"], "groups": hinfo["n_groups"]},
-        "plan_ms": plan_ms,
+        "plan_ms_whole_sequence": plan_ms,
     }
 
     if not args.no_extras:

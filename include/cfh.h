@@ -85,7 +85,9 @@ typedef struct cfh_tuning {
     int32_t variant;       /* fused kernel: 0 = default, 1 = LDS-staged (every rotation through LDS),
                               2 = register-tiled (micro-groups of 4 dimensions in registers, LDS
                               only between micro-groups, next coset prefetched into registers;
-                              needs tile_bits in 10..13), 3 = register-tiled without the prefetch */
+                              needs tile_bits in 10..13), 3 = register-tiled without the prefetch,
+                              4 = register-tiled, one unrolled body per (partner mask, register
+                              sign mask, real/imaginary) so member signs cost no instructions */
     int32_t batch_items;   /* batched runs: at most this many work items per pass (0 = 32) */
 } cfh_tuning;
 
@@ -193,11 +195,12 @@ cfh_status cfh_plan_destroy(cfh_plan p);
 cfh_status cfh_plan_dry_run(int n, int dtype, const cfh_pauli *rot, size_t m, const cfh_tuning *tuning,
                             int64_t *n_passes, int64_t *pass_start, int64_t *order);
 
-/* Plan summary: passes, rotations, tile bits actually used and the number
- * of HBM bytes one application moves (2 * 2^n * bytes per amplitude per
- * pass).  Any pointer may be NULL. */
+/* Plan summary: passes, rotations, tile bits actually used, the number of
+ * HBM bytes one application moves (2 * 2^n * bytes per amplitude per pass)
+ * and the fused kernel variant the plan runs (as in cfh_tuning.variant after
+ * resolving the default; 0 for an unfused plan).  Any pointer may be NULL. */
 cfh_status cfh_plan_info(cfh_plan p, int64_t *n_passes, int64_t *n_rot, int32_t *tile_bits,
-                         double *hbm_bytes);
+                         double *hbm_bytes, int32_t *variant);
 
 /* Pass boundaries and order: pass_start has n_passes+1 entries (prefix
  * offsets into order), order has m rotation indices in application order. */

@@ -58,7 +58,7 @@ def plan_candidates(n: int, dtype) -> List[dict]:
                 continue
             out.append({"variant": 1, "tile_bits": tb, "low_bits": lb})
             if 10 <= tb <= 13:
-                out.append({"variant": 3, "tile_bits": tb, "low_bits": lb})
+                out.append({"variant": 4, "tile_bits": tb, "low_bits": lb})
     return out
 
 

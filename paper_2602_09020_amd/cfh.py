@@ -72,7 +72,8 @@ _SIGS = {
     "cfh_plan_create": (C.c_int32, [C.c_int, C.c_int, _vp, C.c_size_t, _P(cfh_tuning), _P(_vp)]),
     "cfh_plan_destroy": (C.c_int32, [_vp]),
     "cfh_plan_dry_run": (C.c_int32, [C.c_int, C.c_int, _vp, C.c_size_t, _P(cfh_tuning), _P(C.c_int64), _vp, _vp]),
-    "cfh_plan_info": (C.c_int32, [_vp, _P(C.c_int64), _P(C.c_int64), _P(C.c_int32), _P(C.c_double)]),
+    "cfh_plan_info": (C.c_int32, [_vp, _P(C.c_int64), _P(C.c_int64), _P(C.c_int32), _P(C.c_double),
+                                  _P(C.c_int32)]),
     "cfh_plan_schedule": (C.c_int32, [_vp, _vp, _vp]),
     "cfh_apply_plan": (C.c_int32, [_vp, _vp, _vp, C.c_int, _vp]),
     "cfh_ham_create": (C.c_int32, [C.c_int, C.c_int, _vp, _vp, C.c_size_t, _P(cfh_tuning), _P(_vp)]),
@@ -271,9 +272,10 @@ def cfh_plan_dry_run(n: int, dtype: int, rot: np.ndarray, tuning=None):
 
 
 def cfh_plan_info(p: int) -> dict:
-    np_, nr, tb, hb = C.c_int64(), C.c_int64(), C.c_int32(), C.c_double()
-    _call("cfh_plan_info", p, C.byref(np_), C.byref(nr), C.byref(tb), C.byref(hb))
-    return {"n_passes": np_.value, "n_rot": nr.value, "tile_bits": tb.value, "hbm_bytes": hb.value}
+    np_, nr, tb, hb, var = C.c_int64(), C.c_int64(), C.c_int32(), C.c_double(), C.c_int32()
+    _call("cfh_plan_info", p, C.byref(np_), C.byref(nr), C.byref(tb), C.byref(hb), C.byref(var))
+    return {"n_passes": np_.value, "n_rot": nr.value, "tile_bits": tb.value, "hbm_bytes": hb.value,
+            "variant": var.value}
 
 
 def cfh_plan_schedule(p: int, m: int, n_passes: int):

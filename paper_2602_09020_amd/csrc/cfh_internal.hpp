@@ -89,7 +89,9 @@ struct RotDesc2 {
     uint8_t flags;   // bit 0: beta imaginary (w odd); bit 1: negate (w & 2)
     uint64_t z;      // global z (coset base sign)
     int32_t k;       // rotation index
-    int32_t pad[3];
+    uint32_t zt;     // thread-index parity mask: parity(t & zt) = parity(bt & zl)
+    uint32_t kase;   // cx | zr << 4 | imag << 8, zr_i = parity(u_i & zl); msign_j = parity(j & zr)
+    int32_t pad;
 };
 
 struct MGDesc2 {

@@ -275,16 +275,84 @@ __device__ __forceinline__ void mg_dispatch(int cx, double2 (&r)[kRegs], double 
     }
 }
 
+// Compile-time rotation bodies.  KASE = cx | zr << 4 | imag << 8 fixes the
+// partner mask and every register's sign (the sign of register j is
+// parity(j & zr), since the register offsets are spanned by four vectors), so
+// the signs become negations of FMA operands instead of sign arithmetic.
+constexpr bool cpar(int v) { return __builtin_popcount(v) & 1; }
+
+template <int KASE>
+__device__ __forceinline__ void kase_body(double2 (&r)[kRegs], double c, double s)
+{
+    constexpr int CX = KASE & 15, ZR = (KASE >> 4) & 15;
+    constexpr bool IMAG = (KASE >> 8) & 1;
+    if constexpr (CX == 0) {
+        if constexpr (IMAG) {
+#pragma unroll
+            for (int j = 0; j < kRegs; ++j) {
+                const double sj = cpar(j & ZR) ? -s : s;
+                r[j] = make_double2(c * r[j].x - sj * r[j].y, c * r[j].y + sj * r[j].x);
+            }
+        } else {
+            const double cp = c + s, cm = c - s;
+#pragma unroll
+            for (int j = 0; j < kRegs; ++j) {
+                const double f = cpar(j & ZR) ? cm : cp;
+                r[j] = make_double2(f * r[j].x, f * r[j].y);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) {
+            if ((j ^ CX) > j) {
+                rot_pair(r[j], r[j ^ CX], c, cpar(j & ZR) ? -s : s, cpar((j ^ CX) & ZR) ? -s : s, IMAG);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+}
+
+// Uniform branch tree over the nine bits of kase (one leaf per body).
+template <int BIT, int ACC>
+__device__ __forceinline__ void kase_dispatch(uint32_t kase, double2 (&r)[kRegs], double c, double s)
+{
+    if constexpr (BIT < 0) {
+        kase_body<ACC>(r, c, s);
+    } else {
+        if (kase & (1u << BIT))
+            kase_dispatch<BIT - 1, ACC | (1 << BIT)>(kase, r, c, s);
+        else
+            kase_dispatch<BIT - 1, ACC>(kase, r, c, s);
+    }
+}
+
 // MODE bit 0: prefetch the next coset into registers.
+// MODE bit 1: compile-time rotation bodies; (c, s) of the pass staged in LDS
+//             once per workgroup, thread signs precomputed as one bit mask.
 template <typename Amp, int B, int MODE>
 __global__ void __launch_bounds__(1 << (B - kRegDims))
 k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2 args, uint64_t ntiles)
 {
     constexpr bool PF = MODE & 1;
+    constexpr bool CT = MODE & 2;
     extern __shared__ unsigned char lds_raw[];
     Amp *lds = reinterpret_cast<Amp *>(lds_raw);
+    __shared__ double2 tab[CT ? kMaxRun : 1];
     const uint32_t t = threadIdx.x;
     const int last = args.nmg - 1;
+    uint32_t tsb = 0;  // bit ri: parity(t & zt) of rotation ri
+    if constexpr (CT) {
+        const int nrot = args.mg[last].rot_begin + args.mg[last].rot_count;
+        if ((int)t < nrot) {
+            const RotDesc2 &d = args.rot[t];
+            const double2 cs = coef[d.k];
+            double sv = args.inverse ? -cs.y : cs.y;
+            if (d.flags & 2) sv = -sv;
+            tab[t] = make_double2(cs.x, sv);
+        }
+        for (int ri = 0; ri < nrot; ++ri) tsb |= (uint32_t)par32(t & args.rot[ri].zt) << ri;
+        __syncthreads();
+    }
     uint64_t Lb0 = 0, LbL = 0;
     {
         const uint32_t b0 = deposit32(t, args.mg[0].npiv), bL = deposit32(t, args.mg[last].npiv);
@@ -335,17 +403,26 @@ k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2
                 __syncthreads();
             }
             bprev = bt;
-            for (int ri = m.rot_begin; ri < m.rot_begin + m.rot_count; ++ri) {
-                const RotDesc2 &d = args.rot[ri];
-                const double2 cs = coef[d.k];
-                double sr = args.inverse ? -cs.y : cs.y;
-                if (d.flags & 2) sr = -sr;
-                const int sg = par32(bt & d.zl) ^ par64(tb & d.z);
-                const double srA = sg ? -sr : sr;
-                if (d.flags & 1)
-                    mg_dispatch<true>(d.cx, r, cs.x, srA, d.msign);
-                else
-                    mg_dispatch<false>(d.cx, r, cs.x, srA, d.msign);
+            if constexpr (CT) {
+                for (int ri = m.rot_begin; ri < m.rot_begin + m.rot_count; ++ri) {
+                    const RotDesc2 &d = args.rot[ri];
+                    const double2 cs = tab[ri];
+                    const uint32_t sg = ((tsb >> ri) ^ (uint32_t)par64(tb & d.z)) & 1u;
+                    kase_dispatch<8, 0>(d.kase, r, cs.x, flip_if(cs.y, sg));
+                }
+            } else {
+                for (int ri = m.rot_begin; ri < m.rot_begin + m.rot_count; ++ri) {
+                    const RotDesc2 &d = args.rot[ri];
+                    const double2 cs = coef[d.k];
+                    double sr = args.inverse ? -cs.y : cs.y;
+                    if (d.flags & 2) sr = -sr;
+                    const int sg = par32(bt & d.zl) ^ par64(tb & d.z);
+                    const double srA = sg ? -sr : sr;
+                    if (d.flags & 1)
+                        mg_dispatch<true>(d.cx, r, cs.x, srA, d.msign);
+                    else
+                        mg_dispatch<false>(d.cx, r, cs.x, srA, d.msign);
+                }
             }
         }
         const uint64_t yL = tb ^ LbL;
@@ -777,7 +854,14 @@ cfh_status launch_pass2_b(uint64_t ntiles, hipStream_t s, Amp *psi, const double
         const void *fn = reinterpret_cast<const void *>(&k_pass2<Amp, B, MODE>);
         static bool attr = false;
         if (!attr) {
-            (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            // dynamic LDS may take what the kernel's static LDS leaves of the 160 KiB
+            hipFuncAttributes fa{};
+            cfh_status st = CFH_OK;
+            if (!hip_ok(hipFuncGetAttributes(&fa, fn), "k_pass2: hipFuncGetAttributes", &st)) return st;
+            if (!hip_ok(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)(160 * 1024 - fa.sharedSizeBytes)),
+                        "k_pass2: hipFuncSetAttribute", &st))
+                return st;
             attr = true;
         }
         const unsigned grid = (unsigned)std::min<uint64_t>(ntiles, resident_grid(fn, T, lds));
@@ -789,8 +873,11 @@ cfh_status launch_pass2_b(uint64_t ntiles, hipStream_t s, Amp *psi, const double
 template <typename Amp, int B>
 cfh_status launch_pass2_m(uint64_t ntiles, hipStream_t s, Amp *psi, const double2 *coef, const PassArgs2 &a, int mode)
 {
-    return (mode & 1) ? launch_pass2_b<Amp, B, 1>(ntiles, s, psi, coef, a)
-                      : launch_pass2_b<Amp, B, 0>(ntiles, s, psi, coef, a);
+    switch (mode) {
+    case 1: return launch_pass2_b<Amp, B, 1>(ntiles, s, psi, coef, a);
+    case 2: return launch_pass2_b<Amp, B, 2>(ntiles, s, psi, coef, a);
+    default: return launch_pass2_b<Amp, B, 0>(ntiles, s, psi, coef, a);
+    }
 }
 
 // Workgroups of 2^(b-4) threads: b >= 10 keeps them at one full wave or more.
@@ -1023,16 +1110,16 @@ cfh_status cfh_plan_create(int n, int dtype, const cfh_pauli *rot, size_t m, con
         cfh_status st = build_pass_args(p->passes, p->rot, p->args);
         if (st) return st;
         const int b = p->tu.tile_bits;
-        if (p->tu.variant < 0 || p->tu.variant > 3)
+        if (p->tu.variant < 0 || p->tu.variant > 4)
             return set_error(CFH_E_INVAL, "cfh_plan_create: unknown kernel variant");
         if (p->tu.variant >= 2 && (b < 10 || b > 13))
             return set_error(CFH_E_UNSUPPORTED, "cfh_plan_create: the register-tiled kernel needs tile_bits in 10..13");
-        // default: register-tiled (no prefetch) for complex128 where it applies,
-        // LDS-staged otherwise (measured faster for complex64 storage)
+        // default: register-tiled with compile-time bodies for complex128 where
+        // it applies, LDS-staged otherwise (measured faster for complex64 storage)
         int v = p->tu.variant;
-        if (v == 0) v = (dtype == CFH_C128 && b >= 10 && b <= 13) ? 3 : 1;
+        if (v == 0) v = (dtype == CFH_C128 && b >= 10 && b <= 13) ? 4 : 1;
         p->tu.variant = v;
-        p->mode2 = v == 2 ? 1 : 0;
+        p->mode2 = v == 2 ? 1 : v == 4 ? 2 : 0;
         if (v >= 2) {
             p->v2 = true;
             p->args2.resize(p->passes.size());
@@ -1082,7 +1169,8 @@ cfh_status cfh_plan_destroy(cfh_plan p)
     return CFH_OK;
 }
 
-cfh_status cfh_plan_info(cfh_plan p, int64_t *n_passes, int64_t *n_rot, int32_t *tile_bits, double *hbm_bytes)
+cfh_status cfh_plan_info(cfh_plan p, int64_t *n_passes, int64_t *n_rot, int32_t *tile_bits, double *hbm_bytes,
+                         int32_t *variant)
 {
     if (!p) return set_error(CFH_E_INVAL, "cfh_plan_info: null plan");
     const int64_t np = p->tu.unfused ? (int64_t)p->rot.size() : (int64_t)p->passes.size();
@@ -1090,6 +1178,7 @@ cfh_status cfh_plan_info(cfh_plan p, int64_t *n_passes, int64_t *n_rot, int32_t 
     if (n_rot) *n_rot = (int64_t)p->rot.size();
     if (tile_bits) *tile_bits = p->tu.unfused ? 0 : p->tu.tile_bits;
     if (hbm_bytes) *hbm_bytes = 2.0 * (double)np * (double)(1ull << p->n) * (double)amp_bytes(p->dtype);
+    if (variant) *variant = p->tu.unfused ? 0 : p->tu.variant;
     return CFH_OK;
 }
 

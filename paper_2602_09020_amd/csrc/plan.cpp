@@ -14,17 +14,19 @@ TuningResolved resolve_tuning(const cfh_tuning *t, int n, int dtype, int kind)
     TuningResolved r;
     const bool c64 = dtype == CFH_C64;
     // Defaults measured on MI355X at 28 qubits: complex128 runs best with the
-    // register-tiled kernel on 2^13-amplitude tiles, complex64 with the
-    // LDS-staged kernel on 2^12; 16 contiguous amplitudes per chunk.  Small
-    // states keep at least 512 tiles per pass so every CU gets work.  The
-    // adjoint holds two tiles in LDS and uses 2^11 (c128) / 2^12 (c64).
-    // The read-only Hamiltonian passes use 2^12 / 2^13 tiles with 32-amplitude chunks.
+    // register-tiled kernel on 2^13-amplitude tiles and 8 contiguous
+    // amplitudes per chunk (one more free dimension per pass), complex64 with
+    // the LDS-staged kernel on 2^12 and 16-amplitude chunks.  Small states
+    // keep at least 512 tiles per pass so every CU gets work.  The adjoint
+    // holds two tiles in LDS and uses 2^11 (c128) / 2^12 (c64).  The
+    // read-only Hamiltonian passes use 2^12 / 2^13 tiles with 32-amplitude chunks.
     int b = c64 ? 12 : 13;
     if (kind == kTuneAdjoint) b = c64 ? 12 : 11;
     if (kind == kTuneHamiltonian) b = c64 ? 13 : 12;
     b = std::max(std::min(b, n - 9), std::min(n, 10));
     r.tile_bits = (t && t->tile_bits > 0) ? t->tile_bits : b;
-    r.low_bits = (t && t->low_bits > 0) ? t->low_bits : (kind == kTuneHamiltonian ? 5 : 4);
+    const int c_def = kind == kTuneHamiltonian ? 5 : (kind == kTuneForward && !c64) ? 3 : 4;
+    r.low_bits = (t && t->low_bits > 0) ? t->low_bits : c_def;
     r.max_run = (t && t->max_run > 0) ? t->max_run : kMaxRun;
     r.lookahead = (t && t->lookahead != 0) ? t->lookahead : 512;
     r.unfused = (t && t->unfused) ? 1 : 0;
@@ -250,6 +252,20 @@ bool build_pass_args2(const PassPlan &pp, const std::vector<Pauli> &rot, bool in
             d.msign = (uint16_t)ms;
             const int w = (p.e - popc(p.x & p.z) + 3) & 3;
             d.flags = (uint8_t)((w & 1) | ((w & 2) ? 2 : 0));
+            // register signs are linear in j (U is spanned by the four u_q), so
+            // they are fixed by a 4-bit mask; the thread part by a mask on t
+            uint32_t zr = 0;
+            for (int q = 0; q < kRegDims; ++q)
+                if (popc(s.v[q] & zl[i]) & 1) zr |= 1u << q;
+            d.kase = cx | (zr << 4) | ((uint32_t)(w & 1) << 8);
+            uint32_t zt = 0;
+            int tb = 0;
+            for (int bit = 0; bit < b; ++bit)
+                if ((m.npiv >> bit) & 1) {
+                    if ((zl[i] >> bit) & 1) zt |= 1u << tb;
+                    ++tb;
+                }
+            d.zt = zt;
             d.z = p.z;
             d.k = order[i];
         }

@@ -18,7 +18,7 @@ def test_tune_plan_and_cache(tmp_path, monkeypatch):
     w = W.config(2, n=20, n_rot=300, trotter_steps=1)
     rot = hybrid.Frame(w.n).conjugate(cfh.cfh_pauli_encode(w.rot))
     cands = [{"variant": 1, "tile_bits": 11, "low_bits": 4}, {"variant": 3, "tile_bits": 11, "low_bits": 4},
-             {"variant": 3, "tile_bits": 13, "low_bits": 4}]
+             {"variant": 4, "tile_bits": 13, "low_bits": 3}]
     best = autotune.tune_plan(w.n, torch.complex128, rot, w.theta, candidates=cands)
     assert best in cands
     d = json.load(open(tmp_path / "tune.json"))
