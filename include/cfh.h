@@ -87,7 +87,9 @@ typedef struct cfh_tuning {
                               only between micro-groups, next coset prefetched into registers;
                               needs tile_bits in 10..13), 3 = register-tiled without the prefetch,
                               4 = register-tiled, one unrolled body per (partner mask, register
-                              sign mask, real/imaginary) so member signs cost no instructions */
+                              sign mask, real/imaginary) so member signs cost no instructions,
+                              5 = as 4 with the transposes between micro-groups done in two
+                              halves through half the LDS (tile_bits 10..14) */
     int32_t batch_items;   /* batched runs: at most this many work items per pass (0 = 32) */
 } cfh_tuning;
 

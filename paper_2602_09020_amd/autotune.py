@@ -51,14 +51,17 @@ def plan_candidates(n: int, dtype) -> List[dict]:
     """Kernel variant x tile bits x contiguous low bits, within each kernel's limits."""
     c128 = hybrid.state_dtype(dtype) == _c.CFH_C128
     out = []
-    tb_max = min(n, 13 if c128 else 14)
+    tb_max = min(n, 14)
     for tb in range(max(8, min(n, 10)), tb_max + 1):
         for lb in (3, 4, 5, 6):
             if lb >= tb:
                 continue
-            out.append({"variant": 1, "tile_bits": tb, "low_bits": lb})
+            if tb <= (13 if c128 else 14):
+                out.append({"variant": 1, "tile_bits": tb, "low_bits": lb})
             if 10 <= tb <= 13:
                 out.append({"variant": 4, "tile_bits": tb, "low_bits": lb})
+            if 10 <= tb <= 14:
+                out.append({"variant": 5, "tile_bits": tb, "low_bits": lb})
     return out
 
 

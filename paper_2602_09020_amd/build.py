@@ -7,13 +7,17 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libcfh.so")
-SOURCES = ["frame.cpp", "plan.cpp", "kernels.hip", "batch.hip"]
+SOURCES = ["frame.cpp", "plan.cpp", "kernels.hip", "pass2_c128.hip", "pass2_c64.hip", "batch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # uniform branch trees (the per-rotation body dispatch) stay unstructured:
+    # structurizing them makes every body's outputs live through the whole
+    # tree, which costs register copies and occupancy
+    "-mllvm", "-structurizecfg-skip-uniform-regions=true",
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
 ]

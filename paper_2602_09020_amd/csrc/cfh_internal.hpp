@@ -95,8 +95,9 @@ struct RotDesc2 {
 };
 
 struct MGDesc2 {
-    uint32_t U[kRegs];  // local offset of register j
-    uint32_t npiv;      // local bits that enumerate threads
+    uint32_t U[kRegs];   // local offset of register j
+    uint32_t UC[kRegs];  // U[j] with the anchor bit removed (half-tile LDS index)
+    uint32_t npiv;       // local bits that enumerate threads
     int32_t rot_begin;
     int32_t rot_count;
     int32_t pad;
@@ -110,7 +111,7 @@ struct PassArgs2 {
     int32_t b;
     int32_t nmg;
     int32_t inverse;                 // negate angles (order already reversed on the host)
-    int32_t pad;
+    int32_t qbit;                    // anchor pivot bit (register dim 0 of every micro-group), -1 = none
     MGDesc2 mg[kMaxMG];
     RotDesc2 rot[kMaxRun];
 };
@@ -173,7 +174,9 @@ std::vector<HamPass> plan_hamiltonian(int n, const std::vector<HamGroup> &groups
 RotDesc make_rot_desc(const PassPlan &pp, const Pauli &p, int k);
 // Register-tiled kernel arguments for one pass (forward or inverse order);
 // false if the pass does not fit (more than kMaxMG micro-groups, b < kRegDims).
-bool build_pass_args2(const PassPlan &pp, const std::vector<Pauli> &rot, bool inverse, PassArgs2 &a);
+// anchor: seed every micro-group with the same vector (register dimension 0),
+// so transposes can move the tile through LDS in two halves.
+bool build_pass_args2(const PassPlan &pp, const std::vector<Pauli> &rot, bool inverse, bool anchor, PassArgs2 &a);
 uint32_t local_coords(const std::vector<uint64_t> &v, uint64_t x, bool *in_span);
 uint32_t local_zmask(const std::vector<uint64_t> &v, uint64_t z);
 

@@ -18,8 +18,46 @@
 
 #include "cfh_internal.hpp"
 #include "device_common.hpp"
+#include "launch.hpp"
 
 using namespace cfh;
+
+namespace cfh {
+
+bool hip_ok(hipError_t e, const char *what, cfh_status *st)
+{
+    if (e == hipSuccess) return true;
+    *st = set_error(CFH_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    return false;
+}
+
+cfh_status last_launch(const char *what)
+{
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(CFH_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    return CFH_OK;
+}
+
+// Persistent grid: as many workgroups as can be resident at once (cached per
+// kernel, LDS size and device).
+unsigned resident_grid(const void *fn, int threads, size_t lds)
+{
+    static std::map<std::tuple<const void *, size_t, int>, unsigned> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const auto key = std::make_tuple(fn, lds, dev);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+    const unsigned g = (unsigned)(per_cu * cus);
+    cache[key] = g;
+    return g;
+}
+
+} // namespace cfh
 
 namespace {
 
@@ -200,234 +238,6 @@ k_pass(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs a
         for (int i = 0; i < B - LT; ++i)
             if ((k >> i) & 1) Lk ^= args.v[LT + i];
         psi[yb ^ Lk] = r[k];
-    }
-}
-
-// ------------------------------------------ register-tiled fused pass (v2)
-// Thread t of a workgroup holds, during micro-group g, the 16 amplitudes
-// a = base_t ^ U_g[j] of the coset, base_t = deposit(t, npiv_g).  A rotation
-// of the micro-group pairs registers j and j ^ cx (cx known only at run time
-// but uniform, so it selects one of 15 unrolled bodies).  Member j of the
-// pair gets the sign (-1)^{parity(y & z)} = (-1)^{st ^ msign_j}, with st the
-// thread/coset part and msign_j the register part precomputed on the host.
-// Workgroups are persistent: the loads of the next coset are issued before
-// the current one is processed, so HBM traffic overlaps the arithmetic.
-
-__device__ __forceinline__ uint32_t deposit32(uint32_t v, uint32_t mask)
-{
-    uint32_t r = 0;
-    for (uint32_t m = mask; m && v; m &= m - 1, v >>= 1)
-        if (v & 1) r |= m & (~m + 1);
-    return r;
-}
-
-// v with its sign flipped when the (wave-uniform) bit is set: one XOR of the
-// high word instead of a select between two registers.
-__device__ __forceinline__ double flip_if(double v, uint32_t bit)
-{
-    return __longlong_as_double(__double_as_longlong(v) ^ ((unsigned long long)(bit & 1) << 63));
-}
-
-template <int CX, bool IMAG>
-__device__ __forceinline__ void mg_rot(double2 (&r)[kRegs], double c, double srA, uint32_t msign)
-{
-#pragma unroll
-    for (int j = 0; j < kRegs; ++j) {
-        if ((j ^ CX) > j) {
-            const double s0 = flip_if(srA, msign >> j);
-            const double s1 = flip_if(srA, msign >> (j ^ CX));
-            rot_pair(r[j], r[j ^ CX], c, s0, s1, IMAG);
-            // pairs one after another: the scheduler would otherwise keep the
-            // temporaries of all eight pairs live at once
-            __builtin_amdgcn_sched_barrier(0);
-        }
-    }
-}
-
-template <bool IMAG>
-__device__ __forceinline__ void mg_diag(double2 (&r)[kRegs], double c, double srA, uint32_t msign)
-{
-#pragma unroll
-    for (int j = 0; j < kRegs; ++j) r[j] = rot_diag(r[j], c, flip_if(srA, msign >> j), IMAG);
-}
-
-
-template <bool IMAG>
-__device__ __forceinline__ void mg_dispatch(int cx, double2 (&r)[kRegs], double c, double srA, uint32_t msign)
-{
-    switch (cx) {
-    case 0: mg_diag<IMAG>(r, c, srA, msign); break;
-    case 1: mg_rot<1, IMAG>(r, c, srA, msign); break;
-    case 2: mg_rot<2, IMAG>(r, c, srA, msign); break;
-    case 3: mg_rot<3, IMAG>(r, c, srA, msign); break;
-    case 4: mg_rot<4, IMAG>(r, c, srA, msign); break;
-    case 5: mg_rot<5, IMAG>(r, c, srA, msign); break;
-    case 6: mg_rot<6, IMAG>(r, c, srA, msign); break;
-    case 7: mg_rot<7, IMAG>(r, c, srA, msign); break;
-    case 8: mg_rot<8, IMAG>(r, c, srA, msign); break;
-    case 9: mg_rot<9, IMAG>(r, c, srA, msign); break;
-    case 10: mg_rot<10, IMAG>(r, c, srA, msign); break;
-    case 11: mg_rot<11, IMAG>(r, c, srA, msign); break;
-    case 12: mg_rot<12, IMAG>(r, c, srA, msign); break;
-    case 13: mg_rot<13, IMAG>(r, c, srA, msign); break;
-    case 14: mg_rot<14, IMAG>(r, c, srA, msign); break;
-    default: mg_rot<15, IMAG>(r, c, srA, msign); break;
-    }
-}
-
-// Compile-time rotation bodies.  KASE = cx | zr << 4 | imag << 8 fixes the
-// partner mask and every register's sign (the sign of register j is
-// parity(j & zr), since the register offsets are spanned by four vectors), so
-// the signs become negations of FMA operands instead of sign arithmetic.
-constexpr bool cpar(int v) { return __builtin_popcount(v) & 1; }
-
-template <int KASE>
-__device__ __forceinline__ void kase_body(double2 (&r)[kRegs], double c, double s)
-{
-    constexpr int CX = KASE & 15, ZR = (KASE >> 4) & 15;
-    constexpr bool IMAG = (KASE >> 8) & 1;
-    if constexpr (CX == 0) {
-        if constexpr (IMAG) {
-#pragma unroll
-            for (int j = 0; j < kRegs; ++j) {
-                const double sj = cpar(j & ZR) ? -s : s;
-                r[j] = make_double2(c * r[j].x - sj * r[j].y, c * r[j].y + sj * r[j].x);
-            }
-        } else {
-            const double cp = c + s, cm = c - s;
-#pragma unroll
-            for (int j = 0; j < kRegs; ++j) {
-                const double f = cpar(j & ZR) ? cm : cp;
-                r[j] = make_double2(f * r[j].x, f * r[j].y);
-            }
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < kRegs; ++j) {
-            if ((j ^ CX) > j) {
-                rot_pair(r[j], r[j ^ CX], c, cpar(j & ZR) ? -s : s, cpar((j ^ CX) & ZR) ? -s : s, IMAG);
-                __builtin_amdgcn_sched_barrier(0);
-            }
-        }
-    }
-}
-
-// Uniform branch tree over the nine bits of kase (one leaf per body).
-template <int BIT, int ACC>
-__device__ __forceinline__ void kase_dispatch(uint32_t kase, double2 (&r)[kRegs], double c, double s)
-{
-    if constexpr (BIT < 0) {
-        kase_body<ACC>(r, c, s);
-    } else {
-        if (kase & (1u << BIT))
-            kase_dispatch<BIT - 1, ACC | (1 << BIT)>(kase, r, c, s);
-        else
-            kase_dispatch<BIT - 1, ACC>(kase, r, c, s);
-    }
-}
-
-// MODE bit 0: prefetch the next coset into registers.
-// MODE bit 1: compile-time rotation bodies; (c, s) of the pass staged in LDS
-//             once per workgroup, thread signs precomputed as one bit mask.
-template <typename Amp, int B, int MODE>
-__global__ void __launch_bounds__(1 << (B - kRegDims))
-k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2 args, uint64_t ntiles)
-{
-    constexpr bool PF = MODE & 1;
-    constexpr bool CT = MODE & 2;
-    extern __shared__ unsigned char lds_raw[];
-    Amp *lds = reinterpret_cast<Amp *>(lds_raw);
-    __shared__ double2 tab[CT ? kMaxRun : 1];
-    const uint32_t t = threadIdx.x;
-    const int last = args.nmg - 1;
-    uint32_t tsb = 0;  // bit ri: parity(t & zt) of rotation ri
-    if constexpr (CT) {
-        const int nrot = args.mg[last].rot_begin + args.mg[last].rot_count;
-        if ((int)t < nrot) {
-            const RotDesc2 &d = args.rot[t];
-            const double2 cs = coef[d.k];
-            double sv = args.inverse ? -cs.y : cs.y;
-            if (d.flags & 2) sv = -sv;
-            tab[t] = make_double2(cs.x, sv);
-        }
-        for (int ri = 0; ri < nrot; ++ri) tsb |= (uint32_t)par32(t & args.rot[ri].zt) << ri;
-        __syncthreads();
-    }
-    uint64_t Lb0 = 0, LbL = 0;
-    {
-        const uint32_t b0 = deposit32(t, args.mg[0].npiv), bL = deposit32(t, args.mg[last].npiv);
-#pragma unroll
-        for (int i = 0; i < B; ++i) {
-            if ((b0 >> i) & 1) Lb0 ^= args.v[i];
-            if ((bL >> i) & 1) LbL ^= args.v[i];
-        }
-    }
-    Amp pf[kRegs];
-    uint64_t tile = blockIdx.x;
-    if (PF && tile < ntiles) {
-        const uint64_t y0 = deposit(tile, args.outer_mask) ^ Lb0;
-#pragma unroll
-        for (int j = 0; j < kRegs; ++j) pf[j] = psi[y0 ^ args.LU_first[j]];
-    }
-    for (; tile < ntiles; tile += gridDim.x) {
-        // keep the 2 x 16 per-register address terms from being hoisted out of
-        // the loop as 64 live VGPRs: recomputing them is two scalar-operand XORs
-        asm volatile("" : "+v"(Lb0), "+v"(LbL));
-        const uint64_t tb = deposit(tile, args.outer_mask);
-        double2 r[kRegs];
-        if (PF) {
-#pragma unroll
-            for (int j = 0; j < kRegs; ++j) r[j] = ld(pf[j]);
-            const uint64_t nt = tile + gridDim.x;
-            if (nt < ntiles) {
-                const uint64_t y0 = deposit(nt, args.outer_mask) ^ Lb0;
-#pragma unroll
-                for (int j = 0; j < kRegs; ++j) pf[j] = psi[y0 ^ args.LU_first[j]];
-            }
-        } else {
-            const uint64_t y0 = tb ^ Lb0;
-#pragma unroll
-            for (int j = 0; j < kRegs; ++j) r[j] = ld(psi[y0 ^ args.LU_first[j]]);
-        }
-        uint32_t bprev = 0;
-        for (int g = 0; g <= last; ++g) {
-            const MGDesc2 &m = args.mg[g];
-            const uint32_t bt = deposit32(t, m.npiv);
-            if (g > 0) {
-                const MGDesc2 &mp = args.mg[g - 1];
-#pragma unroll
-                for (int j = 0; j < kRegs; ++j) st(lds[bprev ^ mp.U[j]], r[j]);
-                __syncthreads();
-#pragma unroll
-                for (int j = 0; j < kRegs; ++j) r[j] = ld(lds[bt ^ m.U[j]]);
-                __syncthreads();
-            }
-            bprev = bt;
-            if constexpr (CT) {
-                for (int ri = m.rot_begin; ri < m.rot_begin + m.rot_count; ++ri) {
-                    const RotDesc2 &d = args.rot[ri];
-                    const double2 cs = tab[ri];
-                    const uint32_t sg = ((tsb >> ri) ^ (uint32_t)par64(tb & d.z)) & 1u;
-                    kase_dispatch<8, 0>(d.kase, r, cs.x, flip_if(cs.y, sg));
-                }
-            } else {
-                for (int ri = m.rot_begin; ri < m.rot_begin + m.rot_count; ++ri) {
-                    const RotDesc2 &d = args.rot[ri];
-                    const double2 cs = coef[d.k];
-                    double sr = args.inverse ? -cs.y : cs.y;
-                    if (d.flags & 2) sr = -sr;
-                    const int sg = par32(bt & d.zl) ^ par64(tb & d.z);
-                    const double srA = sg ? -sr : sr;
-                    if (d.flags & 1)
-                        mg_dispatch<true>(d.cx, r, cs.x, srA, d.msign);
-                    else
-                        mg_dispatch<false>(d.cx, r, cs.x, srA, d.msign);
-                }
-            }
-        }
-        const uint64_t yL = tb ^ LbL;
-#pragma unroll
-        for (int j = 0; j < kRegs; ++j) st(psi[yL ^ args.LU_last[j]], r[j]);
     }
 }
 
@@ -778,20 +588,6 @@ __global__ void k_frame_conjugate(const FrameRowDev *__restrict__ rows, int n, c
 }
 
 // ------------------------------------------------------ launch helpers
-inline bool hip_ok(hipError_t e, const char *what, cfh_status *st)
-{
-    if (e == hipSuccess) return true;
-    *st = set_error(CFH_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
-    return false;
-}
-
-cfh_status last_launch(const char *what)
-{
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return set_error(CFH_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
-    return CFH_OK;
-}
-
 size_t amp_bytes(int dtype) { return dtype == CFH_C64 ? 8 : 16; }
 
 template <typename Amp, int B>
@@ -824,74 +620,6 @@ cfh_status launch_pass(int b, uint64_t ntiles, hipStream_t s, Amp *psi, const do
     return last_launch("k_pass");
 }
 
-// Persistent grid: as many workgroups as can be resident at once (cached per
-// kernel, LDS size and device).
-unsigned resident_grid(const void *fn, int threads, size_t lds)
-{
-    static std::map<std::tuple<const void *, size_t, int>, unsigned> cache;
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    const auto key = std::make_tuple(fn, lds, dev);
-    auto it = cache.find(key);
-    if (it != cache.end()) return it->second;
-    int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess || per_cu < 1)
-        per_cu = 1;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
-    const unsigned g = (unsigned)(per_cu * cus);
-    cache[key] = g;
-    return g;
-}
-
-template <typename Amp, int B, int MODE>
-cfh_status launch_pass2_b(uint64_t ntiles, hipStream_t s, Amp *psi, const double2 *coef, const PassArgs2 &a)
-{
-    if constexpr (((size_t)1 << B) * sizeof(Amp) > 160 * 1024) {
-        return set_error(CFH_E_UNSUPPORTED, "tile_bits too large for LDS");
-    } else {
-        constexpr int T = 1 << (B - kRegDims);
-        const size_t lds = a.nmg > 1 ? ((size_t)1 << B) * sizeof(Amp) : 0;
-        const void *fn = reinterpret_cast<const void *>(&k_pass2<Amp, B, MODE>);
-        static bool attr = false;
-        if (!attr) {
-            // dynamic LDS may take what the kernel's static LDS leaves of the 160 KiB
-            hipFuncAttributes fa{};
-            cfh_status st = CFH_OK;
-            if (!hip_ok(hipFuncGetAttributes(&fa, fn), "k_pass2: hipFuncGetAttributes", &st)) return st;
-            if (!hip_ok(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                            (int)(160 * 1024 - fa.sharedSizeBytes)),
-                        "k_pass2: hipFuncSetAttribute", &st))
-                return st;
-            attr = true;
-        }
-        const unsigned grid = (unsigned)std::min<uint64_t>(ntiles, resident_grid(fn, T, lds));
-        hipLaunchKernelGGL((k_pass2<Amp, B, MODE>), dim3(grid), dim3(T), lds, s, psi, coef, a, ntiles);
-        return last_launch("k_pass2");
-    }
-}
-
-template <typename Amp, int B>
-cfh_status launch_pass2_m(uint64_t ntiles, hipStream_t s, Amp *psi, const double2 *coef, const PassArgs2 &a, int mode)
-{
-    switch (mode) {
-    case 1: return launch_pass2_b<Amp, B, 1>(ntiles, s, psi, coef, a);
-    case 2: return launch_pass2_b<Amp, B, 2>(ntiles, s, psi, coef, a);
-    default: return launch_pass2_b<Amp, B, 0>(ntiles, s, psi, coef, a);
-    }
-}
-
-// Workgroups of 2^(b-4) threads: b >= 10 keeps them at one full wave or more.
-template <typename Amp>
-cfh_status launch_pass2(uint64_t ntiles, hipStream_t s, Amp *psi, const double2 *coef, const PassArgs2 &a, int mode)
-{
-    switch (a.b) {
-    case 10: return launch_pass2_m<Amp, 10>(ntiles, s, psi, coef, a, mode);
-    case 11: return launch_pass2_m<Amp, 11>(ntiles, s, psi, coef, a, mode);
-    case 12: return launch_pass2_m<Amp, 12>(ntiles, s, psi, coef, a, mode);
-    case 13: return launch_pass2_m<Amp, 13>(ntiles, s, psi, coef, a, mode);
-    default: return set_error(CFH_E_UNSUPPORTED, "register-tiled pass needs tile_bits in 10..13");
-    }
-}
 
 template <typename Amp>
 cfh_status launch_ham(int b, uint64_t ntiles, unsigned grid, hipStream_t s, const Amp *psi, Amp *out,
@@ -1107,33 +835,49 @@ cfh_status cfh_plan_create(int n, int dtype, const cfh_pauli *rot, size_t m, con
     for (size_t i = 0; i < m; ++i) p->rot[i] = Pauli{rot[i].x, rot[i].z, rot[i].e & 3};
     if (!p->tu.unfused) {
         p->passes = plan_rotations(n, p->rot, p->tu);
+        const int b = p->tu.tile_bits;
+        if (p->tu.variant < 0 || p->tu.variant > 5)
+            return set_error(CFH_E_INVAL, "cfh_plan_create: unknown kernel variant");
+        if (p->tu.variant >= 2 && p->tu.variant <= 4 && (b < 10 || b > 13))
+            return set_error(CFH_E_UNSUPPORTED, "cfh_plan_create: the register-tiled kernel needs tile_bits in 10..13");
+        if (p->tu.variant == 5 && (b < 10 || b > 14))
+            return set_error(CFH_E_UNSUPPORTED, "cfh_plan_create: the half-tile kernel needs tile_bits in 10..14");
+        // default: register-tiled with compile-time bodies where the tile
+        // shape allows it (half-tile transposes for 2^14), LDS-staged otherwise
+        int v = p->tu.variant;
+        if (v == 0) v = b == 14 ? 5 : (b >= 10 && b <= 13) ? 4 : 1;
+        p->tu.variant = v;
+        p->mode2 = v == 2 ? 1 : v == 4 ? 2 : v == 5 ? 6 : 0;
+        if (v >= 2) {
+            // A run that needs more micro-groups than the kernel carries (long
+            // runs of dense masks) is split in two on the same tile basis; the
+            // halves keep the order of the run.
+            std::vector<PassPlan> fitted;
+            std::vector<PassPlan> todo(p->passes.rbegin(), p->passes.rend());
+            PassArgs2 fa, ia;
+            while (!todo.empty()) {
+                PassPlan pp = std::move(todo.back());
+                todo.pop_back();
+                if (build_pass_args2(pp, p->rot, false, v == 5, fa) && build_pass_args2(pp, p->rot, true, v == 5, ia)) {
+                    fitted.push_back(std::move(pp));
+                    p->args2.push_back(fa);
+                    p->args2_inv.push_back(ia);
+                    continue;
+                }
+                if (pp.rots.size() < 2)
+                    return set_error(CFH_E_INVAL, "cfh_plan_create: a rotation does not fit the register-tiled kernel");
+                PassPlan hi = pp;
+                const size_t half = pp.rots.size() / 2;
+                hi.rots.assign(pp.rots.begin() + (std::ptrdiff_t)half, pp.rots.end());
+                pp.rots.resize(half);
+                todo.push_back(std::move(hi));
+                todo.push_back(std::move(pp));
+            }
+            p->passes = std::move(fitted);
+            p->v2 = true;
+        }
         cfh_status st = build_pass_args(p->passes, p->rot, p->args);
         if (st) return st;
-        const int b = p->tu.tile_bits;
-        if (p->tu.variant < 0 || p->tu.variant > 4)
-            return set_error(CFH_E_INVAL, "cfh_plan_create: unknown kernel variant");
-        if (p->tu.variant >= 2 && (b < 10 || b > 13))
-            return set_error(CFH_E_UNSUPPORTED, "cfh_plan_create: the register-tiled kernel needs tile_bits in 10..13");
-        // default: register-tiled with compile-time bodies for complex128 where
-        // it applies, LDS-staged otherwise (measured faster for complex64 storage)
-        int v = p->tu.variant;
-        if (v == 0) v = (dtype == CFH_C128 && b >= 10 && b <= 13) ? 4 : 1;
-        p->tu.variant = v;
-        p->mode2 = v == 2 ? 1 : v == 4 ? 2 : 0;
-        if (v >= 2) {
-            p->v2 = true;
-            p->args2.resize(p->passes.size());
-            p->args2_inv.resize(p->passes.size());
-            for (size_t i = 0; i < p->passes.size() && p->v2; ++i)
-                p->v2 = build_pass_args2(p->passes[i], p->rot, false, p->args2[i]) &&
-                        build_pass_args2(p->passes[i], p->rot, true, p->args2_inv[i]);
-            if (!p->v2) {
-                if (p->tu.variant >= 2)
-                    return set_error(CFH_E_INVAL, "cfh_plan_create: a pass does not fit the register-tiled kernel");
-                p->args2.clear();
-                p->args2_inv.clear();
-            }
-        }
     }
     // The adjoint sweep keeps a tile of the state and one of lam in LDS, so it
     // has its own pass list on tiles of at most 2^12 (c128) / 2^13 (c64).

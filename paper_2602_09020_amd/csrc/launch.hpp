@@ -1,0 +1,32 @@
+// Host-side launch helpers shared by the translation units of libcfh.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "cfh_internal.hpp"
+
+namespace cfh {
+
+// True on hipSuccess; otherwise records the HIP error as CFH_E_HIP in *st.
+bool hip_ok(hipError_t e, const char *what, cfh_status *st);
+
+// Status of the last kernel launch (clears the HIP error state).
+cfh_status last_launch(const char *what);
+
+// Persistent grid: as many workgroups as can be resident at once (cached per
+// kernel, LDS size and device).
+unsigned resident_grid(const void *fn, int threads, size_t lds);
+
+// One register-tiled fused pass (k_pass2) over every coset of the pass's
+// tile subspace; mode bit 0 = prefetch the next coset, bit 1 = compile-time
+// rotation bodies.  Instantiated for double2 and float2 storage in their own
+// translation units.
+template <typename Amp>
+cfh_status launch_pass2(uint64_t ntiles, hipStream_t s, Amp *psi, const double2 *coef, const PassArgs2 &a,
+                        int mode);
+extern template cfh_status launch_pass2<double2>(uint64_t, hipStream_t, double2 *, const double2 *,
+                                                 const PassArgs2 &, int);
+extern template cfh_status launch_pass2<float2>(uint64_t, hipStream_t, float2 *, const double2 *,
+                                                const PassArgs2 &, int);
+
+} // namespace cfh

@@ -1,0 +1,5 @@
+// double2 instantiation of the register-tiled fused pass.
+#include "pass2.hpp"
+
+template cfh_status cfh::launch_pass2<double2>(uint64_t, hipStream_t, double2 *, const double2 *,
+                                                 const cfh::PassArgs2 &, int);

@@ -1,0 +1,5 @@
+// float2 instantiation of the register-tiled fused pass.
+#include "pass2.hpp"
+
+template cfh_status cfh::launch_pass2<float2>(uint64_t, hipStream_t, float2 *, const double2 *,
+                                                 const cfh::PassArgs2 &, int);

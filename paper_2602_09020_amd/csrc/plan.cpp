@@ -13,14 +13,15 @@ TuningResolved resolve_tuning(const cfh_tuning *t, int n, int dtype, int kind)
 {
     TuningResolved r;
     const bool c64 = dtype == CFH_C64;
-    // Defaults measured on MI355X at 28 qubits: complex128 runs best with the
-    // register-tiled kernel on 2^13-amplitude tiles and 8 contiguous
-    // amplitudes per chunk (one more free dimension per pass), complex64 with
-    // the LDS-staged kernel on 2^12 and 16-amplitude chunks.  Small states
-    // keep at least 512 tiles per pass so every CU gets work.  The adjoint
-    // holds two tiles in LDS and uses 2^11 (c128) / 2^12 (c64).  The
-    // read-only Hamiltonian passes use 2^12 / 2^13 tiles with 32-amplitude chunks.
-    int b = c64 ? 12 : 13;
+    // Defaults measured on MI355X at 28 qubits: the register-tiled kernel with
+    // 128-byte contiguous chunks (8 complex128 / 16 complex64 amplitudes),
+    // which leaves the most free dimensions per pass at full cache-line use;
+    // complex128 on 2^14-amplitude tiles (half-tile transposes), complex64 on
+    // 2^13.  Small states keep at least 512 tiles per pass so every CU gets
+    // work.  The adjoint holds two tiles in LDS and uses 2^11 (c128) / 2^12
+    // (c64).  The read-only Hamiltonian passes use 2^12 / 2^13 tiles with
+    // 32-amplitude chunks.
+    int b = c64 ? 13 : 14;
     if (kind == kTuneAdjoint) b = c64 ? 12 : 11;
     if (kind == kTuneHamiltonian) b = c64 ? 13 : 12;
     b = std::max(std::min(b, n - 9), std::min(n, 10));
@@ -180,7 +181,7 @@ std::vector<PassPlan> plan_rotations(int n, const std::vector<Pauli> &rot, const
     return out;
 }
 
-bool build_pass_args2(const PassPlan &pp, const std::vector<Pauli> &rot, bool inverse, PassArgs2 &a)
+bool build_pass_args2(const PassPlan &pp, const std::vector<Pauli> &rot, bool inverse, bool anchor, PassArgs2 &a)
 {
     std::memset(&a, 0, sizeof(a));
     const int b = pp.b;
@@ -199,20 +200,37 @@ bool build_pass_args2(const PassPlan &pp, const std::vector<Pauli> &rot, bool in
         if (!ok) return false;
         zl[i] = local_zmask(pp.v, rot[order[i]].z);
     }
-    // split into micro-groups of at most kRegDims local dimensions
+    // split into micro-groups of at most kRegDims local dimensions; with an
+    // anchor every group starts from the same vector, which keeps its pivot
+    // (the anchor bit) and stays register dimension 0 throughout the pass
+    uint64_t anc = 0;
+    if (anchor)
+        for (int i = 0; i < D && !anc; ++i) anc = xl[i];
     std::vector<Span> spans;
     std::vector<std::vector<int>> members;
+    auto open_group = [&]() {
+        spans.emplace_back();
+        members.emplace_back();
+        if (anc) spans.back().add(anc);
+    };
     for (int i = 0; i < D; ++i) {
-        uint64_t r = spans.empty() ? xl[i] : spans.back().reduce(xl[i]);
-        if (spans.empty() || (r && spans.back().dim() == kRegDims)) {
-            spans.emplace_back();
-            members.emplace_back();
-            r = xl[i];
+        if (spans.empty()) open_group();
+        uint64_t r = spans.back().reduce(xl[i]);
+        if (r && spans.back().dim() == kRegDims) {
+            open_group();
+            r = spans.back().reduce(xl[i]);
         }
         if (r) spans.back().add(r);
         members.back().push_back(i);
     }
+    if (spans.empty()) open_group();
     if ((int)spans.size() > kMaxMG) return false;
+    a.qbit = anc ? 63 - __builtin_clzll(anc) : -1;
+    auto compress = [&](uint32_t u) {
+        if (a.qbit < 0) return u;
+        const uint32_t lo = (1u << a.qbit) - 1;
+        return (u & lo) | ((u >> (a.qbit + 1)) << a.qbit);
+    };
     const uint32_t full = (uint32_t)((1ull << b) - 1);
     int ri = 0;
     for (size_t g = 0; g < spans.size(); ++g) {
@@ -230,6 +248,7 @@ bool build_pass_args2(const PassPlan &pp, const std::vector<Pauli> &rot, bool in
             for (int i = 0; i < kRegDims; ++i)
                 if ((j >> i) & 1) u ^= s.v[i];
             m.U[j] = (uint32_t)u;
+            m.UC[j] = compress(m.U[j]);
         }
         m.rot_begin = ri;
         m.rot_count = (int)members[g].size();

@@ -123,7 +123,8 @@ def test_rotation_errors():
                                     {"tile_bits": 9, "low_bits": 1, "lookahead": -1},
                                     {"variant": 1}, {"variant": 2, "tile_bits": 10, "low_bits": 2},
                                     {"variant": 3, "max_run": 5}, {"variant": 2, "lookahead": -1},
-                                    {"variant": 4, "max_run": 7}, {"variant": 4, "tile_bits": 10, "low_bits": 3}])
+                                    {"variant": 4, "max_run": 7}, {"variant": 4, "tile_bits": 10, "low_bits": 3},
+                                    {"variant": 5, "tile_bits": 10, "low_bits": 2}, {"variant": 5, "max_run": 9}])
 def test_config0_full_state_vs_oracle(dtype, tuning):
     """n = 10, 50-gate Clifford prefix, 200 JW rotations: Phi = C^dag psi."""
     w = W.config(0)
@@ -133,19 +134,21 @@ def test_config0_full_state_vs_oracle(dtype, tuning):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("variant", [1, 0, 4])
+@pytest.mark.parametrize("variant", [1, 0, 4, 5])
 @pytest.mark.parametrize("n,tb,lb", [(14, 12, 5), (14, 13, 6), (13, 9, 4), (15, 11, 3), (16, 14, 4), (5, 4, 2),
-                                     (3, 3, 1), (12, 10, 3), (13, 13, 4)])
+                                     (3, 3, 1), (12, 10, 3), (13, 13, 4), (17, 14, 3)])
 def test_ragged_tiles_vs_oracle(dtype, variant, n, tb, lb):
     """Several tiles per pass, a single whole-state tile, and tiny states."""
     if variant == 4 and not 10 <= tb <= 13:
         pytest.skip("the register-tiled kernels take tile_bits 10..13")
+    if variant == 5 and not 10 <= tb <= 14:
+        pytest.skip("the half-tile register-tiled kernel takes tile_bits 10..14")
     w = W.make_workload("ragged", n, seed=n, n_prefix=3 * n, n_rot=120 if n >= 4 else 0, n_ham=0)
     if n < 4:
         rng = np.random.default_rng(1)
         w.rot = rng.integers(0, 4, size=(40, n)).astype(np.uint8)
         w.theta = rng.uniform(-3, 3, size=40)
-    if dtype == torch.complex128 and tb > 13:
+    if dtype == torch.complex128 and tb > 13 and variant != 5:
         pytest.skip("2^14 complex128 amplitudes exceed one workgroup's LDS")
     psi, *_ = run_workload(w, dtype, {"tile_bits": tb, "low_bits": lb, "variant": variant})
     _, phi_ref = sim.simulate(w)
@@ -153,18 +156,20 @@ def test_ragged_tiles_vs_oracle(dtype, variant, n, tb, lb):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("tb,lb", [(10, 2), (11, 4), (12, 3), (13, 5)])
+@pytest.mark.parametrize("tb,lb", [(10, 2), (11, 4), (12, 3), (13, 5), (14, 3)])
 def test_dense_random_strings_every_body_vs_oracle(dtype, tb, lb):
-    """Uniformly random letters on 13 qubits: every partner mask, register sign
+    """Uniformly random letters on 14 qubits: every partner mask, register sign
     mask and real/imaginary phase of the register-tiled bodies occurs."""
-    n = 13
+    n = 14
     rng = np.random.default_rng(100 + tb)
     rows = rng.integers(0, 4, size=(1500, n)).astype(np.uint8)
     rows[::97] = np.where(rows[::97] == 1, 3, rows[::97])        # some diagonal strings (no X/Y)
     rows[::97] = np.where(rows[::97] == 2, 0, rows[::97])
     w = W.Workload("dense", n, 5, np.zeros((0, 3), np.int32), rows, rng.uniform(-np.pi, np.pi, size=rows.shape[0]),
                    np.zeros((0, n), np.uint8), np.zeros(0))
-    for variant in (3, 4):
+    for variant in (3, 4, 5):
+        if variant < 5 and tb > 13:
+            continue
         psi, *_ = run_workload(w, dtype, {"tile_bits": tb, "low_bits": lb, "variant": variant})
         _, phi_ref = sim.simulate(w)
         assert maxdiff(psi, phi_ref) <= TOL[dtype], variant
@@ -173,13 +178,20 @@ def test_dense_random_strings_every_body_vs_oracle(dtype, tb, lb):
 def test_plan_rejects_unsupported_tuning():
     rot = cfh.cfh_pauli_encode(np.array([[1, 3, 1, 0, 0, 0, 0, 0, 0, 0]], np.uint8))
     for tu, code in [({"variant": 2, "tile_bits": 8}, cfh.CFH_E_UNSUPPORTED), ({"variant": 7}, cfh.CFH_E_INVAL),
+                     ({"variant": 5, "tile_bits": 9}, cfh.CFH_E_UNSUPPORTED),
                      ({"block_threads": 512}, cfh.CFH_E_UNSUPPORTED)]:
         with pytest.raises(cfh.CfhError) as e:
             hybrid.Plan(10, torch.complex128, rot, tu)
         assert e.value.code == code
+    # 2^14-amplitude tiles only with the half-tile kernel (tile_bits is clamped to n)
+    rot16 = cfh.cfh_pauli_encode(np.array([[1, 3, 1] + [0] * 13], np.uint8))
+    with pytest.raises(cfh.CfhError) as e:
+        hybrid.Plan(16, torch.complex128, rot16, {"variant": 4, "tile_bits": 14})
+    assert e.value.code == cfh.CFH_E_UNSUPPORTED
+    assert hybrid.Plan(16, torch.complex128, rot16, {"variant": 5, "tile_bits": 14}).info()["tile_bits"] == 14
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5])
 def test_fused_equals_unfused_and_inverse_roundtrip(variant):
     w = W.config(3, n=18, n_rot=400, n_ham=10)
     psi_f, _, rot, _, plan, _, theta = run_workload(w, torch.complex128, {"variant": variant})

@@ -239,5 +239,7 @@ def test_autotune_candidates_respect_kernel_limits():
                 assert tu["low_bits"] < tu["tile_bits"] <= n
                 if tu["variant"] in (3, 4):
                     assert 10 <= tu["tile_bits"] <= 13
-                if dt == torch.complex128:
+                if tu["variant"] == 5:
+                    assert 10 <= tu["tile_bits"] <= 14
+                if dt == torch.complex128 and tu["variant"] == 1:
                     assert tu["tile_bits"] <= 13
