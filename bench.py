@@ -139,8 +139,11 @@ def main():
             plans.append(p)
         b.record(stream)
         ham = hybrid.Hamiltonian(n, dtype, terms, w.coeff)
+        c, d = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c.record(stream)
         ham.expval_async(psi, e_out)
-        return plans, ham, (a, b)
+        d.record(stream)
+        return plans, ham, (a, b, c, d)
 
     for _ in range(args.warmup):
         step()
@@ -152,7 +155,8 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed * 1e3 / args.steps
-    rot_ms = [a.elapsed_time(b) for _, _, (a, b) in keep]
+    rot_ms = [ev[0].elapsed_time(ev[1]) for _, _, ev in keep]
+    ex_ms = float(np.mean([ev[2].elapsed_time(ev[3]) for _, _, ev in keep]))
     plans, ham, _ = keep[-1]
     infos = [p.info() for p in plans]
     hinfo = ham.info()
@@ -200,7 +204,8 @@ def main():
         "fusion_depth": K / launches,
         "rotation_phase_ms": float(np.mean(rot_ms)),
         "plan_chunk": chunk,
-        "expval": {"value": energy, "passes": hinfo["n_passes"], "groups": hinfo["n_groups"]},
+        "expval": {"value": energy, "passes": hinfo["n_passes"], "groups": hinfo["n_groups"], "ms": ex_ms,
+                   "achieved_gbs": hinfo["hbm_bytes"] / (ex_ms * 1e-3) / 1e9},
         "plan_ms_whole_sequence": plan_ms,
     }
 

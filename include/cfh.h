@@ -220,11 +220,16 @@ cfh_status cfh_apply_plan(cfh_plan p, void *psi, const double *theta_dev, int in
 
 /* Prepare H = sum_j coeff[j] terms[j] (terms already conjugated through the
  * frame, e even) for expectation values and H*psi on n-qubit states.  Terms
- * are grouped by x mask and groups are packed into read-only LDS tile
- * passes.  Allocates device memory.  Errors as cfh_plan_create. */
+ * are grouped by x mask.  For <H> the terms are packed into read-only passes
+ * of the register-tiled kernel (at most 32 terms per pass on 2^b tiles,
+ * b >= 10; tuning variant 1 or smaller tiles select LDS-staged passes); H*psi
+ * always uses LDS-staged passes.  Allocates device memory.  Errors as
+ * cfh_plan_create. */
 cfh_status cfh_ham_create(int n, int dtype, const cfh_pauli *terms, const double *coeff, size_t m,
                           const cfh_tuning *tuning, cfh_ham *out);
 cfh_status cfh_ham_destroy(cfh_ham h);
+/* Read passes of one <H>, distinct x masks, and the HBM bytes those passes
+ * read (2^n * bytes per amplitude each).  Any pointer may be NULL. */
 cfh_status cfh_ham_info(cfh_ham h, int64_t *n_passes, int64_t *n_groups, double *hbm_bytes);
 
 /* out_dev[0] + i out_dev[1] = sum_j coeff_j <psi|P_j|psi> (Eq. chfsexp);

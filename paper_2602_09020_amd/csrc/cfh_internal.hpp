@@ -80,7 +80,7 @@ struct PassArgs {
 // thread index into the non-pivot local bits `npiv` of the micro-group.
 constexpr int kRegDims = 4;
 constexpr int kRegs = 1 << kRegDims;
-constexpr int kMaxMG = 8;
+constexpr int kMaxMG = 12;
 
 struct RotDesc2 {
     uint32_t zl;     // local z parity mask
@@ -151,7 +151,7 @@ struct TuningResolved {
     int tile_bits, low_bits, max_run, lookahead, unfused, block_threads, variant;
 };
 
-enum { kTuneForward = 0, kTuneAdjoint = 1, kTuneHamiltonian = 2 };
+enum { kTuneForward = 0, kTuneAdjoint = 1, kTuneHamiltonian = 2, kTuneMeasure = 3 };
 TuningResolved resolve_tuning(const cfh_tuning *t, int n, int dtype, int kind);
 
 // Builds the passes of a rotation sequence (the fusion planner).
@@ -168,7 +168,14 @@ struct HamPass {
     std::vector<uint64_t> v;
     std::vector<int> groups;
 };
-std::vector<HamPass> plan_hamiltonian(int n, const std::vector<HamGroup> &groups, const TuningResolved &tu);
+std::vector<HamPass> plan_hamiltonian(int n, const std::vector<HamGroup> &groups, const TuningResolved &tu,
+                                      int max_groups = kMaxGroupsPerPass, int max_terms = 1 << 30);
+// Order the terms idx of one pass (all commute inside a sum) so that
+// consecutive terms share register micro-groups: terms whose local x already
+// lies in the current 4-dimensional span first, then the dimension that
+// brings the most remaining terms in.
+std::vector<int> order_for_microgroups(const std::vector<uint64_t> &basis, const std::vector<Pauli> &p,
+                                      const std::vector<int> &idx, bool anchor);
 
 // Fill a kernel descriptor for one rotation inside pass `pp`.
 RotDesc make_rot_desc(const PassPlan &pp, const Pauli &p, int k);

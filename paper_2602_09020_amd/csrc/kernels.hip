@@ -728,18 +728,24 @@ struct cfh_plan_s {
 struct cfh_ham_s {
     int n = 0, dtype = 0;
     TuningResolved tu{};
-    std::vector<HamPass> passes;
+    std::vector<HamPass> passes;        // LDS-staged passes (H psi for the adjoint, small tiles)
     std::vector<HamPassArgs> args;
     HamGroupDev *groups = nullptr;
     HamTermDev *terms = nullptr;
-    double2 *partial = nullptr;  // grid entries
+    double2 *partial = nullptr;         // max(grid, kMeasureGrid) entries
     unsigned grid = 0;
     int64_t n_groups = 0;
+    // register-tiled measurement passes for <H> (used when mmode != 0)
+    std::vector<PassArgs2> margs;
+    double2 *mw = nullptr;              // per-term weight c_k i^{(e-|x&z|)}
+    int mmode = 0;
+    static constexpr unsigned kMeasureGrid = 2048;
     ~cfh_ham_s()
     {
         if (groups) (void)hipFree(groups);
         if (terms) (void)hipFree(terms);
         if (partial) (void)hipFree(partial);
+        if (mw) (void)hipFree(mw);
     }
 };
 
@@ -1059,9 +1065,66 @@ cfh_status cfh_ham_create(int n, int dtype, const cfh_pauli *terms, const double
                     "cfh_ham_create: hipMemcpy", &st))
             return st;
     }
+    // <H> on the register-tiled kernel: passes of at most kMaxRun terms on
+    // 2^b tiles (half-tile transposes at 2^14), terms ordered so consecutive
+    // ones share register micro-groups.  The LDS-staged passes above stay for
+    // H psi and for tiles below 2^10.
+    {
+        TuningResolved tm = resolve_tuning(tuning, n, dtype, kTuneMeasure);
+        if (tm.variant != 1 && tm.tile_bits >= 10 && tm.tile_bits <= 14 && m > 0) {
+            const bool anchor = tm.tile_bits == 14;
+            std::vector<HamGroup> mg;
+            for (const HamGroup &g : groups)
+                for (size_t i = 0; i < g.terms.size(); i += kMaxRun)
+                    mg.push_back(HamGroup{g.x, std::vector<int>(g.terms.begin() + (std::ptrdiff_t)i,
+                                                                g.terms.begin() + (std::ptrdiff_t)std::min(
+                                                                                      g.terms.size(), i + kMaxRun))});
+            std::vector<Pauli> tp(m);
+            for (size_t i = 0; i < m; ++i) tp[i] = Pauli{terms[i].x, terms[i].z, terms[i].e & 3};
+            std::vector<PassPlan> todo;
+            for (const HamPass &hp : plan_hamiltonian(n, mg, tm, kMaxGroupsPerPass, kMaxRun)) {
+                std::vector<int> idx;
+                for (int g : hp.groups) idx.insert(idx.end(), mg[g].terms.begin(), mg[g].terms.end());
+                PassPlan pp;
+                pp.b = hp.b;
+                pp.outer_mask = hp.outer_mask;
+                pp.v = hp.v;
+                pp.rots = order_for_microgroups(hp.v, tp, idx, anchor);
+                todo.push_back(std::move(pp));
+            }
+            std::reverse(todo.begin(), todo.end());
+            PassArgs2 a2;
+            while (!todo.empty()) {
+                PassPlan pp = std::move(todo.back());
+                todo.pop_back();
+                if (build_pass_args2(pp, tp, false, anchor, a2)) {
+                    h->margs.push_back(a2);
+                    continue;
+                }
+                if (pp.rots.size() < 2) return set_error(CFH_E_INVAL, "cfh_ham_create: a term does not fit the tile");
+                PassPlan hi = pp;
+                const size_t half = pp.rots.size() / 2;
+                hi.rots.assign(pp.rots.begin() + (std::ptrdiff_t)half, pp.rots.end());
+                pp.rots.resize(half);
+                todo.push_back(std::move(hi));
+                todo.push_back(std::move(pp));
+            }
+            std::vector<double2> w(m);
+            for (size_t i = 0; i < m; ++i) {
+                const int wp = (terms[i].e - popc(terms[i].x & terms[i].z)) & 3;  // i^wp
+                w[i] = make_double2(wp == 0 ? coeff[i] : wp == 2 ? -coeff[i] : 0.0,
+                                    wp == 1 ? coeff[i] : wp == 3 ? -coeff[i] : 0.0);
+            }
+            if (!hip_ok(hipMalloc(&h->mw, m * sizeof(double2)), "cfh_ham_create: hipMalloc", &st) ||
+                !hip_ok(hipMemcpy(h->mw, w.data(), m * sizeof(double2), hipMemcpyHostToDevice),
+                        "cfh_ham_create: hipMemcpy", &st))
+                return st;
+            h->mmode = anchor ? 14 : 10;
+        }
+    }
     h->grid = persistent_grid(1ull << (n - h->tu.tile_bits));
-    if (!hip_ok(hipMalloc(&h->partial, (size_t)h->grid * sizeof(double2)), "cfh_ham_create: hipMalloc", &st))
-        return st;
+    const size_t np = std::max<size_t>(h->grid, cfh_ham_s::kMeasureGrid);
+    if (!hip_ok(hipMalloc(&h->partial, np * sizeof(double2)), "cfh_ham_create: hipMalloc", &st)) return st;
     *out = h.release();
     return CFH_OK;
 }
@@ -1075,9 +1138,10 @@ cfh_status cfh_ham_destroy(cfh_ham h)
 cfh_status cfh_ham_info(cfh_ham h, int64_t *n_passes, int64_t *n_groups, double *hbm_bytes)
 {
     if (!h) return set_error(CFH_E_INVAL, "cfh_ham_info: null");
-    if (n_passes) *n_passes = (int64_t)h->args.size();
+    const size_t np = h->mmode ? h->margs.size() : h->args.size();  // read passes of one <H>
+    if (n_passes) *n_passes = (int64_t)np;
     if (n_groups) *n_groups = h->n_groups;
-    if (hbm_bytes) *hbm_bytes = (double)h->args.size() * (double)(1ull << h->n) * (double)amp_bytes(h->dtype);
+    if (hbm_bytes) *hbm_bytes = (double)np * (double)(1ull << h->n) * (double)amp_bytes(h->dtype);
     return CFH_OK;
 }
 
@@ -1085,6 +1149,22 @@ cfh_status cfh_expval_async(cfh_ham h, const void *psi, double *out_dev, void *s
 {
     if (!h || !psi || !out_dev) return set_error(CFH_E_INVAL, "cfh_expval_async: null argument");
     hipStream_t s = (hipStream_t)stream;
+    if (h->mmode) {
+        const unsigned G = cfh_ham_s::kMeasureGrid;
+        hipLaunchKernelGGL(k_zero_d, dim3((2 * G + 255) / 256), dim3(256), 0, s, (double *)h->partial,
+                           (int64_t)(2 * G));
+        cfh_status st = last_launch("k_zero_d");
+        if (st) return st;
+        for (const PassArgs2 &a : h->margs) {
+            const uint64_t ntiles = 1ull << (h->n - a.b);
+            st = h->dtype == CFH_C128
+                     ? launch_pass2(ntiles, s, (double2 *)const_cast<void *>(psi), h->mw, a, h->mmode, h->partial, G)
+                     : launch_pass2(ntiles, s, (float2 *)const_cast<void *>(psi), h->mw, a, h->mmode, h->partial, G);
+            if (st) return st;
+        }
+        hipLaunchKernelGGL(k_reduce_partial, dim3(1), dim3(256), 0, s, h->partial, (int)G, out_dev);
+        return last_launch("k_reduce_partial");
+    }
     const int cnt = (int)h->grid * 2;
     hipLaunchKernelGGL(k_zero_d, dim3((cnt + 255) / 256), dim3(256), 0, s, (double *)h->partial, (int64_t)cnt);
     cfh_status st = last_launch("k_zero_d");

@@ -17,16 +17,18 @@ cfh_status last_launch(const char *what);
 // kernel, LDS size and device).
 unsigned resident_grid(const void *fn, int threads, size_t lds);
 
-// One register-tiled fused pass (k_pass2) over every coset of the pass's
-// tile subspace; mode bit 0 = prefetch the next coset, bit 1 = compile-time
-// rotation bodies.  Instantiated for double2 and float2 storage in their own
-// translation units.
+// One register-tiled pass (k_pass2) over every coset of the pass's tile
+// subspace.  mode bit 0 = prefetch the next coset, bit 1 = compile-time
+// bodies, bit 2 = half-tile transposes, bit 3 = read-only measurement (adds
+// each workgroup's share of sum_k w_k <P_k> to partial[workgroup]; at most
+// max_grid workgroups when max_grid > 0).  Instantiated for double2 and float2
+// storage in their own translation units.
 template <typename Amp>
 cfh_status launch_pass2(uint64_t ntiles, hipStream_t s, Amp *psi, const double2 *coef, const PassArgs2 &a,
-                        int mode);
+                        int mode, double2 *partial = nullptr, unsigned max_grid = 0);
 extern template cfh_status launch_pass2<double2>(uint64_t, hipStream_t, double2 *, const double2 *,
-                                                 const PassArgs2 &, int);
+                                                 const PassArgs2 &, int, double2 *, unsigned);
 extern template cfh_status launch_pass2<float2>(uint64_t, hipStream_t, float2 *, const double2 *,
-                                                const PassArgs2 &, int);
+                                                const PassArgs2 &, int, double2 *, unsigned);
 
 } // namespace cfh

@@ -140,6 +140,56 @@ __device__ __forceinline__ void kase_dispatch(uint32_t kase, double2 (&r)[kRegs]
     }
 }
 
+// Read-only term bodies (expectation values).  For a term with partner mask CX
+// the thread's share of
+//   sum_y (-1)^{|y & z|} conj(psi_y) psi_{y ^ x}
+// is (thread and coset sign) * S, S = sum_j sigma_j conj(r_j) r_{j^CX} with
+// sigma_j = (-1)^{msign_j}.  The members j and j^CX of a pair give conjugate
+// products, so S = 2 sum_{j<j^CX} sigma_j Re(conj(r_j) r_{j^CX}) when
+// sigma_CX = +1 (sigma_0 = +1, so sigma_{j^CX} = sigma_j sigma_CX) and
+// 2i sum sigma_j Im(...) when sigma_CX = -1.  Only CX selects a body (16); the
+// register signs are sign-bit flips taken from the uniform msign.
+template <int CX>
+__device__ __forceinline__ void measure_cx(uint32_t msign, const double2 (&r)[kRegs], double wre, double wim,
+                                           double &accr, double &acci)
+{
+    double sum = 0.0;
+    if constexpr (CX == 0) {
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) sum += flip_if(r[j].x * r[j].x + r[j].y * r[j].y, msign >> j);
+        accr += wre * sum;
+        acci += wim * sum;
+    } else if ((msign >> CX) & 1) {
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j)
+            if ((j ^ CX) > j) sum += flip_if(r[j].x * r[j ^ CX].y - r[j].y * r[j ^ CX].x, msign >> j);
+        sum += sum;                 // value = w * (i * sum)
+        accr -= wim * sum;
+        acci += wre * sum;
+    } else {
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j)
+            if ((j ^ CX) > j) sum += flip_if(r[j].x * r[j ^ CX].x + r[j].y * r[j ^ CX].y, msign >> j);
+        sum += sum;
+        accr += wre * sum;
+        acci += wim * sum;
+    }
+}
+
+template <int BIT, int ACC>
+__device__ __forceinline__ void measure_dispatch(uint32_t cx, uint32_t msign, const double2 (&r)[kRegs], double wre,
+                                                 double wim, double &accr, double &acci)
+{
+    if constexpr (BIT < 0) {
+        measure_cx<ACC>(msign, r, wre, wim, accr, acci);
+    } else {
+        if (cx & (1u << BIT))
+            measure_dispatch<BIT - 1, ACC | (1 << BIT)>(cx, msign, r, wre, wim, accr, acci);
+        else
+            measure_dispatch<BIT - 1, ACC>(cx, msign, r, wre, wim, accr, acci);
+    }
+}
+
 // MODE bit 0: prefetch the next coset into registers.
 // MODE bit 1: compile-time rotation bodies; (c, s) of the pass staged in LDS
 //             once per workgroup, thread signs precomputed as one bit mask.
@@ -149,27 +199,41 @@ __device__ __forceinline__ void kase_dispatch(uint32_t kase, double2 (&r)[kRegs]
 //             the registers j with (j & 1) == h in both layouts, and each half
 //             moves through an LDS buffer of 2^(B-1) amplitudes indexed by the
 //             local coordinate with bit qbit removed.
+// MODE bit 3: read-only measurement (with bit 1): the descriptors are terms
+//             of an observable, coef holds their weights w_k = c_k i^{(e-|x&z|)},
+//             nothing is stored and each workgroup adds its share of
+//             sum_k w_k <psi|P_k|psi> to partial[blockIdx.x].
 template <typename Amp, int B, int MODE>
 __global__ void __launch_bounds__(1 << (B - kRegDims))
-k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2 args, uint64_t ntiles)
+k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2 args, uint64_t ntiles,
+        double2 *__restrict__ partial)
 {
     constexpr bool PF = MODE & 1;
     constexpr bool CT = MODE & 2;
     constexpr bool HALF = MODE & 4;
+    constexpr bool MEAS = MODE & 8;
+    static_assert(!MEAS || (CT && !PF), "measurement uses the compile-time bodies without prefetch");
+    constexpr int NW = (1 << (B - kRegDims)) / 64;  // waves per workgroup
     extern __shared__ unsigned char lds_raw[];
     Amp *lds = reinterpret_cast<Amp *>(lds_raw);
     __shared__ double2 tab[CT ? kMaxRun : 1];
+    __shared__ double2 red[MEAS ? NW : 1];
     const uint32_t t = threadIdx.x;
     const int last = args.nmg - 1;
     uint32_t tsb = 0;  // bit ri: parity(t & zt) of rotation ri
+    double accr = 0.0, acci = 0.0;
     if constexpr (CT) {
         const int nrot = args.mg[last].rot_begin + args.mg[last].rot_count;
         if ((int)t < nrot) {
             const RotDesc2 &d = args.rot[t];
             const double2 cs = coef[d.k];
-            double sv = args.inverse ? -cs.y : cs.y;
-            if (d.flags & 2) sv = -sv;
-            tab[t] = make_double2(cs.x, sv);
+            if constexpr (MEAS) {
+                tab[t] = cs;
+            } else {
+                double sv = args.inverse ? -cs.y : cs.y;
+                if (d.flags & 2) sv = -sv;
+                tab[t] = make_double2(cs.x, sv);
+            }
         }
         for (int ri = 0; ri < nrot; ++ri) tsb |= (uint32_t)par32(t & args.rot[ri].zt) << ri;
         __syncthreads();
@@ -190,6 +254,7 @@ k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2
 #pragma unroll
         for (int j = 0; j < kRegs; ++j) pf[j] = psi[y0 ^ args.LU_first[j]];
     }
+#pragma unroll 1
     for (; tile < ntiles; tile += gridDim.x) {
         // keep the 2 x 16 per-register address terms from being hoisted out of
         // the loop as 64 live VGPRs: recomputing them is two scalar-operand XORs
@@ -211,6 +276,7 @@ k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2
             for (int j = 0; j < kRegs; ++j) r[j] = ld(psi[y0 ^ args.LU_first[j]]);
         }
         uint32_t bprev = 0;
+#pragma unroll 1
         for (int g = 0; g <= last; ++g) {
             const MGDesc2 &m = args.mg[g];
             const uint32_t bt = deposit32(t, m.npiv);
@@ -240,7 +306,20 @@ k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2
                 }
             }
             bprev = bt;
-            if constexpr (CT) {
+            if constexpr (MEAS) {
+#pragma unroll 1
+                for (int ri = m.rot_begin; ri < m.rot_begin + m.rot_count; ++ri) {
+                    // the amplitudes do not change between terms: without this the
+                    // products of all 15 partner masks get hoisted out of the loop
+#pragma unroll
+                    for (int j = 0; j < kRegs; ++j) asm volatile("" : "+v"(r[j].x), "+v"(r[j].y));
+                    const RotDesc2 &d = args.rot[ri];
+                    const double2 w = tab[ri];
+                    const uint32_t sg = ((tsb >> ri) ^ (uint32_t)par64(tb & d.z)) & 1u;
+                    measure_dispatch<3, 0>(d.cx, d.msign, r, flip_if(w.x, sg), flip_if(w.y, sg), accr, acci);
+                }
+            } else if constexpr (CT) {
+#pragma unroll 1
                 for (int ri = m.rot_begin; ri < m.rot_begin + m.rot_count; ++ri) {
                     const RotDesc2 &d = args.rot[ri];
                     const double2 cs = tab[ri];
@@ -248,6 +327,7 @@ k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2
                     kase_dispatch<8, 0>(d.kase, r, cs.x, flip_if(cs.y, sg));
                 }
             } else {
+#pragma unroll 1
                 for (int ri = m.rot_begin; ri < m.rot_begin + m.rot_count; ++ri) {
                     const RotDesc2 &d = args.rot[ri];
                     const double2 cs = coef[d.k];
@@ -262,14 +342,33 @@ k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2
                 }
             }
         }
-        const uint64_t yL = tb ^ LbL;
+        if constexpr (!MEAS) {
+            const uint64_t yL = tb ^ LbL;
 #pragma unroll
-        for (int j = 0; j < kRegs; ++j) st(psi[yL ^ args.LU_last[j]], r[j]);
+            for (int j = 0; j < kRegs; ++j) st(psi[yL ^ args.LU_last[j]], r[j]);
+        }
+    }
+    if constexpr (MEAS) {
+        // fixed-order reduction: waves, then one add into this workgroup's slot
+        accr = wave_sum<64>(accr);
+        acci = wave_sum<64>(acci);
+        if ((t & 63) == 0) red[t >> 6] = make_double2(accr, acci);
+        __syncthreads();
+        if (t == 0) {
+            double sr = 0.0, si = 0.0;
+            for (int i = 0; i < NW; ++i) {
+                sr += red[i].x;
+                si += red[i].y;
+            }
+            partial[blockIdx.x].x += sr;
+            partial[blockIdx.x].y += si;
+        }
     }
 }
 
 template <typename Amp, int B, int MODE>
-cfh_status launch_pass2_b(uint64_t ntiles, hipStream_t s, Amp *psi, const double2 *coef, const PassArgs2 &a)
+cfh_status launch_pass2_b(uint64_t ntiles, hipStream_t s, Amp *psi, const double2 *coef, const PassArgs2 &a,
+                          double2 *partial, unsigned max_grid)
 {
     constexpr int LB = (MODE & 4) ? B - 1 : B;  // log2 amplitudes in the transpose buffer
     if constexpr (((size_t)1 << LB) * sizeof(Amp) > 160 * 1024) {
@@ -290,20 +389,24 @@ cfh_status launch_pass2_b(uint64_t ntiles, hipStream_t s, Amp *psi, const double
                 return st;
             attr = true;
         }
-        const unsigned grid = (unsigned)std::min<uint64_t>(ntiles, resident_grid(fn, T, lds));
-        hipLaunchKernelGGL((k_pass2<Amp, B, MODE>), dim3(grid), dim3(T), lds, s, psi, coef, a, ntiles);
+        unsigned grid = (unsigned)std::min<uint64_t>(ntiles, resident_grid(fn, T, lds));
+        if (max_grid) grid = std::min(grid, max_grid);
+        hipLaunchKernelGGL((k_pass2<Amp, B, MODE>), dim3(grid), dim3(T), lds, s, psi, coef, a, ntiles, partial);
         return last_launch("k_pass2");
     }
 }
 
 template <typename Amp, int B>
-cfh_status launch_pass2_m(uint64_t ntiles, hipStream_t s, Amp *psi, const double2 *coef, const PassArgs2 &a, int mode)
+cfh_status launch_pass2_m(uint64_t ntiles, hipStream_t s, Amp *psi, const double2 *coef, const PassArgs2 &a, int mode,
+                          double2 *partial, unsigned max_grid)
 {
     switch (mode) {
-    case 1: return launch_pass2_b<Amp, B, 1>(ntiles, s, psi, coef, a);
-    case 2: return launch_pass2_b<Amp, B, 2>(ntiles, s, psi, coef, a);
-    case 6: return launch_pass2_b<Amp, B, 6>(ntiles, s, psi, coef, a);
-    default: return launch_pass2_b<Amp, B, 0>(ntiles, s, psi, coef, a);
+    case 1: return launch_pass2_b<Amp, B, 1>(ntiles, s, psi, coef, a, partial, max_grid);
+    case 2: return launch_pass2_b<Amp, B, 2>(ntiles, s, psi, coef, a, partial, max_grid);
+    case 6: return launch_pass2_b<Amp, B, 6>(ntiles, s, psi, coef, a, partial, max_grid);
+    case 10: return launch_pass2_b<Amp, B, 10>(ntiles, s, psi, coef, a, partial, max_grid);
+    case 14: return launch_pass2_b<Amp, B, 14>(ntiles, s, psi, coef, a, partial, max_grid);
+    default: return launch_pass2_b<Amp, B, 0>(ntiles, s, psi, coef, a, partial, max_grid);
     }
 }
 
@@ -313,16 +416,18 @@ namespace cfh {
 
 // Workgroups of 2^(b-4) threads: b >= 10 keeps them at one full wave or more.
 template <typename Amp>
-cfh_status launch_pass2(uint64_t ntiles, hipStream_t s, Amp *psi, const double2 *coef, const PassArgs2 &a, int mode)
+cfh_status launch_pass2(uint64_t ntiles, hipStream_t s, Amp *psi, const double2 *coef, const PassArgs2 &a, int mode,
+                        double2 *partial, unsigned max_grid)
 {
     switch (a.b) {
-    case 10: return launch_pass2_m<Amp, 10>(ntiles, s, psi, coef, a, mode);
-    case 11: return launch_pass2_m<Amp, 11>(ntiles, s, psi, coef, a, mode);
-    case 12: return launch_pass2_m<Amp, 12>(ntiles, s, psi, coef, a, mode);
-    case 13: return launch_pass2_m<Amp, 13>(ntiles, s, psi, coef, a, mode);
+    case 10: return launch_pass2_m<Amp, 10>(ntiles, s, psi, coef, a, mode, partial, max_grid);
+    case 11: return launch_pass2_m<Amp, 11>(ntiles, s, psi, coef, a, mode, partial, max_grid);
+    case 12: return launch_pass2_m<Amp, 12>(ntiles, s, psi, coef, a, mode, partial, max_grid);
+    case 13: return launch_pass2_m<Amp, 13>(ntiles, s, psi, coef, a, mode, partial, max_grid);
     case 14:
         // 1024-thread workgroups; only the half-tile transposes fit 2^14 complex128 in LDS
-        if (mode == 6) return launch_pass2_b<Amp, 14, 6>(ntiles, s, psi, coef, a);
+        if (mode == 6) return launch_pass2_b<Amp, 14, 6>(ntiles, s, psi, coef, a, partial, max_grid);
+        if (mode == 14) return launch_pass2_b<Amp, 14, 14>(ntiles, s, psi, coef, a, partial, max_grid);
         return set_error(CFH_E_UNSUPPORTED, "tile_bits 14 needs the half-tile register-tiled kernel");
     default: return set_error(CFH_E_UNSUPPORTED, "register-tiled pass needs tile_bits in 10..14");
     }

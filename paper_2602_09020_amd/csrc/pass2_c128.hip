@@ -1,5 +1,5 @@
-// double2 instantiation of the register-tiled fused pass.
+// double2 instantiation of the register-tiled pass kernels.
 #include "pass2.hpp"
 
 template cfh_status cfh::launch_pass2<double2>(uint64_t, hipStream_t, double2 *, const double2 *,
-                                                 const cfh::PassArgs2 &, int);
+                                             const cfh::PassArgs2 &, int, double2 *, unsigned);

@@ -1,5 +1,5 @@
-// float2 instantiation of the register-tiled fused pass.
+// float2 instantiation of the register-tiled pass kernels.
 #include "pass2.hpp"
 
 template cfh_status cfh::launch_pass2<float2>(uint64_t, hipStream_t, float2 *, const double2 *,
-                                                 const cfh::PassArgs2 &, int);
+                                             const cfh::PassArgs2 &, int, double2 *, unsigned);

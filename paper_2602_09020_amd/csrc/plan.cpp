@@ -26,7 +26,7 @@ TuningResolved resolve_tuning(const cfh_tuning *t, int n, int dtype, int kind)
     if (kind == kTuneHamiltonian) b = c64 ? 13 : 12;
     b = std::max(std::min(b, n - 9), std::min(n, 10));
     r.tile_bits = (t && t->tile_bits > 0) ? t->tile_bits : b;
-    const int c_def = kind == kTuneHamiltonian ? 5 : (kind == kTuneForward && !c64) ? 3 : 4;
+    const int c_def = kind == kTuneHamiltonian ? 5 : ((kind == kTuneForward || kind == kTuneMeasure) && !c64) ? 3 : 4;
     r.low_bits = (t && t->low_bits > 0) ? t->low_bits : c_def;
     r.max_run = (t && t->max_run > 0) ? t->max_run : kMaxRun;
     r.lookahead = (t && t->lookahead != 0) ? t->lookahead : 512;
@@ -303,7 +303,8 @@ bool build_pass_args2(const PassPlan &pp, const std::vector<Pauli> &rot, bool in
     return true;
 }
 
-std::vector<HamPass> plan_hamiltonian(int n, const std::vector<HamGroup> &groups, const TuningResolved &tu)
+std::vector<HamPass> plan_hamiltonian(int n, const std::vector<HamGroup> &groups, const TuningResolved &tu,
+                                      int max_groups, int max_terms)
 {
     const int b = tu.tile_bits, c = tu.low_bits;
     const int G = (int)groups.size();
@@ -311,6 +312,7 @@ std::vector<HamPass> plan_hamiltonian(int n, const std::vector<HamGroup> &groups
     int left = G;
     std::vector<HamPass> out;
     while (left > 0) {
+        int nterms = 0;
         // Grow a b-dimensional subspace greedily.  Sparse x masks (JW strings)
         // are covered best by whole qubits (unit vectors: one tile then holds
         // every group inside those qubits); a dense x that would need too many
@@ -320,16 +322,21 @@ std::vector<HamPass> plan_hamiltonian(int n, const std::vector<HamGroup> &groups
         for (int j = 0; j < c; ++j) s.add(1ull << j);
         std::vector<int> chosen;
         std::vector<char> in(G, 0);
+        auto fits = [&](int g) { return nterms + (int)groups[g].terms.size() <= max_terms; };
         auto sweep = [&]() {
-            for (int g = 0; g < G && (int)chosen.size() < kMaxGroupsPerPass; ++g)
-                if (!done[g] && !in[g] && s.reduce(groups[g].x) == 0) { in[g] = 1; chosen.push_back(g); }
+            for (int g = 0; g < G && (int)chosen.size() < max_groups; ++g)
+                if (!done[g] && !in[g] && fits(g) && s.reduce(groups[g].x) == 0) {
+                    in[g] = 1;
+                    chosen.push_back(g);
+                    nterms += (int)groups[g].terms.size();
+                }
         };
         sweep();
-        while ((int)chosen.size() < kMaxGroupsPerPass && s.dim() < b) {
+        while ((int)chosen.size() < max_groups && nterms < max_terms && s.dim() < b) {
             int best = -1, best_cost = 1 << 30;
             uint64_t best_r = 0;
             for (int g = 0; g < G; ++g) {
-                if (done[g] || in[g]) continue;
+                if (done[g] || in[g] || !fits(g)) continue;
                 const uint64_t r = s.reduce(groups[g].x);
                 const int cost = popc(r);
                 if (cost < best_cost) { best_cost = cost; best = g; best_r = r; }
@@ -345,12 +352,71 @@ std::vector<HamPass> plan_hamiltonian(int n, const std::vector<HamGroup> &groups
             }
             sweep();
         }
+        if (chosen.empty()) {
+            // every remaining group is larger than max_terms on its own (the
+            // caller splits such groups); take one so the loop always ends
+            for (int g = 0; g < G && chosen.empty(); ++g)
+                if (!done[g]) {
+                    const uint64_t r = s.reduce(groups[g].x);
+                    if (r) s.add(r);
+                    chosen.push_back(g);
+                }
+        }
         HamPass hp;
         hp.b = b;
         finish_basis(s, n, b, hp.v, hp.outer_mask);
         for (int g : chosen) { done[g] = 1; --left; }
         hp.groups = std::move(chosen);
         out.push_back(std::move(hp));
+    }
+    return out;
+}
+
+std::vector<int> order_for_microgroups(const std::vector<uint64_t> &basis, const std::vector<Pauli> &p,
+                                      const std::vector<int> &idx, bool anchor)
+{
+    const int m = (int)idx.size();
+    std::vector<uint64_t> xl(m);
+    for (int i = 0; i < m; ++i) {
+        bool ok = false;
+        xl[i] = local_coords(basis, p[idx[i]].x, &ok);
+    }
+    uint64_t anc = 0;
+    if (anchor)
+        for (int i = 0; i < m && !anc; ++i) anc = xl[i];
+    std::vector<char> used(m, 0);
+    std::vector<int> out;
+    out.reserve(m);
+    Span s;
+    if (anc) s.add(anc);
+    int left = m;
+    while (left > 0) {
+        for (int i = 0; i < m; ++i)
+            if (!used[i] && s.reduce(xl[i]) == 0) {
+                used[i] = 1;
+                out.push_back(idx[i]);
+                --left;
+            }
+        if (!left) break;
+        if (s.dim() >= kRegDims) {
+            s = Span();
+            if (anc) s.add(anc);
+            continue;
+        }
+        // the dimension that brings the most remaining terms into the span
+        int best = -1, best_cov = -1;
+        for (int i = 0; i < m; ++i) {
+            if (used[i]) continue;
+            Span t = s;
+            t.add(s.reduce(xl[i]));
+            int cov = 0;
+            for (int j = 0; j < m; ++j) cov += !used[j] && t.reduce(xl[j]) == 0;
+            if (cov > best_cov) {
+                best_cov = cov;
+                best = i;
+            }
+        }
+        s.add(s.reduce(xl[best]));
     }
     return out;
 }

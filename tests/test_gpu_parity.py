@@ -232,6 +232,47 @@ def test_expval_config0_vs_oracle(dtype):
     assert abs(e.imag) <= (1e-12 if dtype == torch.complex128 else 1e-4) * scale
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n,tb,lb", [(14, 10, 3), (15, 12, 4), (16, 13, 3), (17, 14, 3), (15, 11, 5)])
+def test_expval_register_tiled_vs_oracle(dtype, n, tb, lb):
+    """<H> on the register-tiled read-only passes: JW terms, dense random terms,
+    diagonal terms and 40 terms sharing one x mask (more than one pass holds),
+    against the oracle's physical state and against the LDS-staged passes."""
+    rng = np.random.default_rng(n + tb)
+    w = W.make_workload("meas", n, seed=n, n_prefix=2 * n, n_rot=60, n_ham=150)
+    dense = rng.integers(0, 4, size=(80, n)).astype(np.uint8)
+    diag = np.where(rng.integers(0, 2, size=(20, n)) == 1, 3, 0).astype(np.uint8)
+    same = np.where(rng.integers(0, 2, size=(40, n)) == 1, 3, 0).astype(np.uint8)
+    same[:, 0] = 1
+    same[:, 3] = 2                                   # one x mask (qubits 0 and 3), 40 z masks
+    rows = np.concatenate([w.ham, dense, diag, same])
+    coeff = rng.normal(size=rows.shape[0])
+    frame, rot, _, plan, _ = hybrid.prepare(w, dtype)
+    psi = hybrid.new_state(n, dtype, index=w.init)
+    plan.apply(psi, torch.tensor(w.theta, device=DEV))
+    terms = frame.conjugate(cfh.cfh_pauli_encode(rows))
+    h4 = hybrid.Hamiltonian(n, dtype, terms, coeff, {"tile_bits": tb, "low_bits": lb})
+    # LDS-staged passes hold a whole tile in LDS: at most 2^13 complex128 amplitudes
+    h1 = hybrid.Hamiltonian(n, dtype, terms, coeff, {"tile_bits": min(tb, 13), "low_bits": lb, "variant": 1})
+    e4, e1 = h4.expval(psi), h1.expval(psi)
+    ref_psi, _ = sim.simulate(w)
+    e_ref = sim.energy(ref_psi, n, rows, coeff)
+    scale = np.abs(coeff).sum()
+    tol = (1e-12 if dtype == torch.complex128 else 1e-4) * scale
+    assert abs(e4.real - e_ref) <= tol and abs(e4.imag) <= tol
+    assert abs(e4 - e1) <= tol
+    assert h4.info()["n_passes"] >= (rows.shape[0] + 31) // 32
+
+
+def test_expval_register_tiled_is_deterministic():
+    w = W.config(1, n=20, n_rot=200)
+    frame, rot, terms, plan, ham = hybrid.prepare(w, torch.complex128)
+    psi = hybrid.new_state(w.n, torch.complex128, index=w.init)
+    plan.apply(psi, torch.tensor(w.theta, device=DEV))
+    vals = {ham.expval(psi) for _ in range(3)}
+    assert len(vals) == 1
+
+
 def test_expval_basis_closed_forms():
     """<k|Z^z|k> = (-1)^|z & k| and <k|P|k> = 0 for any X or Y letter."""
     n = 16
