@@ -304,12 +304,14 @@ def main():
         ws = W.batched_configs()
         out["batched"] = {"circuits": len(ws), "rotations": int(sum(x.n_rot for x in ws)),
                           "qubits": [int(min(x.n for x in ws)), int(max(x.n for x in ws))]}
-        for dt, tag, cands in ((torch.complex128, "c128", [{"tile_bits": 10, "batch_items": 32},
-                                                          {"tile_bits": 10, "batch_items": 128},
-                                                          {"tile_bits": 11, "batch_items": 64}]),
-                               (torch.complex64, "c64", [{"tile_bits": 11, "batch_items": 32},
-                                                        {"tile_bits": 11, "batch_items": 128},
-                                                        {"tile_bits": 12, "batch_items": 64}])):
+        for dt, tag, cands in ((torch.complex128, "c128", [{"tile_bits": 10, "batch_items": 128, "group_mib": 0},
+                                                          {"tile_bits": 10, "batch_items": 128, "group_mib": 192},
+                                                          {"tile_bits": 11, "batch_items": 64, "group_mib": 128},
+                                                          {"tile_bits": 10, "batch_items": 64, "group_mib": 96}]),
+                               (torch.complex64, "c64", [{"tile_bits": 11, "batch_items": 128, "group_mib": 0},
+                                                        {"tile_bits": 11, "batch_items": 128, "group_mib": 192},
+                                                        {"tile_bits": 12, "batch_items": 64, "group_mib": 128},
+                                                        {"tile_bits": 11, "batch_items": 64, "group_mib": 96}])):
             t0 = time.perf_counter()
             tu = autotune.tune_batch(ws, dt, candidates=cands, use_cache=False)
             tune_s = time.perf_counter() - t0
@@ -327,10 +329,14 @@ def main():
                 ms = a.elapsed_time(b)
                 lat = (r["t_end"].astype(np.float64) - r["t_start"].astype(np.float64)) / r["tick_hz"] * 1e3
                 rots = out["batched"]["rotations"] * (2 if wg else 1)
+                binfo = B.info()
+                nbytes = binfo["bytes_grad" if wg else "bytes_fwd"]
                 res["forward_and_adjoint" if wg else "forward"] = {
                     "ms": ms, "rotations_per_s": rots / (ms * 1e-3),
+                    "algorithmic_gb": nbytes / 1e9, "achieved_gbs": nbytes / (ms * 1e-3) / 1e9,
                     "p50_circuit_ms": float(np.percentile(lat, 50)), "p99_circuit_ms": float(np.percentile(lat, 99))}
             res["tuning"] = tu
+            res["cache_groups"] = B.info()["n_groups"]
             res["tune_s"] = tune_s
             res["state_gb"] = B.info()["state_bytes"] / 1e9
             out["batched"][tag] = res

@@ -91,6 +91,9 @@ typedef struct cfh_tuning {
                               5 = as 4 with the transposes between micro-groups done in two
                               halves through half the LDS (tile_bits 10..14) */
     int32_t batch_items;   /* batched runs: at most this many work items per pass (0 = 32) */
+    int32_t group_mib;     /* batched runs: circuits are scheduled in consecutive groups whose
+                              state and lam vectors fit this many MiB (so the 256 MiB Infinity Cache
+                              can keep a group resident across its levels); <= 0 = one group */
 } cfh_tuning;
 
 typedef struct cfh_frame_s *cfh_frame;
@@ -292,9 +295,12 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
                             cfh_batch *out);
 cfh_status cfh_batch_destroy(cfh_batch b);
 
-/* Work items (gradient run), passes, rotations and state bytes of a batch. */
+/* Work items (gradient run), passes, rotations, state bytes, the
+ * algorithmic HBM bytes of one forward run and of one gradient run (every
+ * pass reads and writes its vectors once), and the number of cache groups
+ * the circuits are scheduled in.  Any pointer may be NULL. */
 cfh_status cfh_batch_info(cfh_batch b, int64_t *n_items_grad, int64_t *n_passes, int64_t *n_rot,
-                          double *state_bytes);
+                          double *state_bytes, double *bytes_fwd, double *bytes_grad, int32_t *n_groups);
 
 /* Replace all angles (host array, concatenated in circuit order); synchronous. */
 cfh_status cfh_batch_set_theta(cfh_batch b, const double *theta_host);

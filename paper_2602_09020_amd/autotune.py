@@ -111,7 +111,8 @@ def tune_plan(n: int, dtype, rot: np.ndarray, theta: np.ndarray, candidates: Opt
 def batch_candidates(dtype) -> List[dict]:
     c128 = hybrid.state_dtype(dtype) == _c.CFH_C128
     tbs = (9, 10, 11) if c128 else (10, 11, 12)
-    return [{"tile_bits": tb, "batch_items": it} for tb in tbs for it in (16, 64)]
+    return [{"tile_bits": tb, "batch_items": it, "group_mib": gm} for tb in tbs for it in (16, 64)
+            for gm in (0, 128, 192)]
 
 
 def tune_batch(workloads, dtype, candidates: Optional[Iterable[dict]] = None, with_grad: bool = True,

@@ -33,7 +33,8 @@ class cfh_pauli(C.Structure):
 class cfh_tuning(C.Structure):
     _fields_ = [("tile_bits", C.c_int32), ("low_bits", C.c_int32), ("max_run", C.c_int32),
                 ("lookahead", C.c_int32), ("unfused", C.c_int32), ("block_threads", C.c_int32),
-                ("variant", C.c_int32), ("batch_items", C.c_int32)]
+                ("variant", C.c_int32), ("batch_items", C.c_int32),
+                ("group_mib", C.c_int32)]
 
 
 class cfh_circuit_desc(C.Structure):
@@ -85,7 +86,8 @@ _SIGS = {
     "cfh_adjoint_grad": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cfh_batch_create": (C.c_int32, [_vp, C.c_int, C.c_int, _P(cfh_tuning), _P(_vp)]),
     "cfh_batch_destroy": (C.c_int32, [_vp]),
-    "cfh_batch_info": (C.c_int32, [_vp, _P(C.c_int64), _P(C.c_int64), _P(C.c_int64), _P(C.c_double)]),
+    "cfh_batch_info": (C.c_int32, [_vp, _P(C.c_int64), _P(C.c_int64), _P(C.c_int64), _P(C.c_double),
+                                   _P(C.c_double), _P(C.c_double), _P(C.c_int32)]),
     "cfh_batch_set_theta": (C.c_int32, [_vp, _vp]),
     "cfh_batch_run": (C.c_int32, [_vp, C.c_int, _vp]),
     "cfh_batch_graph_launch": (C.c_int32, [_vp, C.c_int, _vp]),
@@ -365,8 +367,11 @@ def cfh_batch_destroy(b: int) -> None:
 
 def cfh_batch_info(b: int) -> dict:
     it, np_, nr, sb = C.c_int64(), C.c_int64(), C.c_int64(), C.c_double()
-    _call("cfh_batch_info", b, C.byref(it), C.byref(np_), C.byref(nr), C.byref(sb))
-    return {"n_items_grad": it.value, "n_passes": np_.value, "n_rot": nr.value, "state_bytes": sb.value}
+    bf, bg, ng = C.c_double(), C.c_double(), C.c_int32()
+    _call("cfh_batch_info", b, C.byref(it), C.byref(np_), C.byref(nr), C.byref(sb), C.byref(bf), C.byref(bg),
+          C.byref(ng))
+    return {"n_items_grad": it.value, "n_passes": np_.value, "n_rot": nr.value, "state_bytes": sb.value,
+            "bytes_fwd": bf.value, "bytes_grad": bg.value, "n_groups": ng.value}
 
 
 def cfh_batch_set_theta(b: int, theta: np.ndarray) -> None:

@@ -110,18 +110,33 @@ __global__ void __launch_bounds__(kBThreads) k_batch_level(const BatchArgs A, co
     double eacc = 0.0;
     __syncthreads();
 
+    // local element a = t + k*T maps to base ^ Lt ^ Lk[k]: the thread part
+    // (bits below log2 T) and the register part are disjoint, so their images
+    // under the basis combine by XOR
+    constexpr int LT = 8;
+    static_assert(T == 1 << LT, "work items use 256 threads");
+    constexpr int KMAX = NMAX > T ? NMAX / T : 1;
+    uint64_t Lt = 0;
+    for (int i = 0; i < LT && i < b; ++i)
+        if ((t >> i) & 1) Lt ^= P.v[i];
+    uint64_t Lk[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        uint64_t y = 0;
+        for (int i = LT; i < b; ++i)
+            if ((k >> (i - LT)) & 1) y ^= P.v[i];
+        Lk[k] = y;
+    }
     for (uint64_t tile = tile0; tile < tile1; ++tile) {
         const uint64_t base = deposit(tile, P.outer_mask);
-        // global index of local element a
-        auto gidx = [&](int a) {
-            uint64_t y = base;
-            for (int i = 0; i < b; ++i)
-                if ((a >> i) & 1) y ^= P.v[i];
-            return y;
-        };
+        // global index of this thread's k-th element a = t + k*T
+        auto gk = [&](int k) { return base ^ Lt ^ Lk[k]; };
         if (P.type == kPassFwd) {
-            for (int a = t; a < N; a += T) {
-                const uint64_t y = gidx(a);
+            #pragma unroll
+            for (int k = 0; k < KMAX; ++k) {
+                const int a = t + k * T;
+                if (a >= N) break;
+                const uint64_t y = gk(k);
                 if (P.flags & kFlagInit) st(tp[a], make_double2(y == C.init ? 1.0 : 0.0, 0.0));
                 else tp[a] = psi[y];
             }
@@ -154,11 +169,24 @@ __global__ void __launch_bounds__(kBThreads) k_batch_level(const BatchArgs A, co
                 }
                 __syncthreads();
             }
-            for (int a = t; a < N; a += T) psi[gidx(a)] = tp[a];
+            #pragma unroll
+            for (int k = 0; k < KMAX; ++k) {
+                const int a = t + k * T;
+                if (a >= N) break;
+                psi[gk(k)] = tp[a];
+            }
         } else if (P.type == kPassHam) {
-            for (int a = t; a < N; a += T) tp[a] = psi[gidx(a)];
+            #pragma unroll
+            for (int k = 0; k < KMAX; ++k) {
+                const int a = t + k * T;
+                if (a >= N) break;
+                tp[a] = psi[gk(k)];
+            }
             __syncthreads();
-            for (int a = t; a < N; a += T) {
+            #pragma unroll
+            for (int k = 0; k < KMAX; ++k) {
+                const int a = t + k * T;
+                if (a >= N) break;
                 double ar = 0.0, ai = 0.0;
                 for (int g = P.first; g < P.first + P.count; ++g) {
                     const HamGroupDev G = A.groups[g];
@@ -170,7 +198,7 @@ __global__ void __launch_bounds__(kBThreads) k_batch_level(const BatchArgs A, co
                         ai += sg * (tm.wre * v.y + tm.wim * v.x);
                     }
                 }
-                const uint64_t y = gidx(a);
+                const uint64_t y = gk(k);
                 double2 o = make_double2(ar, ai);
                 if (P.flags & kFlagAccumulate) {
                     const double2 p = ld(lam[y]);
@@ -185,8 +213,11 @@ __global__ void __launch_bounds__(kBThreads) k_batch_level(const BatchArgs A, co
                 }
             }
         } else {  // adjoint
-            for (int a = t; a < N; a += T) {
-                const uint64_t y = gidx(a);
+            #pragma unroll
+            for (int k = 0; k < KMAX; ++k) {
+                const int a = t + k * T;
+                if (a >= N) break;
+                const uint64_t y = gk(k);
                 tp[a] = psi[y];
                 tl[a] = lam[y];
             }
@@ -239,8 +270,11 @@ __global__ void __launch_bounds__(kBThreads) k_batch_level(const BatchArgs A, co
                 if ((t & 63) == 0) wacc[ri][t >> 6] += g;
                 __syncthreads();
             }
-            for (int a = t; a < N; a += T) {
-                const uint64_t y = gidx(a);
+            #pragma unroll
+            for (int k = 0; k < KMAX; ++k) {
+                const int a = t + k * T;
+                if (a >= N) break;
+                const uint64_t y = gk(k);
                 psi[y] = tp[a];
                 lam[y] = tl[a];
             }
@@ -327,6 +361,8 @@ struct cfh_batch_s {
     };
     std::vector<Level> levels[2];   // [0] forward + energy, [1] with gradients
     int64_t n_items[2] = {0, 0};
+    int n_groups = 0;               // cache groups of circuits
+    double bytes[2] = {0.0, 0.0};   // algorithmic HBM bytes of one forward / gradient run
     void *arena = nullptr;
     BPass *d_passes = nullptr;
     BCirc *d_circs = nullptr;
@@ -536,28 +572,63 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
     B->total_amp = amp;
     // level tables: items of pass `lv` of every circuit, then the passes of the
     // level whose partial sums are reduced (adjoint passes, the energy pass)
+    // Circuits run in consecutive groups whose psi and lam vectors fit the
+    // cache budget, so a group's vectors stay in the Infinity Cache across its
+    // levels; all levels of one group precede the next group.
+    const int gm = tuning ? tuning->group_mib : 0;
+    const int64_t budget = gm <= 0 ? INT64_MAX : (int64_t)gm << 20;
+    std::vector<std::pair<int, int>> cgroups;
+    {
+        int c0 = 0;
+        int64_t acc = 0;
+        for (int c = 0; c < count; ++c) {
+            const int64_t bytes = 2 * ((int64_t)ab << circs[c].n);
+            if (c > c0 && acc + bytes > budget) {
+                cgroups.push_back({c0, c});
+                c0 = c;
+                acc = 0;
+            }
+            acc += bytes;
+        }
+        cgroups.push_back({c0, count});
+    }
     std::vector<BItem> items[2];
     std::vector<int> red[2];
     for (int g = 0; g < 2; ++g) {
         const auto &chains = g ? chain_grad : chain_fwd;
-        size_t maxlen = 0;
-        for (auto &ch : chains) maxlen = std::max(maxlen, ch.size());
-        for (size_t lv = 0; lv < maxlen; ++lv) {
-            cfh_batch_s::Level L{(int64_t)items[g].size(), 0, (int64_t)red[g].size(), 0};
-            for (int c = 0; c < count; ++c) {
-                if (lv >= chains[c].size()) continue;
-                const int p = chains[c][lv];
-                for (int i = 0; i < B->passes[p].nitems; ++i) items[g].push_back(BItem{p, i});
-                const BPass &P = B->passes[p];
-                const bool ends = g ? P.end_flag_grad : (P.flags & kFlagEnd);
-                if (P.type == kPassAdj || (P.flags & kFlagEnergy) || ends) red[g].push_back(p);
+        for (const auto &cg : cgroups) {
+            size_t maxlen = 0;
+            for (int c = cg.first; c < cg.second; ++c) maxlen = std::max(maxlen, chains[c].size());
+            for (size_t lv = 0; lv < maxlen; ++lv) {
+                cfh_batch_s::Level L{(int64_t)items[g].size(), 0, (int64_t)red[g].size(), 0};
+                for (int c = cg.first; c < cg.second; ++c) {
+                    if (lv >= chains[c].size()) continue;
+                    const int p = chains[c][lv];
+                    for (int i = 0; i < B->passes[p].nitems; ++i) items[g].push_back(BItem{p, i});
+                    const BPass &P = B->passes[p];
+                    const bool ends = g ? P.end_flag_grad : (P.flags & kFlagEnd);
+                    if (P.type == kPassAdj || (P.flags & kFlagEnergy) || ends) red[g].push_back(p);
+                }
+                L.item_cnt = (int64_t)items[g].size() - L.item_off;
+                L.red_cnt = (int64_t)red[g].size() - L.red_off;
+                B->levels[g].push_back(L);
             }
-            L.item_cnt = (int64_t)items[g].size() - L.item_off;
-            L.red_cnt = (int64_t)red[g].size() - L.red_off;
-            B->levels[g].push_back(L);
         }
         B->n_items[g] = (int64_t)items[g].size();
     }
+    B->n_groups = (int)cgroups.size();
+    // algorithmic bytes: a rotation pass reads and writes psi (the first one
+    // only writes), a Hamiltonian pass reads psi and writes lam (and reads it
+    // when accumulating), an adjoint pass reads and writes psi and lam
+    for (int g = 0; g < 2; ++g)
+        for (int c = 0; c < count; ++c)
+            for (int p : (g ? chain_grad : chain_fwd)[c]) {
+                const BPass &P = B->passes[p];
+                const double S = (double)((int64_t)ab << circs[c].n);
+                B->bytes[g] += P.type == kPassFwd ? ((P.flags & kFlagInit) ? 1.0 : 2.0) * S
+                               : P.type == kPassHam ? ((P.flags & kFlagAccumulate) ? 3.0 : 2.0) * S
+                                                    : 4.0 * S;
+            }
 
     // one device arena
     const int npass = (int)B->passes.size();
@@ -615,13 +686,17 @@ cfh_status cfh_batch_destroy(cfh_batch b)
     return CFH_OK;
 }
 
-cfh_status cfh_batch_info(cfh_batch b, int64_t *n_items_grad, int64_t *n_passes, int64_t *n_rot, double *state_bytes)
+cfh_status cfh_batch_info(cfh_batch b, int64_t *n_items_grad, int64_t *n_passes, int64_t *n_rot, double *state_bytes,
+                          double *bytes_fwd, double *bytes_grad, int32_t *n_groups)
 {
     if (!b) return set_error(CFH_E_INVAL, "cfh_batch_info: null batch");
     if (n_items_grad) *n_items_grad = b->n_items[1];
     if (n_passes) *n_passes = (int64_t)b->passes.size();
     if (n_rot) *n_rot = b->total_rot;
     if (state_bytes) *state_bytes = (double)b->total_amp * (b->dtype == CFH_C64 ? 8 : 16);
+    if (bytes_fwd) *bytes_fwd = b->bytes[0];
+    if (bytes_grad) *bytes_grad = b->bytes[1];
+    if (n_groups) *n_groups = b->n_groups;
     return CFH_OK;
 }
 

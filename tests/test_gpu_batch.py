@@ -66,6 +66,26 @@ def test_batch_matches_single_circuit_path():
         assert np.abs(theta.grad.cpu().numpy() - r["grad"][i]).max() <= 1e-11
 
 
+def test_batch_cache_groups_give_identical_results():
+    """Scheduling circuits in cache groups changes only the order of levels:
+    every circuit's passes and reductions are the same, so results are bitwise
+    equal to the single-group schedule."""
+    ws = W.batched_configs(seed=9, count=10, n_range=(12, 16), r_range=(60, 200), n_ham=30)
+    ref = hybrid.Batch(ws, torch.complex128, {"group_mib": 0})
+    ref.run(with_grad=True)
+    r0 = ref.results()
+    for gm in (1, 4):
+        B = hybrid.Batch(ws, torch.complex128, {"group_mib": gm})
+        assert B.info()["n_groups"] > 1
+        B.run(with_grad=True)
+        r = B.results()
+        assert np.array_equal(r["energy"], r0["energy"])
+        for i in range(len(ws)):
+            assert np.array_equal(r["grad"][i], r0["grad"][i])
+    info = ref.info()
+    assert info["n_groups"] == 1 and info["bytes_grad"] > info["bytes_fwd"] > 0
+
+
 def test_batch_hipgraph_replays_are_deterministic():
     ws = W.batched_configs(seed=5, count=12, n_range=(12, 15), r_range=(60, 200), n_ham=30)
     B = hybrid.Batch(ws, torch.complex128)
