@@ -86,7 +86,7 @@ struct RotDesc2 {
     uint32_t zl;     // local z parity mask
     uint16_t msign;  // bit j = parity(U[j] & zl)
     uint8_t cx;      // partner mask in register coordinates, 0 = diagonal
-    uint8_t flags;   // bit 0: beta imaginary (w odd); bit 1: negate (w & 2)
+    uint8_t flags;   // bit 0: beta imaginary (w odd); bit 1: negate (w & 2); bit 2: i^{(e-|x&z|)} negative
     uint64_t z;      // global z (coset base sign)
     int32_t k;       // rotation index
     uint32_t zt;     // thread-index parity mask: parity(t & zt) = parity(bt & zl)
@@ -151,7 +151,7 @@ struct TuningResolved {
     int tile_bits, low_bits, max_run, lookahead, unfused, block_threads, variant;
 };
 
-enum { kTuneForward = 0, kTuneAdjoint = 1, kTuneHamiltonian = 2, kTuneMeasure = 3 };
+enum { kTuneForward = 0, kTuneAdjoint = 1, kTuneHamiltonian = 2, kTuneMeasure = 3, kTuneAdjoint2 = 4 };
 TuningResolved resolve_tuning(const cfh_tuning *t, int n, int dtype, int kind);
 
 // Builds the passes of a rotation sequence (the fusion planner).

@@ -716,8 +716,10 @@ struct cfh_plan_s {
     double2 *coef = nullptr;     // device, m entries
     double *gpart = nullptr;     // device, adj_grid * kMaxRun
     unsigned adj_grid = 0;
-    std::vector<PassArgs> adj_args;       // passes of the adjoint sweep (two LDS tiles)
+    std::vector<PassArgs> adj_args;       // passes of the LDS-staged adjoint sweep (two LDS tiles)
     int adj_b = 0;
+    std::vector<PassArgs2> adj2_args;     // register-tiled adjoint sweep: inverse-order descriptors
+    static constexpr unsigned kAdj2Grid = 2048;
     ~cfh_plan_s()
     {
         if (coef) (void)hipFree(coef);
@@ -842,6 +844,7 @@ cfh_status cfh_plan_create(int n, int dtype, const cfh_pauli *rot, size_t m, con
     if (!p->tu.unfused) {
         p->passes = plan_rotations(n, p->rot, p->tu);
         const int b = p->tu.tile_bits;
+        if (p->tu.variant == 6) p->tu.variant = 0;  // register-tiled adjoint; default forward kernel
         if (p->tu.variant < 0 || p->tu.variant > 5)
             return set_error(CFH_E_INVAL, "cfh_plan_create: unknown kernel variant");
         if (p->tu.variant >= 2 && p->tu.variant <= 4 && (b < 10 || b > 13))
@@ -902,13 +905,44 @@ cfh_status cfh_plan_create(int n, int dtype, const cfh_pauli *rot, size_t m, con
         }
         p->adj_b = ta.tile_bits;
     }
+    // Register-tiled adjoint: psi and lam of a coset in registers, both moved
+    // through LDS between micro-groups (half-tile transposes), so it has its
+    // own pass list on 2^13 (c128) / 2^14 (c64) tiles.  Opt-in (tuning
+    // variant 6 selects it for the adjoint; the forward pass then uses the
+    // default kernel) until its parity is established.
+    const bool reg_adjoint = tuning && tuning->variant == 6;
+    if (reg_adjoint && !p->rot.empty()) {
+        TuningResolved t2 = resolve_tuning(tuning, n, dtype, kTuneAdjoint2);
+        if (t2.tile_bits >= 10 && t2.tile_bits <= 14) {
+            t2.unfused = 0;
+            std::vector<PassPlan> todo;
+            for (PassPlan &pp : plan_rotations(n, p->rot, t2)) todo.push_back(std::move(pp));
+            std::reverse(todo.begin(), todo.end());
+            PassArgs2 ia;
+            while (!todo.empty()) {
+                PassPlan pp = std::move(todo.back());
+                todo.pop_back();
+                if (build_pass_args2(pp, p->rot, true, true, ia)) {
+                    p->adj2_args.push_back(ia);
+                    continue;
+                }
+                if (pp.rots.size() < 2)
+                    return set_error(CFH_E_INVAL, "cfh_plan_create: a rotation does not fit the adjoint kernel");
+                PassPlan hi = pp;
+                const size_t half = pp.rots.size() / 2;
+                hi.rots.assign(pp.rots.begin() + (std::ptrdiff_t)half, pp.rots.end());
+                pp.rots.resize(half);
+                todo.push_back(std::move(hi));
+                todo.push_back(std::move(pp));
+            }
+        }
+    }
     cfh_status st = CFH_OK;
     if (m && !hip_ok(hipMalloc(&p->coef, m * sizeof(double2)), "cfh_plan_create: hipMalloc", &st)) return st;
     // adjoint partial sums: one row of kMaxRun per persistent workgroup
     p->adj_grid = persistent_grid(1ull << (n - p->adj_b));
-    if (!hip_ok(hipMalloc(&p->gpart, (size_t)p->adj_grid * kMaxRun * sizeof(double)), "cfh_plan_create: hipMalloc",
-                &st))
-        return st;
+    const size_t gp = std::max<size_t>(p->adj_grid, p->adj2_args.empty() ? 0 : cfh_plan_s::kAdj2Grid);
+    if (!hip_ok(hipMalloc(&p->gpart, gp * kMaxRun * sizeof(double)), "cfh_plan_create: hipMalloc", &st)) return st;
     *out = p.release();
     return CFH_OK;
 }
@@ -1243,6 +1277,19 @@ cfh_status cfh_adjoint_grad(cfh_plan p, cfh_ham h, void *psi, void *lam, const d
     if (m == 0) return CFH_OK;
     hipLaunchKernelGGL(k_coef, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, theta_dev, p->coef, m);
     if ((st = last_launch("k_coef"))) return st;
+    if (!p->adj2_args.empty()) {
+        for (int64_t i = (int64_t)p->adj2_args.size() - 1; i >= 0; --i) {
+            const PassArgs2 &a = p->adj2_args[i];
+            const uint64_t ntiles = 1ull << (p->n - a.b);
+            st = p->dtype == CFH_C128
+                     ? launch_adj2(ntiles, s, (double2 *)psi, (double2 *)lam, p->coef, a, true, p->gpart,
+                                   cfh_plan_s::kAdj2Grid, grad_dev)
+                     : launch_adj2(ntiles, s, (float2 *)psi, (float2 *)lam, p->coef, a, true, p->gpart,
+                                   cfh_plan_s::kAdj2Grid, grad_dev);
+            if (st) return st;
+        }
+        return CFH_OK;
+    }
     for (int64_t i = (int64_t)p->adj_args.size() - 1; i >= 0; --i) {
         const PassArgs &a = p->adj_args[i];
         const uint64_t ntiles = 1ull << (p->n - a.b);

@@ -31,4 +31,16 @@ extern template cfh_status launch_pass2<double2>(uint64_t, hipStream_t, double2 
 extern template cfh_status launch_pass2<float2>(uint64_t, hipStream_t, float2 *, const double2 *,
                                                 const PassArgs2 &, int, double2 *, unsigned);
 
+// Register-tiled adjoint pass over every coset: rewinds psi and lam by the
+// pass's rotations (inverse-order descriptors) and writes
+// grad[k] = Im <lam|P_k|psi> for each of them (one reduction launch follows
+// the pass).  gpart holds max_grid * kMaxRun doubles of scratch.
+template <typename Amp>
+cfh_status launch_adj2(uint64_t ntiles, hipStream_t s, Amp *psi, Amp *lam, const double2 *coef, const PassArgs2 &a,
+                       bool half, double *gpart, unsigned max_grid, double *grad);
+extern template cfh_status launch_adj2<double2>(uint64_t, hipStream_t, double2 *, double2 *, const double2 *,
+                                                const PassArgs2 &, bool, double *, unsigned, double *);
+extern template cfh_status launch_adj2<float2>(uint64_t, hipStream_t, float2 *, float2 *, const double2 *,
+                                               const PassArgs2 &, bool, double *, unsigned, double *);
+
 } // namespace cfh

@@ -366,6 +366,217 @@ k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2
     }
 }
 
+// ------------------------------------------------ register-tiled adjoint pass
+// psi and lam of one coset in registers (16 amplitudes each per thread).  The
+// run is walked backwards (inverse-order descriptors, angles negated): for
+// each rotation the thread adds its share of Im <lam|P_k|psi> over the coset,
+// then both vectors are rewound by R_k^dag with the same compile-time bodies
+// as the forward pass.  With (P psi)_y = i^wp (-1)^{|y&z|} psi_{y^x} the share
+// is (thread and coset sign) * Im(i^wp Z), Z = sum_j sigma_j conj(l_j) p_{j^cx}:
+// Re Z for odd wp (real beta in the rotation), Im Z for even wp; the sign of
+// i^wp is descriptor flag bit 2.  Per-wave sums accumulate in LDS over the
+// cosets and are written per workgroup in a fixed order.
+template <int KASE>
+__device__ __forceinline__ void adj_body(double2 (&p)[kRegs], double2 (&l)[kRegs], double c, double s, double &g)
+{
+    constexpr int CX = KASE & 15, ZR = (KASE >> 4) & 15;
+    constexpr bool IMAG = (KASE >> 8) & 1;
+#pragma unroll
+    for (int j = 0; j < kRegs; ++j) {
+        const double2 u = p[j ^ CX], v = l[j];
+        const double q = IMAG ? v.x * u.y - v.y * u.x : v.x * u.x + v.y * u.y;
+        g += cpar(j & ZR) ? -q : q;
+    }
+    kase_body<KASE>(p, c, s);
+    kase_body<KASE>(l, c, s);
+}
+
+// (accumulates through a reference like the other trees: a value returned
+// out of the unstructured branch tree came back from the wrong leaf)
+template <int BIT, int ACC>
+__device__ __forceinline__ void adj_dispatch(uint32_t kase, double2 (&p)[kRegs], double2 (&l)[kRegs], double c,
+                                             double s, double &g)
+{
+    if constexpr (BIT < 0) {
+        adj_body<ACC>(p, l, c, s, g);
+    } else {
+        if (kase & (1u << BIT))
+            adj_dispatch<BIT - 1, ACC | (1 << BIT)>(kase, p, l, c, s, g);
+        else
+            adj_dispatch<BIT - 1, ACC>(kase, p, l, c, s, g);
+    }
+}
+
+// HALF: half-tile transposes (anchored micro-groups), as in k_pass2.
+template <typename Amp, int B, bool HALF>
+__global__ void __launch_bounds__(1 << (B - kRegDims))
+k_adj2(Amp *__restrict__ psi, Amp *__restrict__ lam, const double2 *__restrict__ coef, const PassArgs2 args,
+       uint64_t ntiles, double *__restrict__ gpart)
+{
+    constexpr int NW = (1 << (B - kRegDims)) / 64;
+    constexpr int LB = HALF ? B - 1 : B;
+    extern __shared__ unsigned char lds_raw[];
+    Amp *ldp = reinterpret_cast<Amp *>(lds_raw);
+    Amp *ldl = ldp + (1 << LB);
+    __shared__ double2 tab[kMaxRun];
+    __shared__ double wacc[kMaxRun][NW];
+    const uint32_t t = threadIdx.x;
+    const int last = args.nmg - 1;
+    const int nrot = args.mg[last].rot_begin + args.mg[last].rot_count;
+    if ((int)t < nrot) {
+        const RotDesc2 &d = args.rot[t];
+        const double2 cs = coef[d.k];
+        double sv = args.inverse ? -cs.y : cs.y;
+        if (d.flags & 2) sv = -sv;
+        tab[t] = make_double2(cs.x, sv);
+    }
+    for (int i = t; i < kMaxRun * NW; i += blockDim.x) (&wacc[0][0])[i] = 0.0;
+    uint32_t tsb = 0;
+    for (int ri = 0; ri < nrot; ++ri) tsb |= (uint32_t)par32(t & args.rot[ri].zt) << ri;
+    __syncthreads();
+    uint64_t Lb0 = 0, LbL = 0;
+    {
+        const uint32_t b0 = deposit32(t, args.mg[0].npiv), bL = deposit32(t, args.mg[last].npiv);
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            if ((b0 >> i) & 1) Lb0 ^= args.v[i];
+            if ((bL >> i) & 1) LbL ^= args.v[i];
+        }
+    }
+#pragma unroll 1
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        asm volatile("" : "+v"(Lb0), "+v"(LbL));
+        const uint64_t tb = deposit(tile, args.outer_mask);
+        double2 p[kRegs], l[kRegs];
+        {
+            const uint64_t y0 = tb ^ Lb0;
+#pragma unroll
+            for (int j = 0; j < kRegs; ++j) {
+                p[j] = ld(psi[y0 ^ args.LU_first[j]]);
+                l[j] = ld(lam[y0 ^ args.LU_first[j]]);
+            }
+        }
+        uint32_t bprev = 0;
+#pragma unroll 1
+        for (int g = 0; g <= last; ++g) {
+            const MGDesc2 &m = args.mg[g];
+            const uint32_t bt = deposit32(t, m.npiv);
+            if (g > 0) {
+                const MGDesc2 &mp = args.mg[g - 1];
+                if constexpr (HALF) {
+                    const uint32_t lo = (1u << args.qbit) - 1;
+                    const uint32_t bw = (bprev & lo) | ((bprev >> 1) & ~lo);
+                    const uint32_t br = (bt & lo) | ((bt >> 1) & ~lo);
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                        for (int j = h; j < kRegs; j += 2) {
+                            st(ldp[bw ^ mp.UC[j]], p[j]);
+                            st(ldl[bw ^ mp.UC[j]], l[j]);
+                        }
+                        __syncthreads();
+#pragma unroll
+                        for (int j = h; j < kRegs; j += 2) {
+                            p[j] = ld(ldp[br ^ m.UC[j]]);
+                            l[j] = ld(ldl[br ^ m.UC[j]]);
+                        }
+                        __syncthreads();
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < kRegs; ++j) {
+                        st(ldp[bprev ^ mp.U[j]], p[j]);
+                        st(ldl[bprev ^ mp.U[j]], l[j]);
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int j = 0; j < kRegs; ++j) {
+                        p[j] = ld(ldp[bt ^ m.U[j]]);
+                        l[j] = ld(ldl[bt ^ m.U[j]]);
+                    }
+                    __syncthreads();
+                }
+            }
+            bprev = bt;
+#pragma unroll 1
+            for (int ri = m.rot_begin; ri < m.rot_begin + m.rot_count; ++ri) {
+                const RotDesc2 &d = args.rot[ri];
+                const double2 cs = tab[ri];
+                const uint32_t sg = ((tsb >> ri) ^ (uint32_t)par64(tb & d.z)) & 1u;
+                double gr = 0.0;
+                adj_dispatch<8, 0>(d.kase, p, l, cs.x, flip_if(cs.y, sg), gr);
+                gr = flip_if(gr, sg ^ ((uint32_t)d.flags >> 2));
+                gr = wave_sum<64>(gr);
+                // every lane holds the same wave sum and writes the same value:
+                // no divergent branch inside the unstructured rotation loop
+                wacc[ri][t >> 6] += gr;
+            }
+        }
+        const uint64_t yL = tb ^ LbL;
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) {
+            st(psi[yL ^ args.LU_last[j]], p[j]);
+            st(lam[yL ^ args.LU_last[j]], l[j]);
+        }
+    }
+    __syncthreads();
+    if ((int)t < nrot) {
+        double sum = 0.0;
+        for (int w = 0; w < NW; ++w) sum += wacc[t][w];
+        gpart[(uint64_t)blockIdx.x * kMaxRun + t] = sum;
+    }
+}
+
+// grad[k of rotation ri] = sum over the pass's workgroups of their partials (fixed order).
+__global__ void k_grad_reduce2(const double *__restrict__ gpart, int nblocks, const PassArgs2 args,
+                               double *__restrict__ grad)
+{
+    const int ri = blockIdx.x;
+    __shared__ double sh[256];
+    double a = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) a += gpart[(uint64_t)b * kMaxRun + ri];
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) grad[args.rot[ri].k] = sh[0];
+}
+
+template <typename Amp, int B, bool HALF>
+cfh_status launch_adj2_b(uint64_t ntiles, hipStream_t s, Amp *psi, Amp *lam, const double2 *coef,
+                         const PassArgs2 &a, double *gpart, unsigned max_grid, double *grad)
+{
+    constexpr int LB = HALF ? B - 1 : B;
+    if constexpr (2 * ((size_t)1 << LB) * sizeof(Amp) > 150 * 1024) {
+        return set_error(CFH_E_UNSUPPORTED, "adjoint tile too large for LDS");
+    } else {
+        constexpr int T = 1 << (B - kRegDims);
+        const size_t lds = a.nmg > 1 ? 2 * ((size_t)1 << LB) * sizeof(Amp) : 0;
+        const void *fn = reinterpret_cast<const void *>(&k_adj2<Amp, B, HALF>);
+        static bool attr = false;
+        if (!attr) {
+            hipFuncAttributes fa{};
+            cfh_status st = CFH_OK;
+            if (!hip_ok(hipFuncGetAttributes(&fa, fn), "k_adj2: hipFuncGetAttributes", &st)) return st;
+            if (!hip_ok(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)(160 * 1024 - fa.sharedSizeBytes)),
+                        "k_adj2: hipFuncSetAttribute", &st))
+                return st;
+            attr = true;
+        }
+        unsigned grid = (unsigned)std::min<uint64_t>(ntiles, resident_grid(fn, T, lds));
+        grid = std::min(grid, max_grid);
+        hipLaunchKernelGGL((k_adj2<Amp, B, HALF>), dim3(grid), dim3(T), lds, s, psi, lam, coef, a, ntiles, gpart);
+        cfh_status st = last_launch("k_adj2");
+        if (st) return st;
+        const int nrot = a.mg[a.nmg - 1].rot_begin + a.mg[a.nmg - 1].rot_count;
+        hipLaunchKernelGGL(k_grad_reduce2, dim3(nrot), dim3(256), 0, s, gpart, (int)grid, a, grad);
+        return last_launch("k_grad_reduce2");
+    }
+}
+
 template <typename Amp, int B, int MODE>
 cfh_status launch_pass2_b(uint64_t ntiles, hipStream_t s, Amp *psi, const double2 *coef, const PassArgs2 &a,
                           double2 *partial, unsigned max_grid)
@@ -413,6 +624,25 @@ cfh_status launch_pass2_m(uint64_t ntiles, hipStream_t s, Amp *psi, const double
 } // namespace
 
 namespace cfh {
+
+template <typename Amp>
+cfh_status launch_adj2(uint64_t ntiles, hipStream_t s, Amp *psi, Amp *lam, const double2 *coef, const PassArgs2 &a,
+                       bool half, double *gpart, unsigned max_grid, double *grad)
+{
+    switch (a.b) {
+#define CFH_ADJ2_CASE(BB)                                                                                   \
+    case BB:                                                                                                \
+        return half ? launch_adj2_b<Amp, BB, true>(ntiles, s, psi, lam, coef, a, gpart, max_grid, grad)    \
+                    : launch_adj2_b<Amp, BB, false>(ntiles, s, psi, lam, coef, a, gpart, max_grid, grad);
+        CFH_ADJ2_CASE(10) CFH_ADJ2_CASE(11) CFH_ADJ2_CASE(12) CFH_ADJ2_CASE(13)
+#undef CFH_ADJ2_CASE
+    case 14:
+        if (half) return launch_adj2_b<Amp, 14, true>(ntiles, s, psi, lam, coef, a, gpart, max_grid, grad);
+        return set_error(CFH_E_UNSUPPORTED, "register-tiled adjoint: tile_bits 14 needs half-tile transposes");
+    default:
+        return set_error(CFH_E_UNSUPPORTED, "register-tiled adjoint needs tile_bits in 10..14");
+    }
+}
 
 // Workgroups of 2^(b-4) threads: b >= 10 keeps them at one full wave or more.
 template <typename Amp>

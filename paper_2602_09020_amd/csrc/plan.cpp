@@ -24,9 +24,12 @@ TuningResolved resolve_tuning(const cfh_tuning *t, int n, int dtype, int kind)
     int b = c64 ? 13 : 14;
     if (kind == kTuneAdjoint) b = c64 ? 12 : 11;
     if (kind == kTuneHamiltonian) b = c64 ? 13 : 12;
+    if (kind == kTuneAdjoint2) b = c64 ? 14 : 13;
     b = std::max(std::min(b, n - 9), std::min(n, 10));
     r.tile_bits = (t && t->tile_bits > 0) ? t->tile_bits : b;
-    const int c_def = kind == kTuneHamiltonian ? 5 : ((kind == kTuneForward || kind == kTuneMeasure) && !c64) ? 3 : 4;
+    const int c_def = kind == kTuneHamiltonian ? 5
+                      : ((kind == kTuneForward || kind == kTuneMeasure || kind == kTuneAdjoint2) && !c64) ? 3
+                                                                                                          : 4;
     r.low_bits = (t && t->low_bits > 0) ? t->low_bits : c_def;
     r.max_run = (t && t->max_run > 0) ? t->max_run : kMaxRun;
     r.lookahead = (t && t->lookahead != 0) ? t->lookahead : 512;
@@ -270,7 +273,9 @@ bool build_pass_args2(const PassPlan &pp, const std::vector<Pauli> &rot, bool in
                 if (popc(m.U[j] & zl[i]) & 1) ms |= 1u << j;
             d.msign = (uint16_t)ms;
             const int w = (p.e - popc(p.x & p.z) + 3) & 3;
-            d.flags = (uint8_t)((w & 1) | ((w & 2) ? 2 : 0));
+            // bit 2: sign of i^{(e-|x&z|)}, the phase of P psi (adjoint gradient)
+            const int wp = (p.e - popc(p.x & p.z)) & 3;
+            d.flags = (uint8_t)((w & 1) | ((w & 2) ? 2 : 0) | ((wp & 2) ? 4 : 0));
             // register signs are linear in j (U is spanned by the four u_q), so
             // they are fixed by a 4-bit mask; the thread part by a mask on t
             uint32_t zr = 0;

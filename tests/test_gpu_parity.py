@@ -322,6 +322,54 @@ def test_adjoint_vs_oracle_parameter_shift_and_fd():
     assert np.abs(g - fd).max() <= 1e-6
 
 
+REG_ADJ_SKIP = ("register-tiled adjoint (tuning variant 6) disabled: on the device it applied the wrong "
+                "partner mask to the rewound state; cause not yet shown")
+
+
+@pytest.mark.skip(reason=REG_ADJ_SKIP)
+def test_adjoint_register_tiled_vs_oracle_parameter_shift():
+    """The register-tiled adjoint (tuning variant 6) on a 10-qubit ansatz with a
+    dense Clifford prefix: every gradient against the exact parameter shift."""
+    w = W.make_workload("adj2", 10, seed=12, n_prefix=60, n_rot=80, n_ham=40, n_occupied=5)
+    frame, rot, terms, plan, ham = hybrid.prepare(w, torch.complex128, {"variant": 6})
+    psi0 = hybrid.new_state(w.n, torch.complex128, index=w.init)
+    theta = torch.tensor(w.theta, device=DEV, requires_grad=True)
+    e = hybrid.PauliEnergy.apply(theta, plan, ham, psi0)
+    e.backward()
+    g = theta.grad.cpu().numpy()
+    assert abs(e.item() - sim.energy_of(w, w.theta)) <= 1e-12 * np.abs(w.coeff).sum()
+    assert np.abs(g - sim.param_shift_grad(w)).max() <= 1e-10
+
+
+@pytest.mark.skip(reason=REG_ADJ_SKIP)
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n,tb", [(14, 10), (15, 12), (16, 13), (17, 14)])
+def test_adjoint_register_tiled_matches_lds_adjoint(dtype, n, tb):
+    """Dense random strings (every body shape) plus JW strings: gradients and the
+    rewound state of the register-tiled adjoint equal the LDS-staged adjoint."""
+    rng = np.random.default_rng(n)
+    w = W.make_workload("adj3", n, seed=n, n_prefix=2 * n, n_rot=150, n_ham=60)
+    w.rot = np.concatenate([w.rot, rng.integers(0, 4, size=(150, n)).astype(np.uint8)])
+    w.theta = np.concatenate([w.theta, rng.uniform(-np.pi, np.pi, size=150)])
+    out = {}
+    for tag, tu in (("reg", {"tile_bits": tb, "low_bits": 3, "variant": 6}),
+                    ("lds", {"variant": 1, "tile_bits": min(tb, 11)})):
+        frame, rot, terms, plan, ham = hybrid.prepare(w, dtype, tu)
+        psi = hybrid.new_state(n, dtype, index=w.init)
+        th = torch.tensor(w.theta, device=DEV)
+        plan.apply(psi, th)
+        lam = torch.empty_like(psi)
+        grad = torch.empty_like(th)
+        cfh.cfh_adjoint_grad(plan.h, ham.h, psi, lam, th, grad)
+        torch.cuda.synchronize()
+        out[tag] = (grad.cpu().numpy(), psi.cpu().to(torch.complex128).numpy())
+    tol = 1e-11 if dtype == torch.complex128 else 2e-3
+    assert np.abs(out["reg"][0] - out["lds"][0]).max() <= tol * max(1.0, np.abs(w.coeff).sum())
+    ref = np.zeros(1 << n, np.complex128)
+    ref[w.init] = 1
+    assert np.abs(out["reg"][1] - ref).max() <= (1e-11 if dtype == torch.complex128 else 1e-4)
+
+
 def test_adjoint_rewinds_state():
     w = W.config(3, n=14, n_rot=150, n_ham=50)
     frame, rot, terms, plan, ham = hybrid.prepare(w, torch.complex128)
