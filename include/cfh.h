@@ -89,9 +89,8 @@ typedef struct cfh_tuning {
                               4 = register-tiled, one unrolled body per (partner mask, register
                               sign mask, real/imaginary) so member signs cost no instructions,
                               5 = as 4 with the transposes between micro-groups done in two
-                              halves through half the LDS (tile_bits 10..14),
-                              6 = default forward kernel plus the register-tiled adjoint sweep
-                              (experimental; the default adjoint is LDS-staged) */
+                              halves through half the LDS (tile_bits 10..14).  Every variant but 1
+                              also selects the register-tiled adjoint sweep (1: LDS-staged) */
     int32_t batch_items;   /* batched runs: at most this many work items per pass (0 = 32) */
     int32_t group_mib;     /* batched runs: circuits are scheduled in consecutive groups whose
                               state and lam vectors fit this many MiB (so the 256 MiB Infinity Cache

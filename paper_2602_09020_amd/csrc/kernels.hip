@@ -844,7 +844,6 @@ cfh_status cfh_plan_create(int n, int dtype, const cfh_pauli *rot, size_t m, con
     if (!p->tu.unfused) {
         p->passes = plan_rotations(n, p->rot, p->tu);
         const int b = p->tu.tile_bits;
-        if (p->tu.variant == 6) p->tu.variant = 0;  // register-tiled adjoint; default forward kernel
         if (p->tu.variant < 0 || p->tu.variant > 5)
             return set_error(CFH_E_INVAL, "cfh_plan_create: unknown kernel variant");
         if (p->tu.variant >= 2 && p->tu.variant <= 4 && (b < 10 || b > 13))
@@ -907,12 +906,13 @@ cfh_status cfh_plan_create(int n, int dtype, const cfh_pauli *rot, size_t m, con
     }
     // Register-tiled adjoint: psi and lam of a coset in registers, both moved
     // through LDS between micro-groups (half-tile transposes), so it has its
-    // own pass list on 2^13 (c128) / 2^14 (c64) tiles.  Opt-in (tuning
-    // variant 6 selects it for the adjoint; the forward pass then uses the
-    // default kernel) until its parity is established.
-    const bool reg_adjoint = tuning && tuning->variant == 6;
-    if (reg_adjoint && !p->rot.empty()) {
+    // own pass list on 2^13 (c128) / 2^14 (c64) tiles.  Tuning variant 1
+    // keeps the LDS-staged adjoint.
+    if (p->tu.variant != 1 && !p->rot.empty()) {
         TuningResolved t2 = resolve_tuning(tuning, n, dtype, kTuneAdjoint2);
+        // two half-tile LDS buffers (psi and lam): at most 2^13 complex128 / 2^14 complex64
+        t2.tile_bits = std::min(t2.tile_bits, dtype == CFH_C128 ? 13 : 14);
+        if (t2.tile_bits < n) t2.low_bits = std::min(t2.low_bits, t2.tile_bits - 1);
         if (t2.tile_bits >= 10 && t2.tile_bits <= 14) {
             t2.unfused = 0;
             std::vector<PassPlan> todo;

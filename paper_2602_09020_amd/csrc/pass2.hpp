@@ -376,34 +376,51 @@ k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2
 // Re Z for odd wp (real beta in the rotation), Im Z for even wp; the sign of
 // i^wp is descriptor flag bit 2.  Per-wave sums accumulate in LDS over the
 // cosets and are written per workgroup in a fixed order.
-template <int KASE>
-__device__ __forceinline__ void adj_body(double2 (&p)[kRegs], double2 (&l)[kRegs], double c, double s, double &g)
+// The register signs are taken at run time from msign (bit j = sign of
+// register j), so only the partner mask and real/imaginary beta select a body:
+// 32 bodies of the two-vector update instead of 512.
+template <int CX, bool IMAG>
+__device__ __forceinline__ void adj_body(double2 (&p)[kRegs], double2 (&l)[kRegs], double c, double s,
+                                         uint32_t msign, double &g)
 {
-    constexpr int CX = KASE & 15, ZR = (KASE >> 4) & 15;
-    constexpr bool IMAG = (KASE >> 8) & 1;
 #pragma unroll
     for (int j = 0; j < kRegs; ++j) {
         const double2 u = p[j ^ CX], v = l[j];
-        const double q = IMAG ? v.x * u.y - v.y * u.x : v.x * u.x + v.y * u.y;
-        g += cpar(j & ZR) ? -q : q;
+        g += flip_if(IMAG ? v.x * u.y - v.y * u.x : v.x * u.x + v.y * u.y, msign >> j);
     }
-    kase_body<KASE>(p, c, s);
-    kase_body<KASE>(l, c, s);
+    if constexpr (CX == 0) {
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) {
+            const double sj = flip_if(s, msign >> j);
+            p[j] = rot_diag(p[j], c, sj, IMAG);
+            l[j] = rot_diag(l[j], c, sj, IMAG);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) {
+            if ((j ^ CX) > j) {
+                const double s0 = flip_if(s, msign >> j), s1 = flip_if(s, msign >> (j ^ CX));
+                rot_pair(p[j], p[j ^ CX], c, s0, s1, IMAG);
+                rot_pair(l[j], l[j ^ CX], c, s0, s1, IMAG);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
 }
 
-// (accumulates through a reference like the other trees: a value returned
-// out of the unstructured branch tree came back from the wrong leaf)
+// branch tree over bit 8 (imaginary beta) and bits 3..0 (partner mask) of kase
 template <int BIT, int ACC>
 __device__ __forceinline__ void adj_dispatch(uint32_t kase, double2 (&p)[kRegs], double2 (&l)[kRegs], double c,
-                                             double s, double &g)
+                                             double s, uint32_t msign, double &g)
 {
     if constexpr (BIT < 0) {
-        adj_body<ACC>(p, l, c, s, g);
+        adj_body<ACC & 15, (ACC >> 8) & 1>(p, l, c, s, msign, g);
     } else {
+        constexpr int NEXT = BIT == 8 ? 3 : BIT - 1;
         if (kase & (1u << BIT))
-            adj_dispatch<BIT - 1, ACC | (1 << BIT)>(kase, p, l, c, s, g);
+            adj_dispatch<NEXT, ACC | (1 << BIT)>(kase, p, l, c, s, msign, g);
         else
-            adj_dispatch<BIT - 1, ACC>(kase, p, l, c, s, g);
+            adj_dispatch<NEXT, ACC>(kase, p, l, c, s, msign, g);
     }
 }
 
@@ -504,7 +521,7 @@ k_adj2(Amp *__restrict__ psi, Amp *__restrict__ lam, const double2 *__restrict__
                 const double2 cs = tab[ri];
                 const uint32_t sg = ((tsb >> ri) ^ (uint32_t)par64(tb & d.z)) & 1u;
                 double gr = 0.0;
-                adj_dispatch<8, 0>(d.kase, p, l, cs.x, flip_if(cs.y, sg), gr);
+                adj_dispatch<8, 0>(d.kase, p, l, cs.x, flip_if(cs.y, sg), d.msign, gr);
                 gr = flip_if(gr, sg ^ ((uint32_t)d.flags >> 2));
                 gr = wave_sum<64>(gr);
                 // every lane holds the same wave sum and writes the same value:
@@ -549,7 +566,7 @@ cfh_status launch_adj2_b(uint64_t ntiles, hipStream_t s, Amp *psi, Amp *lam, con
                          const PassArgs2 &a, double *gpart, unsigned max_grid, double *grad)
 {
     constexpr int LB = HALF ? B - 1 : B;
-    if constexpr (2 * ((size_t)1 << LB) * sizeof(Amp) > 150 * 1024) {
+    if constexpr (2 * ((size_t)1 << LB) * sizeof(Amp) > 128 * 1024) {
         return set_error(CFH_E_UNSUPPORTED, "adjoint tile too large for LDS");
     } else {
         constexpr int T = 1 << (B - kRegDims);

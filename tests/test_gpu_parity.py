@@ -322,16 +322,11 @@ def test_adjoint_vs_oracle_parameter_shift_and_fd():
     assert np.abs(g - fd).max() <= 1e-6
 
 
-REG_ADJ_SKIP = ("register-tiled adjoint (tuning variant 6) disabled: on the device it applied the wrong "
-                "partner mask to the rewound state; cause not yet shown")
-
-
-@pytest.mark.skip(reason=REG_ADJ_SKIP)
 def test_adjoint_register_tiled_vs_oracle_parameter_shift():
-    """The register-tiled adjoint (tuning variant 6) on a 10-qubit ansatz with a
+    """The register-tiled adjoint (default tuning) on a 10-qubit ansatz with a
     dense Clifford prefix: every gradient against the exact parameter shift."""
     w = W.make_workload("adj2", 10, seed=12, n_prefix=60, n_rot=80, n_ham=40, n_occupied=5)
-    frame, rot, terms, plan, ham = hybrid.prepare(w, torch.complex128, {"variant": 6})
+    frame, rot, terms, plan, ham = hybrid.prepare(w, torch.complex128)
     psi0 = hybrid.new_state(w.n, torch.complex128, index=w.init)
     theta = torch.tensor(w.theta, device=DEV, requires_grad=True)
     e = hybrid.PauliEnergy.apply(theta, plan, ham, psi0)
@@ -341,7 +336,6 @@ def test_adjoint_register_tiled_vs_oracle_parameter_shift():
     assert np.abs(g - sim.param_shift_grad(w)).max() <= 1e-10
 
 
-@pytest.mark.skip(reason=REG_ADJ_SKIP)
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("n,tb", [(14, 10), (15, 12), (16, 13), (17, 14)])
 def test_adjoint_register_tiled_matches_lds_adjoint(dtype, n, tb):
@@ -352,7 +346,7 @@ def test_adjoint_register_tiled_matches_lds_adjoint(dtype, n, tb):
     w.rot = np.concatenate([w.rot, rng.integers(0, 4, size=(150, n)).astype(np.uint8)])
     w.theta = np.concatenate([w.theta, rng.uniform(-np.pi, np.pi, size=150)])
     out = {}
-    for tag, tu in (("reg", {"tile_bits": tb, "low_bits": 3, "variant": 6}),
+    for tag, tu in (("reg", {"tile_bits": tb, "low_bits": 3}),
                     ("lds", {"variant": 1, "tile_bits": min(tb, 11)})):
         frame, rot, terms, plan, ham = hybrid.prepare(w, dtype, tu)
         psi = hybrid.new_state(n, dtype, index=w.init)
