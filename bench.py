@@ -27,9 +27,17 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+# Sources that decide what the fused pass kernel does and which rotations each
+# launch carries: a counter run taken on other sources is stale.
+KERNEL_SOURCES = ("pass2.hpp", "cfh_internal.hpp", "plan.cpp", "kernels.hip", "launch.hpp")
+
+
 def kernel_source_hash() -> str:
-    with open(os.path.join(ROOT, "paper_2602_09020_amd", "csrc", "kernels.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2602_09020_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def counter_traffic(name: str, kernel: str):
