@@ -95,6 +95,9 @@ typedef struct cfh_tuning {
     int32_t group_mib;     /* batched runs: circuits are scheduled in consecutive groups whose
                               state and lam vectors fit this many MiB (so the 256 MiB Infinity Cache
                               can keep a group resident across its levels); <= 0 = one group */
+    int32_t tile_order;    /* register-tiled passes: 0 = cosets that share 128-byte lines (chunks
+                              narrower than 128 B) run on the same XCD at the same time, so the line
+                              is fetched into one L2 once; 1 = cosets in index order */
 } cfh_tuning;
 
 typedef struct cfh_frame_s *cfh_frame;

@@ -868,6 +868,7 @@ cfh_status cfh_plan_create(int n, int dtype, const cfh_pauli *rot, size_t m, con
                 todo.pop_back();
                 if (build_pass_args2(pp, p->rot, false, v == 5, fa) && build_pass_args2(pp, p->rot, true, v == 5, ia)) {
                     fitted.push_back(std::move(pp));
+                    fa.xrot = ia.xrot = line_share_bits(fa.outer_mask, n, fa.b, (int)amp_bytes(dtype), p->tu.tile_order);
                     p->args2.push_back(fa);
                     p->args2_inv.push_back(ia);
                     continue;
@@ -923,6 +924,7 @@ cfh_status cfh_plan_create(int n, int dtype, const cfh_pauli *rot, size_t m, con
                 PassPlan pp = std::move(todo.back());
                 todo.pop_back();
                 if (build_pass_args2(pp, p->rot, true, true, ia)) {
+                    ia.xrot = line_share_bits(ia.outer_mask, n, ia.b, (int)amp_bytes(dtype), t2.tile_order);
                     p->adj2_args.push_back(ia);
                     continue;
                 }
@@ -1132,6 +1134,7 @@ cfh_status cfh_ham_create(int n, int dtype, const cfh_pauli *terms, const double
                 PassPlan pp = std::move(todo.back());
                 todo.pop_back();
                 if (build_pass_args2(pp, tp, false, anchor, a2)) {
+                    a2.xrot = line_share_bits(a2.outer_mask, n, a2.b, (int)amp_bytes(dtype), tm.tile_order);
                     h->margs.push_back(a2);
                     continue;
                 }

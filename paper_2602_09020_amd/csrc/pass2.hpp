@@ -203,6 +203,20 @@ __device__ __forceinline__ void measure_dispatch(uint32_t cx, uint32_t msign, co
 //             of an observable, coef holds their weights w_k = c_k i^{(e-|x&z|)},
 //             nothing is stored and each workgroup adds its share of
 //             sum_k w_k <psi|P_k|psi> to partial[blockIdx.x].
+// Coset handled at loop index t of the persistent loop.  Workgroups are
+// dealt to the 8 XCDs in turn (workgroup w runs on XCD w mod 8) and the grid
+// is a multiple of 8 when p > 0, so loop indices t and t + 8j (j < 2^p) run on
+// one XCD at the same time.  The 2^p cosets whose amplitudes share 128-byte
+// lines differ only in their low p index bits; they get loop indices 8 apart,
+// so each line is filled into that XCD's L2 once and written back whole.
+// Needs 8 * 2^p <= ntiles (both powers of two): then this is a permutation.
+__device__ __forceinline__ uint64_t coset_of(uint64_t t, int p)
+{
+    if (p == 0) return t;
+    const uint64_t m = (8ull << p) - 1, lo = t & m;
+    return (t & ~m) | ((lo & 7) << p) | (lo >> 3);
+}
+
 template <typename Amp, int B, int MODE>
 __global__ void __launch_bounds__(1 << (B - kRegDims))
 k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2 args, uint64_t ntiles,
@@ -250,7 +264,7 @@ k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2
     Amp pf[kRegs];
     uint64_t tile = blockIdx.x;
     if (PF && tile < ntiles) {
-        const uint64_t y0 = deposit(tile, args.outer_mask) ^ Lb0;
+        const uint64_t y0 = deposit(coset_of(tile, args.xrot), args.outer_mask) ^ Lb0;
 #pragma unroll
         for (int j = 0; j < kRegs; ++j) pf[j] = psi[y0 ^ args.LU_first[j]];
     }
@@ -259,14 +273,14 @@ k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2
         // keep the 2 x 16 per-register address terms from being hoisted out of
         // the loop as 64 live VGPRs: recomputing them is two scalar-operand XORs
         asm volatile("" : "+v"(Lb0), "+v"(LbL));
-        const uint64_t tb = deposit(tile, args.outer_mask);
+        const uint64_t tb = deposit(coset_of(tile, args.xrot), args.outer_mask);
         double2 r[kRegs];
         if (PF) {
 #pragma unroll
             for (int j = 0; j < kRegs; ++j) r[j] = ld(pf[j]);
             const uint64_t nt = tile + gridDim.x;
             if (nt < ntiles) {
-                const uint64_t y0 = deposit(nt, args.outer_mask) ^ Lb0;
+                const uint64_t y0 = deposit(coset_of(nt, args.xrot), args.outer_mask) ^ Lb0;
 #pragma unroll
                 for (int j = 0; j < kRegs; ++j) pf[j] = psi[y0 ^ args.LU_first[j]];
             }
@@ -463,7 +477,7 @@ k_adj2(Amp *__restrict__ psi, Amp *__restrict__ lam, const double2 *__restrict__
 #pragma unroll 1
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         asm volatile("" : "+v"(Lb0), "+v"(LbL));
-        const uint64_t tb = deposit(tile, args.outer_mask);
+        const uint64_t tb = deposit(coset_of(tile, args.xrot), args.outer_mask);
         double2 p[kRegs], l[kRegs];
         {
             const uint64_t y0 = tb ^ Lb0;
@@ -585,6 +599,7 @@ cfh_status launch_adj2_b(uint64_t ntiles, hipStream_t s, Amp *psi, Amp *lam, con
         }
         unsigned grid = (unsigned)std::min<uint64_t>(ntiles, resident_grid(fn, T, lds));
         grid = std::min(grid, max_grid);
+        if (a.xrot > 0) grid &= ~7u;  // coset_of: one line group per XCD
         hipLaunchKernelGGL((k_adj2<Amp, B, HALF>), dim3(grid), dim3(T), lds, s, psi, lam, coef, a, ntiles, gpart);
         cfh_status st = last_launch("k_adj2");
         if (st) return st;
@@ -619,6 +634,7 @@ cfh_status launch_pass2_b(uint64_t ntiles, hipStream_t s, Amp *psi, const double
         }
         unsigned grid = (unsigned)std::min<uint64_t>(ntiles, resident_grid(fn, T, lds));
         if (max_grid) grid = std::min(grid, max_grid);
+        if (a.xrot > 0) grid &= ~7u;  // coset_of: one line group per XCD
         hipLaunchKernelGGL((k_pass2<Amp, B, MODE>), dim3(grid), dim3(T), lds, s, psi, coef, a, ntiles, partial);
         return last_launch("k_pass2");
     }

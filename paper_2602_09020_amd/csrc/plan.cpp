@@ -36,6 +36,7 @@ TuningResolved resolve_tuning(const cfh_tuning *t, int n, int dtype, int kind)
     r.unfused = (t && t->unfused) ? 1 : 0;
     r.block_threads = (t && t->block_threads > 0) ? t->block_threads : 256;
     r.variant = t ? t->variant : 0;
+    r.tile_order = t ? t->tile_order : 0;
     r.max_run = std::min(r.max_run, kMaxRun);
     r.tile_bits = std::min(r.tile_bits, std::min(n, kMaxTileBits));
     r.low_bits = std::min(r.low_bits, r.tile_bits);
@@ -140,6 +141,16 @@ RotDesc make_rot_desc(const PassPlan &pp, const Pauli &p, int k)
     d.w = (p.e - popc(p.x & p.z) + 3) & 3;
     d.dsign = popc(p.x & p.z) & 1;
     return d;
+}
+
+int line_share_bits(uint64_t outer_mask, int n, int b, int amp_bytes, int tile_order)
+{
+    if (tile_order != 0) return 0;
+    const int line_amps = 128 / amp_bytes;
+    const int p = popc(outer_mask & (uint64_t)(line_amps - 1));
+    // the cosets of a line group and the 8 XCDs must tile the coset range
+    if (p == 0 || n - b < 3 + p) return 0;
+    return p;
 }
 
 std::vector<PassPlan> plan_rotations(int n, const std::vector<Pauli> &rot, const TuningResolved &tu)
