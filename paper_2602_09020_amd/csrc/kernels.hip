@@ -1044,6 +1044,13 @@ cfh_status cfh_ham_create(int n, int dtype, const cfh_pauli *terms, const double
     h->n = n;
     h->dtype = dtype;
     h->tu = resolve_tuning(tuning, n, dtype, kTuneHamiltonian);
+    {
+        // the LDS-staged passes (H psi, and <H> below 2^10) hold a whole tile
+        // in LDS: 2^13 complex128 / 2^14 complex64 amplitudes at most
+        const int lcap = dtype == CFH_C128 ? 13 : 14;
+        if (h->tu.tile_bits > lcap) h->tu.tile_bits = lcap;
+        if (h->tu.tile_bits < n) h->tu.low_bits = std::min(h->tu.low_bits, h->tu.tile_bits - 1);
+    }
     // group terms by x mask (first-appearance order)
     std::map<uint64_t, int> gid;
     std::vector<HamGroup> groups;
