@@ -25,6 +25,7 @@
 #include <new>
 #include <vector>
 
+#include "batch.hpp"
 #include "cfh_internal.hpp"
 #include "device_common.hpp"
 
@@ -32,57 +33,6 @@ using namespace cfh;
 using namespace cfh::dev;
 
 namespace {
-
-constexpr int kBThreads = 256;
-constexpr int kBWaves = kBThreads / 64;
-
-enum { kPassFwd = 0, kPassHam = 1, kPassAdj = 2 };
-enum { kFlagInit = 1, kFlagAccumulate = 2, kFlagEnergy = 4, kFlagStart = 8, kFlagEnd = 16 };
-
-struct BPass {
-    uint64_t outer_mask;
-    uint64_t v[kMaxTileBits];
-    int32_t type, circ, b, flags;
-    int32_t nitems;      // work items of this pass
-    int32_t tiles_per_item;
-    int32_t first;       // first rotation (fwd/adj) or group (ham) in the batch arrays
-    int32_t count;       // number of rotations / groups
-    int32_t end_flag_grad;  // 1 if this pass ends the circuit in a gradient run
-    int32_t pad[3];
-};
-
-struct BCirc {
-    int64_t psi_off;     // amplitude offset of the circuit's state in the arenas
-    uint64_t init;       // initial basis index
-    int64_t theta_off;   // offset of its angles / gradients
-    int64_t gpart_off;   // per-item gradient partials (items * kMaxRun doubles)
-    int64_t epart_off;   // per-item energy partials (items doubles)
-    int32_t n, pad;
-};
-
-struct BItem {
-    int32_t pass;
-    int32_t idx;         // item index inside its pass
-};
-
-struct BatchArgs {
-    const BPass *passes;
-    const BCirc *circs;
-    const RotDesc *rot;
-    const HamGroupDev *groups;
-    const HamTermDev *terms;
-    const double2 *coef;
-    void *psi;
-    void *lam;
-    double *grad;
-    double *energy;
-    double *gpart;
-    double *epart;
-    uint64_t *t_start;
-    uint64_t *t_end;
-    int with_grad;
-    int pad;
-};
 
 // One work item: a range of cosets of one pass.
 template <typename Amp, int BMAX>
@@ -358,15 +308,20 @@ struct cfh_batch_s {
     // per level: [offset, count) into the item table and into the reduction list
     struct Level {
         int64_t item_off, item_cnt, red_off, red_cnt;
+        int64_t item2_off, item2_cnt;  // register-tiled forward items
     };
     std::vector<Level> levels[2];   // [0] forward + energy, [1] with gradients
     int64_t n_items[2] = {0, 0};
     int n_groups = 0;               // cache groups of circuits
+    int64_t n_passes = 0;           // passes of the gradient chains (forward, Hamiltonian, adjoint)
     double bytes[2] = {0.0, 0.0};   // algorithmic HBM bytes of one forward / gradient run
     void *arena = nullptr;
     BPass *d_passes = nullptr;
     BCirc *d_circs = nullptr;
     BItem *d_items[2] = {nullptr, nullptr};
+    BItem *d_items2[2] = {nullptr, nullptr};
+    PassArgs2 *d_pa = nullptr;
+    int reg_fwd = 0;                // circuits with n >= kBatchRegTile run forward on register tiles
     int *d_reduce[2] = {nullptr, nullptr};
     RotDesc *d_rot = nullptr;
     HamGroupDev *d_groups = nullptr;
@@ -421,14 +376,15 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
 {
     if (!out || !circ || count < 1) return set_error(CFH_E_INVAL, "cfh_batch_create: bad arguments");
     if (dtype != CFH_C64 && dtype != CFH_C128) return set_error(CFH_E_UNSUPPORTED, "cfh_batch_create: dtype");
-    if (tuning && tuning->variant != 0)
+    if (tuning && tuning->variant != 0 && tuning->variant != 2)
         return set_error(CFH_E_UNSUPPORTED,
-                         "cfh_batch_create: only the level-synchronous schedule (variant 0) is available; the "
-                         "persistent work-queue kernel is disabled");
+                         "cfh_batch_create: variant 0 (register-tiled forward passes where n >= 12) or 2 "
+                         "(LDS-staged passes only); the persistent work-queue kernel (1) is disabled");
     std::unique_ptr<cfh_batch_s> B(new (std::nothrow) cfh_batch_s);
     if (!B) return set_error(CFH_E_NOMEM, "cfh_batch_create: host memory");
     B->count = count;
     B->dtype = dtype;
+    B->reg_fwd = !(tuning && tuning->variant == 2);
     const int bcap = dtype == CFH_C128 ? 11 : 12;
     B->bmax = (tuning && tuning->tile_bits > 0) ? tuning->tile_bits : 10;
     if (B->bmax < 8 || B->bmax > bcap)
@@ -438,6 +394,7 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
 
     std::vector<BCirc> circs(count);
     std::vector<RotDesc> rots;
+    std::vector<PassArgs2> pa;
     std::vector<HamGroupDev> gdev;
     std::vector<HamTermDev> tdev;
     std::vector<double> theta_all;
@@ -497,17 +454,62 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
             P.tiles_per_item = tpi;
             P.first = first;
             P.count = cnt;
+            P.p2 = -1;
             B->passes.push_back(P);
             return (int)B->passes.size() - 1;
         };
-        // forward rotation passes
+        // LDS-staged plan: the forward passes of small circuits (or of tuning
+        // variant 2) and, walked backwards, the adjoint passes of every circuit
         const std::vector<PassPlan> fw = plan_rotations(d.n, r, tu);
-        std::vector<int> fwd_ids;
+        std::vector<int> fw_lds;  // LDS-staged pass of fw[i]
         for (size_t i = 0; i < fw.size(); ++i) {
             const int first = (int)rots.size();
             for (int k : fw[i].rots) rots.push_back(make_rot_desc(fw[i], r[k], k));
-            fwd_ids.push_back(new_pass(kPassFwd, b, fw[i].outer_mask, fw[i].v, first, (int)fw[i].rots.size(),
-                                       (i == 0 ? kFlagInit | kFlagStart : 0)));
+            fw_lds.push_back(new_pass(kPassFwd, b, fw[i].outer_mask, fw[i].v, first, (int)fw[i].rots.size(),
+                                      (i == 0 ? kFlagInit | kFlagStart : 0)));
+        }
+        std::vector<int> fwd_ids;
+        if (B->reg_fwd && d.n >= kBatchRegTile && d.m > 0) {
+            // forward passes on 2^12-amplitude register tiles (128-byte chunks);
+            // a run needing more micro-groups than a pass carries is split in two
+            cfh_tuning t2{};
+            t2.tile_bits = kBatchRegTile;
+            t2.max_run = tc.max_run;
+            const TuningResolved tu2 = resolve_tuning(&t2, d.n, dtype, kTuneForward);
+            const uint64_t nt2 = 1ull << (d.n - kBatchRegTile);
+            const int tpi2 = (int)std::max<uint64_t>(1, (nt2 + max_items - 1) / max_items);
+            const int nitems2 = (int)((nt2 + tpi2 - 1) / tpi2);
+            std::vector<PassPlan> todo;
+            for (PassPlan &pp : plan_rotations(d.n, r, tu2)) todo.push_back(std::move(pp));
+            std::reverse(todo.begin(), todo.end());
+            PassArgs2 a2;
+            bool first_pass = true;
+            while (!todo.empty()) {
+                PassPlan pp = std::move(todo.back());
+                todo.pop_back();
+                if (!build_pass_args2(pp, r, false, false, a2)) {
+                    if (pp.rots.size() < 2)
+                        return set_error(CFH_E_INVAL, "cfh_batch_create: a rotation does not fit the register tile");
+                    PassPlan hi = pp;
+                    const size_t half = pp.rots.size() / 2;
+                    hi.rots.assign(pp.rots.begin() + (std::ptrdiff_t)half, pp.rots.end());
+                    pp.rots.resize(half);
+                    todo.push_back(std::move(hi));
+                    todo.push_back(std::move(pp));
+                    continue;
+                }
+                if (a2.b != kBatchRegTile) return set_error(CFH_E_INVAL, "cfh_batch_create: register tile size");
+                const int id = new_pass(kPassFwd, kBatchRegTile, pp.outer_mask, pp.v, 0, (int)pp.rots.size(),
+                                        first_pass ? kFlagInit | kFlagStart : 0);
+                B->passes[id].p2 = (int)pa.size();
+                B->passes[id].nitems = nitems2;
+                B->passes[id].tiles_per_item = tpi2;
+                pa.push_back(a2);
+                fwd_ids.push_back(id);
+                first_pass = false;
+            }
+        } else {
+            fwd_ids = fw_lds;
         }
         // Hamiltonian passes (lam = H psi, energy on the last)
         std::map<uint64_t, int> gid;
@@ -557,7 +559,7 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
         // adjoint passes: the forward passes walked backwards
         std::vector<int> adj_ids;
         for (int i = (int)fw.size() - 1; i >= 0; --i) {
-            const BPass &F = B->passes[fwd_ids[i]];
+            const BPass &F = B->passes[fw_lds[i]];
             adj_ids.push_back(new_pass(kPassAdj, F.b, F.outer_mask, fw[i].v, F.first, F.count, 0));
         }
         B->passes[adj_ids.back()].end_flag_grad = 1;
@@ -569,6 +571,7 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
         chain_grad[c] = chain;
     }
     B->total_rot = (int64_t)theta_all.size();
+    for (const auto &ch : chain_grad) B->n_passes += (int64_t)ch.size();
     B->total_amp = amp;
     // level tables: items of pass `lv` of every circuit, then the passes of the
     // level whose partial sums are reduced (adjoint passes, the energy pass)
@@ -592,7 +595,7 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
         }
         cgroups.push_back({c0, count});
     }
-    std::vector<BItem> items[2];
+    std::vector<BItem> items[2], items2[2];
     std::vector<int> red[2];
     for (int g = 0; g < 2; ++g) {
         const auto &chains = g ? chain_grad : chain_fwd;
@@ -600,21 +603,24 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
             size_t maxlen = 0;
             for (int c = cg.first; c < cg.second; ++c) maxlen = std::max(maxlen, chains[c].size());
             for (size_t lv = 0; lv < maxlen; ++lv) {
-                cfh_batch_s::Level L{(int64_t)items[g].size(), 0, (int64_t)red[g].size(), 0};
+                cfh_batch_s::Level L{(int64_t)items[g].size(), 0, (int64_t)red[g].size(), 0,
+                                     (int64_t)items2[g].size(), 0};
                 for (int c = cg.first; c < cg.second; ++c) {
                     if (lv >= chains[c].size()) continue;
                     const int p = chains[c][lv];
-                    for (int i = 0; i < B->passes[p].nitems; ++i) items[g].push_back(BItem{p, i});
+                    auto &dst = B->passes[p].p2 >= 0 ? items2[g] : items[g];
+                    for (int i = 0; i < B->passes[p].nitems; ++i) dst.push_back(BItem{p, i});
                     const BPass &P = B->passes[p];
                     const bool ends = g ? P.end_flag_grad : (P.flags & kFlagEnd);
                     if (P.type == kPassAdj || (P.flags & kFlagEnergy) || ends) red[g].push_back(p);
                 }
                 L.item_cnt = (int64_t)items[g].size() - L.item_off;
+                L.item2_cnt = (int64_t)items2[g].size() - L.item2_off;
                 L.red_cnt = (int64_t)red[g].size() - L.red_off;
                 B->levels[g].push_back(L);
             }
         }
-        B->n_items[g] = (int64_t)items[g].size();
+        B->n_items[g] = (int64_t)(items[g].size() + items2[g].size());
     }
     B->n_groups = (int)cgroups.size();
     // algorithmic bytes: a rotation pass reads and writes psi (the first one
@@ -637,6 +643,9 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
         {(void **)&B->d_circs, count * sizeof(BCirc)},
         {(void **)&B->d_items[0], std::max<size_t>(1, items[0].size()) * sizeof(BItem)},
         {(void **)&B->d_items[1], std::max<size_t>(1, items[1].size()) * sizeof(BItem)},
+        {(void **)&B->d_items2[0], std::max<size_t>(1, items2[0].size()) * sizeof(BItem)},
+        {(void **)&B->d_items2[1], std::max<size_t>(1, items2[1].size()) * sizeof(BItem)},
+        {(void **)&B->d_pa, std::max<size_t>(1, pa.size()) * sizeof(PassArgs2)},
         {(void **)&B->d_reduce[0], std::max<size_t>(1, red[0].size()) * sizeof(int)},
         {(void **)&B->d_reduce[1], std::max<size_t>(1, red[1].size()) * sizeof(int)},
         {(void **)&B->d_rot, std::max<size_t>(1, rots.size()) * sizeof(RotDesc)},
@@ -669,6 +678,9 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
         !up(B->d_circs, circs.data(), count * sizeof(BCirc)) ||
         !up(B->d_items[0], items[0].data(), items[0].size() * sizeof(BItem)) ||
         !up(B->d_items[1], items[1].data(), items[1].size() * sizeof(BItem)) ||
+        !up(B->d_items2[0], items2[0].data(), items2[0].size() * sizeof(BItem)) ||
+        !up(B->d_items2[1], items2[1].data(), items2[1].size() * sizeof(BItem)) ||
+        !up(B->d_pa, pa.data(), pa.size() * sizeof(PassArgs2)) ||
         !up(B->d_reduce[0], red[0].data(), red[0].size() * sizeof(int)) ||
         !up(B->d_reduce[1], red[1].data(), red[1].size() * sizeof(int)) ||
         !up(B->d_rot, rots.data(), rots.size() * sizeof(RotDesc)) ||
@@ -691,7 +703,7 @@ cfh_status cfh_batch_info(cfh_batch b, int64_t *n_items_grad, int64_t *n_passes,
 {
     if (!b) return set_error(CFH_E_INVAL, "cfh_batch_info: null batch");
     if (n_items_grad) *n_items_grad = b->n_items[1];
-    if (n_passes) *n_passes = (int64_t)b->passes.size();
+    if (n_passes) *n_passes = b->n_passes;
     if (n_rot) *n_rot = b->total_rot;
     if (state_bytes) *state_bytes = (double)b->total_amp * (b->dtype == CFH_C64 ? 8 : 16);
     if (bytes_fwd) *bytes_fwd = b->bytes[0];
@@ -737,10 +749,20 @@ cfh_status cfh_batch_run(cfh_batch b, int with_grad, void *stream)
     A.t_end = b->d_tend;
     A.with_grad = g;
     for (const auto &L : b->levels[g]) {
-        cfh_status st = b->dtype == CFH_C128
-                            ? launch_level<double2>(b->bmax, (unsigned)L.item_cnt, s, A, b->d_items[g] + L.item_off)
-                            : launch_level<float2>(b->bmax, (unsigned)L.item_cnt, s, A, b->d_items[g] + L.item_off);
-        if (st) return st;
+        if (L.item_cnt) {
+            cfh_status st = b->dtype == CFH_C128
+                                ? launch_level<double2>(b->bmax, (unsigned)L.item_cnt, s, A, b->d_items[g] + L.item_off)
+                                : launch_level<float2>(b->bmax, (unsigned)L.item_cnt, s, A, b->d_items[g] + L.item_off);
+            if (st) return st;
+        }
+        if (L.item2_cnt) {
+            cfh_status st = b->dtype == CFH_C128
+                                ? launch_batch_fwd2<double2>((unsigned)L.item2_cnt, s, A, b->d_pa,
+                                                             b->d_items2[g] + L.item2_off)
+                                : launch_batch_fwd2<float2>((unsigned)L.item2_cnt, s, A, b->d_pa,
+                                                            b->d_items2[g] + L.item2_off);
+            if (st) return st;
+        }
         if (L.red_cnt) {
             hipLaunchKernelGGL(k_batch_reduce, dim3((unsigned)L.red_cnt), dim3(kBThreads), 0, s, A,
                                b->d_reduce[g] + L.red_off);

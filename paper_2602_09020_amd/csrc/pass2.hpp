@@ -190,19 +190,6 @@ __device__ __forceinline__ void measure_dispatch(uint32_t cx, uint32_t msign, co
     }
 }
 
-// MODE bit 0: prefetch the next coset into registers.
-// MODE bit 1: compile-time rotation bodies; (c, s) of the pass staged in LDS
-//             once per workgroup, thread signs precomputed as one bit mask.
-// MODE bit 2: half-tile transposes.  Register dimension 0 of every
-//             micro-group is the same anchor vector, whose pivot is local
-//             bit qbit; so the amplitudes with local bit qbit = h are exactly
-//             the registers j with (j & 1) == h in both layouts, and each half
-//             moves through an LDS buffer of 2^(B-1) amplitudes indexed by the
-//             local coordinate with bit qbit removed.
-// MODE bit 3: read-only measurement (with bit 1): the descriptors are terms
-//             of an observable, coef holds their weights w_k = c_k i^{(e-|x&z|)},
-//             nothing is stored and each workgroup adds its share of
-//             sum_k w_k <psi|P_k|psi> to partial[blockIdx.x].
 // Coset handled at loop index t of the persistent loop.  Workgroups are
 // dealt to the 8 XCDs in turn (workgroup w runs on XCD w mod 8) and the grid
 // is a multiple of 8 when p > 0, so loop indices t and t + 8j (j < 2^p) run on
@@ -217,6 +204,19 @@ __device__ __forceinline__ uint64_t coset_of(uint64_t t, int p)
     return (t & ~m) | ((lo & 7) << p) | (lo >> 3);
 }
 
+// MODE bit 0: prefetch the next coset into registers.
+// MODE bit 1: compile-time rotation bodies; (c, s) of the pass staged in LDS
+//             once per workgroup, thread signs precomputed as one bit mask.
+// MODE bit 2: half-tile transposes.  Register dimension 0 of every
+//             micro-group is the same anchor vector, whose pivot is local
+//             bit qbit; so the amplitudes with local bit qbit = h are exactly
+//             the registers j with (j & 1) == h in both layouts, and each half
+//             moves through an LDS buffer of 2^(B-1) amplitudes indexed by the
+//             local coordinate with bit qbit removed.
+// MODE bit 3: read-only measurement (with bit 1): the descriptors are terms
+//             of an observable, coef holds their weights w_k = c_k i^{(e-|x&z|)},
+//             nothing is stored and each workgroup adds its share of
+//             sum_k w_k <psi|P_k|psi> to partial[blockIdx.x].
 template <typename Amp, int B, int MODE>
 __global__ void __launch_bounds__(1 << (B - kRegDims))
 k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2 args, uint64_t ntiles,

@@ -51,6 +51,42 @@ def test_batch_gradients_vs_oracle_parameter_shift():
         assert np.abs(st - ref).max() <= 1e-12
 
 
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 1e-4)])
+def test_batch_register_tiled_forward_vs_oracle(dtype, tol):
+    """Circuits of 12-15 qubits run their forward passes on 2^12-amplitude
+    register tiles (variant 0): final states and energies against the oracle,
+    the same within rounding as the LDS-staged passes (variant 2), and
+    gradients against the parameter shift."""
+    rng = np.random.default_rng(4)
+    ws = []
+    for i, n in enumerate((12, 13, 14, 15, 12)):
+        w = W.make_workload(f"r{i}", n, seed=300 + i, n_prefix=2 * n, n_rot=int(rng.integers(60, 160)), n_ham=25)
+        if i == 4:
+            # dense random strings: every partner mask and register sign mask
+            w.rot = rng.integers(0, 4, size=(200, n)).astype(np.uint8)
+            w.theta = rng.uniform(-np.pi, np.pi, size=200)
+        ws.append(w)
+    out = {}
+    for variant in (0, 2):
+        B = hybrid.Batch(ws, dtype, {"variant": variant, "batch_items": 3})
+        B.run(with_grad=False)
+        r = B.results()
+        out[variant] = (r["energy"], [B.state(i).cpu().to(torch.complex128).numpy() for i in range(len(ws))])
+    for i, w in enumerate(ws):
+        psi, phi = sim.simulate(w)
+        scale = np.abs(w.coeff).sum()
+        assert np.abs(out[0][1][i] - phi).max() <= tol, i
+        assert abs(out[0][0][i] - sim.energy(psi, w.n, w.ham, w.coeff)) <= tol * scale, i
+        assert np.abs(out[0][1][i] - out[2][1][i]).max() <= tol, i
+    if dtype == torch.complex128:
+        g = [W.make_workload(f"rg{i}", 12, seed=400 + i, n_prefix=20, n_rot=30, n_ham=15) for i in range(2)]
+        B = hybrid.Batch(g, dtype)
+        B.run(with_grad=True)
+        r = B.results()
+        for i, w in enumerate(g):
+            assert np.abs(r["grad"][i] - sim.param_shift_grad(w)).max() <= 1e-10, i
+
+
 def test_batch_matches_single_circuit_path():
     ws = W.batched_configs(seed=3, count=8, n_range=(12, 16), r_range=(100, 300), n_ham=40)
     B = hybrid.Batch(ws, torch.complex128)
