@@ -309,6 +309,7 @@ struct cfh_batch_s {
     struct Level {
         int64_t item_off, item_cnt, red_off, red_cnt;
         int64_t item2_off, item2_cnt;  // register-tiled forward items
+        int64_t item3_off, item3_cnt;  // register-tiled adjoint items
     };
     std::vector<Level> levels[2];   // [0] forward + energy, [1] with gradients
     int64_t n_items[2] = {0, 0};
@@ -320,6 +321,7 @@ struct cfh_batch_s {
     BCirc *d_circs = nullptr;
     BItem *d_items[2] = {nullptr, nullptr};
     BItem *d_items2[2] = {nullptr, nullptr};
+    BItem *d_items3 = nullptr;
     PassArgs2 *d_pa = nullptr;
     int reg_fwd = 0;                // circuits with n >= kBatchRegTile run forward on register tiles
     int *d_reduce[2] = {nullptr, nullptr};
@@ -425,6 +427,10 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
         const uint64_t ntiles = 1ull << (d.n - b);
         const int tpi = (int)std::max<uint64_t>(1, (ntiles + max_items - 1) / max_items);
         const int nitems = (int)((ntiles + tpi - 1) / tpi);
+        const bool reg = B->reg_fwd && d.n >= kBatchRegTile && d.m > 0;
+        const uint64_t nt2 = reg ? 1ull << (d.n - kBatchRegTile) : 1;
+        const int tpi2 = (int)std::max<uint64_t>(1, (nt2 + max_items - 1) / max_items);
+        const int nitems2 = (int)((nt2 + tpi2 - 1) / tpi2);
         BCirc &C = circs[c];
         C.psi_off = amp;
         C.init = d.init_index;
@@ -434,7 +440,7 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
         C.n = d.n;
         B->psi_off.push_back(amp);
         amp += (int64_t)1 << d.n;
-        gpart += (int64_t)nitems * kMaxRun;
+        gpart += (int64_t)std::max(nitems, nitems2) * kMaxRun;
         epart += nitems;
         theta_all.insert(theta_all.end(), d.theta, d.theta + d.m);
         B->n.push_back(d.n);
@@ -468,17 +474,15 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
             fw_lds.push_back(new_pass(kPassFwd, b, fw[i].outer_mask, fw[i].v, first, (int)fw[i].rots.size(),
                                       (i == 0 ? kFlagInit | kFlagStart : 0)));
         }
-        std::vector<int> fwd_ids;
-        if (B->reg_fwd && d.n >= kBatchRegTile && d.m > 0) {
+        std::vector<int> fwd_ids, adj_reg;
+        if (reg) {
             // forward passes on 2^12-amplitude register tiles (128-byte chunks);
             // a run needing more micro-groups than a pass carries is split in two
             cfh_tuning t2{};
             t2.tile_bits = kBatchRegTile;
             t2.max_run = tc.max_run;
             const TuningResolved tu2 = resolve_tuning(&t2, d.n, dtype, kTuneForward);
-            const uint64_t nt2 = 1ull << (d.n - kBatchRegTile);
-            const int tpi2 = (int)std::max<uint64_t>(1, (nt2 + max_items - 1) / max_items);
-            const int nitems2 = (int)((nt2 + tpi2 - 1) / tpi2);
+            std::vector<PassPlan> done;
             std::vector<PassPlan> todo;
             for (PassPlan &pp : plan_rotations(d.n, r, tu2)) todo.push_back(std::move(pp));
             std::reverse(todo.begin(), todo.end());
@@ -506,7 +510,41 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
                 B->passes[id].tiles_per_item = tpi2;
                 pa.push_back(a2);
                 fwd_ids.push_back(id);
+                done.push_back(std::move(pp));
                 first_pass = false;
+            }
+            // adjoint passes: the same runs walked backwards with anchored
+            // micro-groups (half-tile transposes); a run that needs more
+            // micro-groups anchored is split, its later half walked first
+            std::vector<PassPlan> rtodo(done.begin(), done.end());
+            while (!rtodo.empty()) {
+                PassPlan pp = std::move(rtodo.back());
+                rtodo.pop_back();
+                if (!build_pass_args2(pp, r, true, true, a2)) {
+                    if (pp.rots.size() < 2)
+                        return set_error(CFH_E_INVAL, "cfh_batch_create: a rotation does not fit the register tile");
+                    PassPlan hi = pp;
+                    const size_t half = pp.rots.size() / 2;
+                    hi.rots.assign(pp.rots.begin() + (std::ptrdiff_t)half, pp.rots.end());
+                    pp.rots.resize(half);
+                    rtodo.push_back(std::move(pp));
+                    rtodo.push_back(std::move(hi));
+                    continue;
+                }
+                // gradient slot t of the pass belongs to rotation a2.rot[t].k
+                const int first = (int)rots.size();
+                const int nr = a2.mg[a2.nmg - 1].rot_begin + a2.mg[a2.nmg - 1].rot_count;
+                for (int t = 0; t < nr; ++t) {
+                    RotDesc rd{};
+                    rd.k = a2.rot[t].k;
+                    rots.push_back(rd);
+                }
+                const int id = new_pass(kPassAdj, kBatchRegTile, pp.outer_mask, pp.v, first, nr, 0);
+                B->passes[id].p2 = (int)pa.size();
+                B->passes[id].nitems = nitems2;
+                B->passes[id].tiles_per_item = tpi2;
+                pa.push_back(a2);
+                adj_reg.push_back(id);
             }
         } else {
             fwd_ids = fw_lds;
@@ -557,11 +595,12 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
         if (ham_ids.empty()) return set_error(CFH_E_INVAL, "cfh_batch_create: every circuit needs an observable");
         if (fwd_ids.empty()) return set_error(CFH_E_INVAL, "cfh_batch_create: every circuit needs rotations");
         // adjoint passes: the forward passes walked backwards
-        std::vector<int> adj_ids;
-        for (int i = (int)fw.size() - 1; i >= 0; --i) {
-            const BPass &F = B->passes[fw_lds[i]];
-            adj_ids.push_back(new_pass(kPassAdj, F.b, F.outer_mask, fw[i].v, F.first, F.count, 0));
-        }
+        std::vector<int> adj_ids = adj_reg;
+        if (!reg)
+            for (int i = (int)fw.size() - 1; i >= 0; --i) {
+                const BPass &F = B->passes[fw_lds[i]];
+                adj_ids.push_back(new_pass(kPassAdj, F.b, F.outer_mask, fw[i].v, F.first, F.count, 0));
+            }
         B->passes[adj_ids.back()].end_flag_grad = 1;
         // dependency chains
         std::vector<int> chain = fwd_ids;
@@ -595,7 +634,7 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
         }
         cgroups.push_back({c0, count});
     }
-    std::vector<BItem> items[2], items2[2];
+    std::vector<BItem> items[2], items2[2], items3;
     std::vector<int> red[2];
     for (int g = 0; g < 2; ++g) {
         const auto &chains = g ? chain_grad : chain_fwd;
@@ -604,11 +643,11 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
             for (int c = cg.first; c < cg.second; ++c) maxlen = std::max(maxlen, chains[c].size());
             for (size_t lv = 0; lv < maxlen; ++lv) {
                 cfh_batch_s::Level L{(int64_t)items[g].size(), 0, (int64_t)red[g].size(), 0,
-                                     (int64_t)items2[g].size(), 0};
+                                     (int64_t)items2[g].size(), 0, (int64_t)items3.size(), 0};
                 for (int c = cg.first; c < cg.second; ++c) {
                     if (lv >= chains[c].size()) continue;
                     const int p = chains[c][lv];
-                    auto &dst = B->passes[p].p2 >= 0 ? items2[g] : items[g];
+                    auto &dst = B->passes[p].p2 < 0 ? items[g] : B->passes[p].type == kPassAdj ? items3 : items2[g];
                     for (int i = 0; i < B->passes[p].nitems; ++i) dst.push_back(BItem{p, i});
                     const BPass &P = B->passes[p];
                     const bool ends = g ? P.end_flag_grad : (P.flags & kFlagEnd);
@@ -616,11 +655,12 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
                 }
                 L.item_cnt = (int64_t)items[g].size() - L.item_off;
                 L.item2_cnt = (int64_t)items2[g].size() - L.item2_off;
+                L.item3_cnt = (int64_t)items3.size() - L.item3_off;
                 L.red_cnt = (int64_t)red[g].size() - L.red_off;
                 B->levels[g].push_back(L);
             }
         }
-        B->n_items[g] = (int64_t)(items[g].size() + items2[g].size());
+        B->n_items[g] = (int64_t)(items[g].size() + items2[g].size() + (g ? items3.size() : 0));
     }
     B->n_groups = (int)cgroups.size();
     // algorithmic bytes: a rotation pass reads and writes psi (the first one
@@ -645,6 +685,7 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
         {(void **)&B->d_items[1], std::max<size_t>(1, items[1].size()) * sizeof(BItem)},
         {(void **)&B->d_items2[0], std::max<size_t>(1, items2[0].size()) * sizeof(BItem)},
         {(void **)&B->d_items2[1], std::max<size_t>(1, items2[1].size()) * sizeof(BItem)},
+        {(void **)&B->d_items3, std::max<size_t>(1, items3.size()) * sizeof(BItem)},
         {(void **)&B->d_pa, std::max<size_t>(1, pa.size()) * sizeof(PassArgs2)},
         {(void **)&B->d_reduce[0], std::max<size_t>(1, red[0].size()) * sizeof(int)},
         {(void **)&B->d_reduce[1], std::max<size_t>(1, red[1].size()) * sizeof(int)},
@@ -680,6 +721,7 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
         !up(B->d_items[1], items[1].data(), items[1].size() * sizeof(BItem)) ||
         !up(B->d_items2[0], items2[0].data(), items2[0].size() * sizeof(BItem)) ||
         !up(B->d_items2[1], items2[1].data(), items2[1].size() * sizeof(BItem)) ||
+        !up(B->d_items3, items3.data(), items3.size() * sizeof(BItem)) ||
         !up(B->d_pa, pa.data(), pa.size() * sizeof(PassArgs2)) ||
         !up(B->d_reduce[0], red[0].data(), red[0].size() * sizeof(int)) ||
         !up(B->d_reduce[1], red[1].data(), red[1].size() * sizeof(int)) ||
@@ -761,6 +803,14 @@ cfh_status cfh_batch_run(cfh_batch b, int with_grad, void *stream)
                                                              b->d_items2[g] + L.item2_off)
                                 : launch_batch_fwd2<float2>((unsigned)L.item2_cnt, s, A, b->d_pa,
                                                             b->d_items2[g] + L.item2_off);
+            if (st) return st;
+        }
+        if (L.item3_cnt) {
+            cfh_status st = b->dtype == CFH_C128
+                                ? launch_batch_adj2<double2>((unsigned)L.item3_cnt, s, A, b->d_pa,
+                                                             b->d_items3 + L.item3_off)
+                                : launch_batch_adj2<float2>((unsigned)L.item3_cnt, s, A, b->d_pa,
+                                                            b->d_items3 + L.item3_off);
             if (st) return st;
         }
         if (L.red_cnt) {

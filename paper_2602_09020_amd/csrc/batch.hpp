@@ -75,4 +75,14 @@ extern template cfh_status launch_batch_fwd2<double2>(unsigned, hipStream_t, con
 extern template cfh_status launch_batch_fwd2<float2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
                                                      const BItem *);
 
+// Register-tiled adjoint items of one level (half-tile transposes of psi and
+// lam): gradient partials per item as the LDS-staged adjoint items write them.
+template <typename Amp>
+cfh_status launch_batch_adj2(unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,
+                             const BItem *items);
+extern template cfh_status launch_batch_adj2<double2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
+                                                      const BItem *);
+extern template cfh_status launch_batch_adj2<float2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
+                                                     const BItem *);
+
 } // namespace cfh

@@ -1,4 +1,5 @@
-// Register-tiled forward rotation passes of the batched runs (cfh_batch_*).
+// Register-tiled forward and adjoint rotation passes of the batched runs
+// (cfh_batch_*).
 //
 // Same scheme as the single-state register-tiled pass (k_pass2, compile-time
 // pair bodies): a workgroup holds one coset of the pass's 2^b-amplitude tile
@@ -92,6 +93,136 @@ k_batch_fwd2(const BatchArgs A, const PassArgs2 *__restrict__ pa, const BItem *_
     }
 }
 
+// Adjoint items: psi and lam of a coset in registers, the pass's rotations
+// walked backwards (inverse-order descriptors, half-tile transposes of both
+// vectors), each rotation's share of g_k = Im <lam|P_k|psi> summed per wave
+// over the item's cosets and written to the item's gradient partials, which
+// the level's reduction adds in a fixed order.
+template <typename Amp, int B>
+__global__ void __launch_bounds__(1 << (B - kRegDims))
+k_batch_adj2(const BatchArgs A, const PassArgs2 *__restrict__ pa, const BItem *__restrict__ items)
+{
+    constexpr int NW = (1 << (B - kRegDims)) / 64;
+    constexpr int LB = B - 1;
+    extern __shared__ unsigned char lds_raw[];
+    Amp *ldp = reinterpret_cast<Amp *>(lds_raw);
+    Amp *ldl = ldp + (1 << LB);
+    __shared__ double2 tab[kMaxRun];
+    __shared__ double wacc[kMaxRun][NW];
+    const uint32_t t = threadIdx.x;
+    const BItem it = items[blockIdx.x];
+    const BPass &P = A.passes[it.pass];
+    const BCirc &C = A.circs[P.circ];
+    const PassArgs2 &args = pa[P.p2];
+    Amp *psi = reinterpret_cast<Amp *>(A.psi) + C.psi_off;
+    Amp *lam = reinterpret_cast<Amp *>(A.lam) + C.psi_off;
+    const double2 *coef = A.coef + C.theta_off;
+    const int last = args.nmg - 1;
+    const int nrot = args.mg[last].rot_begin + args.mg[last].rot_count;
+    if ((int)t < nrot) {
+        const RotDesc2 &d = args.rot[t];
+        const double2 cs = coef[d.k];
+        double sv = args.inverse ? -cs.y : cs.y;
+        if (d.flags & 2) sv = -sv;
+        tab[t] = make_double2(cs.x, sv);
+    }
+    for (int i = t; i < kMaxRun * NW; i += blockDim.x) (&wacc[0][0])[i] = 0.0;
+    uint32_t tsb = 0;
+    for (int ri = 0; ri < nrot; ++ri) tsb |= (uint32_t)par32(t & args.rot[ri].zt) << ri;
+    __syncthreads();
+    uint64_t Lb0 = 0, LbL = 0;
+    {
+        const uint32_t b0 = deposit32(t, args.mg[0].npiv), bL = deposit32(t, args.mg[last].npiv);
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            if ((b0 >> i) & 1) Lb0 ^= args.v[i];
+            if ((bL >> i) & 1) LbL ^= args.v[i];
+        }
+    }
+    const uint64_t ntiles = 1ull << (C.n - args.b);
+    const uint64_t tile0 = (uint64_t)it.idx * (uint64_t)P.tiles_per_item;
+    const uint64_t tile1 = std::min<uint64_t>(ntiles, tile0 + (uint64_t)P.tiles_per_item);
+#pragma unroll 1
+    for (uint64_t tile = tile0; tile < tile1; ++tile) {
+        asm volatile("" : "+v"(Lb0), "+v"(LbL));
+        const uint64_t tb = deposit(tile, args.outer_mask);
+        double2 p[kRegs], l[kRegs];
+        {
+            const uint64_t y0 = tb ^ Lb0;
+#pragma unroll
+            for (int j = 0; j < kRegs; ++j) {
+                p[j] = ld(psi[y0 ^ args.LU_first[j]]);
+                l[j] = ld(lam[y0 ^ args.LU_first[j]]);
+            }
+        }
+        uint32_t bprev = 0;
+#pragma unroll 1
+        for (int g = 0; g <= last; ++g) {
+            const MGDesc2 &m = args.mg[g];
+            const uint32_t bt = deposit32(t, m.npiv);
+            if (g > 0) {
+                const MGDesc2 &mp = args.mg[g - 1];
+                // bprev and bt have 0 at the anchor bit (it is a pivot)
+                const uint32_t lo = (1u << args.qbit) - 1;
+                const uint32_t bw = (bprev & lo) | ((bprev >> 1) & ~lo);
+                const uint32_t br = (bt & lo) | ((bt >> 1) & ~lo);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                    for (int j = h; j < kRegs; j += 2) {
+                        st(ldp[bw ^ mp.UC[j]], p[j]);
+                        st(ldl[bw ^ mp.UC[j]], l[j]);
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int j = h; j < kRegs; j += 2) {
+                        p[j] = ld(ldp[br ^ m.UC[j]]);
+                        l[j] = ld(ldl[br ^ m.UC[j]]);
+                    }
+                    __syncthreads();
+                }
+            }
+            bprev = bt;
+#pragma unroll 1
+            for (int ri = m.rot_begin; ri < m.rot_begin + m.rot_count; ++ri) {
+                const RotDesc2 &d = args.rot[ri];
+                const double2 cs = tab[ri];
+                const uint32_t sg = ((tsb >> ri) ^ (uint32_t)par64(tb & d.z)) & 1u;
+                double gr = 0.0;
+                adj_dispatch<8, 0>(d.kase, p, l, cs.x, flip_if(cs.y, sg), d.msign, gr);
+                gr = flip_if(gr, sg ^ ((uint32_t)d.flags >> 2));
+                gr = wave_sum<64>(gr);
+                // every lane holds the same wave sum and writes the same value
+                wacc[ri][t >> 6] += gr;
+            }
+        }
+        const uint64_t yL = tb ^ LbL;
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) {
+            st(psi[yL ^ args.LU_last[j]], p[j]);
+            st(lam[yL ^ args.LU_last[j]], l[j]);
+        }
+    }
+    __syncthreads();
+    if ((int)t < nrot) {
+        double sum = 0.0;
+        for (int w = 0; w < NW; ++w) sum += wacc[t][w];
+        A.gpart[C.gpart_off + (int64_t)it.idx * kMaxRun + t] = sum;
+    }
+}
+
+template <typename KernelFn>
+cfh_status set_lds_limit(KernelFn fn, const char *what)
+{
+    hipFuncAttributes fa{};
+    cfh_status st = CFH_OK;
+    if (!hip_ok(hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(fn)), what, &st)) return st;
+    hip_ok(hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(160 * 1024 - fa.sharedSizeBytes)),
+           what, &st);
+    return st;
+}
+
 } // namespace
 
 namespace cfh {
@@ -103,25 +234,38 @@ cfh_status launch_batch_fwd2(unsigned grid, hipStream_t s, const BatchArgs &A, c
     constexpr int B = kBatchRegTile;
     constexpr int T = 1 << (B - kRegDims);
     constexpr size_t lds = ((size_t)1 << B) * sizeof(Amp);
-    const void *fn = reinterpret_cast<const void *>(&k_batch_fwd2<Amp, B>);
     static bool attr = false;
     if (!attr) {
-        hipFuncAttributes fa{};
-        cfh_status st = CFH_OK;
-        if (!hip_ok(hipFuncGetAttributes(&fa, fn), "k_batch_fwd2: hipFuncGetAttributes", &st)) return st;
-        if (!hip_ok(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)(160 * 1024 - fa.sharedSizeBytes)),
-                    "k_batch_fwd2: hipFuncSetAttribute", &st))
-            return st;
+        if (cfh_status st = set_lds_limit(&k_batch_fwd2<Amp, B>, "k_batch_fwd2: LDS limit")) return st;
         attr = true;
     }
     hipLaunchKernelGGL((k_batch_fwd2<Amp, B>), dim3(grid), dim3(T), lds, s, A, pa, items);
     return last_launch("k_batch_fwd2");
 }
 
+template <typename Amp>
+cfh_status launch_batch_adj2(unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,
+                             const BItem *items)
+{
+    constexpr int B = kBatchRegTile;
+    constexpr int T = 1 << (B - kRegDims);
+    constexpr size_t lds = 2 * ((size_t)1 << (B - 1)) * sizeof(Amp);  // half-tile buffers of psi and lam
+    static bool attr = false;
+    if (!attr) {
+        if (cfh_status st = set_lds_limit(&k_batch_adj2<Amp, B>, "k_batch_adj2: LDS limit")) return st;
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_batch_adj2<Amp, B>), dim3(grid), dim3(T), lds, s, A, pa, items);
+    return last_launch("k_batch_adj2");
+}
+
 template cfh_status launch_batch_fwd2<double2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
                                                const BItem *);
 template cfh_status launch_batch_fwd2<float2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
+                                              const BItem *);
+template cfh_status launch_batch_adj2<double2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
+                                               const BItem *);
+template cfh_status launch_batch_adj2<float2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
                                               const BItem *);
 
 } // namespace cfh
