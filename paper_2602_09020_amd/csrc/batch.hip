@@ -307,9 +307,8 @@ struct cfh_batch_s {
     std::vector<BPass> passes;
     // per level: [offset, count) into the item table and into the reduction list
     struct Level {
-        int64_t item_off, item_cnt, red_off, red_cnt;
-        int64_t item2_off, item2_cnt;  // register-tiled forward items
-        int64_t item3_off, item3_cnt;  // register-tiled adjoint items
+        int64_t red_off, red_cnt;
+        int64_t off[kKernCount], cnt[kKernCount];  // items of each kernel (kKern*)
     };
     std::vector<Level> levels[2];   // [0] forward + energy, [1] with gradients
     int64_t n_items[2] = {0, 0};
@@ -319,10 +318,9 @@ struct cfh_batch_s {
     void *arena = nullptr;
     BPass *d_passes = nullptr;
     BCirc *d_circs = nullptr;
-    BItem *d_items[2] = {nullptr, nullptr};
-    BItem *d_items2[2] = {nullptr, nullptr};
-    BItem *d_items3 = nullptr;
+    BItem *d_items[2][kKernCount] = {};
     PassArgs2 *d_pa = nullptr;
+    double2 *d_mw = nullptr;
     int reg_fwd = 0;                // circuits with n >= kBatchRegTile run forward on register tiles
     int *d_reduce[2] = {nullptr, nullptr};
     RotDesc *d_rot = nullptr;
@@ -397,6 +395,7 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
     std::vector<BCirc> circs(count);
     std::vector<RotDesc> rots;
     std::vector<PassArgs2> pa;
+    std::vector<double2> mw_all;
     std::vector<HamGroupDev> gdev;
     std::vector<HamTermDev> tdev;
     std::vector<double> theta_all;
@@ -437,11 +436,17 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
         C.theta_off = (int64_t)theta_all.size();
         C.gpart_off = gpart;
         C.epart_off = epart;
+        C.mw_off = (int64_t)mw_all.size();
         C.n = d.n;
+        for (int64_t i = 0; i < d.mh; ++i) {
+            const int wp = (d.terms[i].e - popc(d.terms[i].x & d.terms[i].z)) & 3;  // i^wp
+            const double cf = d.coeff[i];
+            mw_all.push_back(make_double2(wp == 0 ? cf : wp == 2 ? -cf : 0.0, wp == 1 ? cf : wp == 3 ? -cf : 0.0));
+        }
         B->psi_off.push_back(amp);
         amp += (int64_t)1 << d.n;
         gpart += (int64_t)std::max(nitems, nitems2) * kMaxRun;
-        epart += nitems;
+        epart += std::max(nitems, nitems2);
         theta_all.insert(theta_all.end(), d.theta, d.theta + d.m);
         B->n.push_back(d.n);
         B->m.push_back((int)d.m);
@@ -593,6 +598,60 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
                                        (int)hp[i].groups.size(), flags));
         }
         if (ham_ids.empty()) return set_error(CFH_E_INVAL, "cfh_batch_create: every circuit needs an observable");
+        // forward runs of register-tiled circuits need only E: read-only
+        // measurement passes on register tiles instead of writing lam = H psi
+        std::vector<int> meas_ids;
+        if (reg) {
+            cfh_tuning t3{};
+            t3.tile_bits = kBatchRegTile;
+            const TuningResolved tm = resolve_tuning(&t3, d.n, dtype, kTuneMeasure);
+            std::vector<HamGroup> mgr;
+            for (const HamGroup &g : groups)
+                for (size_t i = 0; i < g.terms.size(); i += kMaxRun)
+                    mgr.push_back(HamGroup{g.x, std::vector<int>(g.terms.begin() + (std::ptrdiff_t)i,
+                                                                 g.terms.begin() + (std::ptrdiff_t)std::min(
+                                                                                       g.terms.size(), i + kMaxRun))});
+            std::vector<Pauli> tp(d.mh);
+            for (int64_t i = 0; i < d.mh; ++i) tp[i] = Pauli{d.terms[i].x, d.terms[i].z, d.terms[i].e & 3};
+            std::vector<PassPlan> todo;
+            for (const HamPass &mp : plan_hamiltonian(d.n, mgr, tm, kMaxGroupsPerPass, kMaxRun)) {
+                std::vector<int> idx;
+                for (int g : mp.groups) idx.insert(idx.end(), mgr[g].terms.begin(), mgr[g].terms.end());
+                PassPlan pp;
+                pp.b = mp.b;
+                pp.outer_mask = mp.outer_mask;
+                pp.v = mp.v;
+                pp.rots = order_for_microgroups(mp.v, tp, idx, false);
+                todo.push_back(std::move(pp));
+            }
+            std::reverse(todo.begin(), todo.end());
+            PassArgs2 a3;
+            while (!todo.empty()) {
+                PassPlan pp = std::move(todo.back());
+                todo.pop_back();
+                if (!build_pass_args2(pp, tp, false, false, a3)) {
+                    if (pp.rots.size() < 2)
+                        return set_error(CFH_E_INVAL, "cfh_batch_create: a term does not fit the register tile");
+                    PassPlan hi = pp;
+                    const size_t half = pp.rots.size() / 2;
+                    hi.rots.assign(pp.rots.begin() + (std::ptrdiff_t)half, pp.rots.end());
+                    pp.rots.resize(half);
+                    todo.push_back(std::move(hi));
+                    todo.push_back(std::move(pp));
+                    continue;
+                }
+                if (a3.b != kBatchRegTile) return set_error(CFH_E_INVAL, "cfh_batch_create: register tile size");
+                const int id = new_pass(kPassMeas, kBatchRegTile, pp.outer_mask, pp.v, 0, (int)pp.rots.size(),
+                                        meas_ids.empty() ? 0 : kFlagAccumulate);
+                B->passes[id].p2 = (int)pa.size();
+                B->passes[id].nitems = nitems2;
+                B->passes[id].tiles_per_item = tpi2;
+                pa.push_back(a3);
+                meas_ids.push_back(id);
+            }
+            if (meas_ids.empty()) return set_error(CFH_E_INVAL, "cfh_batch_create: every circuit needs an observable");
+            B->passes[meas_ids.back()].flags |= kFlagEnergy | kFlagEnd;
+        }
         if (fwd_ids.empty()) return set_error(CFH_E_INVAL, "cfh_batch_create: every circuit needs rotations");
         // adjoint passes: the forward passes walked backwards
         std::vector<int> adj_ids = adj_reg;
@@ -604,8 +663,11 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
         B->passes[adj_ids.back()].end_flag_grad = 1;
         // dependency chains
         std::vector<int> chain = fwd_ids;
-        chain.insert(chain.end(), ham_ids.begin(), ham_ids.end());
+        chain.insert(chain.end(), meas_ids.begin(), meas_ids.end());
+        if (meas_ids.empty()) chain.insert(chain.end(), ham_ids.begin(), ham_ids.end());
         chain_fwd[c] = chain;
+        chain = fwd_ids;
+        chain.insert(chain.end(), ham_ids.begin(), ham_ids.end());
         chain.insert(chain.end(), adj_ids.begin(), adj_ids.end());
         chain_grad[c] = chain;
     }
@@ -634,7 +696,7 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
         }
         cgroups.push_back({c0, count});
     }
-    std::vector<BItem> items[2], items2[2], items3;
+    std::vector<BItem> items[2][kKernCount];
     std::vector<int> red[2];
     for (int g = 0; g < 2; ++g) {
         const auto &chains = g ? chain_grad : chain_fwd;
@@ -642,25 +704,30 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
             size_t maxlen = 0;
             for (int c = cg.first; c < cg.second; ++c) maxlen = std::max(maxlen, chains[c].size());
             for (size_t lv = 0; lv < maxlen; ++lv) {
-                cfh_batch_s::Level L{(int64_t)items[g].size(), 0, (int64_t)red[g].size(), 0,
-                                     (int64_t)items2[g].size(), 0, (int64_t)items3.size(), 0};
+                cfh_batch_s::Level L{};
+                L.red_off = (int64_t)red[g].size();
+                for (int k = 0; k < kKernCount; ++k) L.off[k] = (int64_t)items[g][k].size();
                 for (int c = cg.first; c < cg.second; ++c) {
                     if (lv >= chains[c].size()) continue;
                     const int p = chains[c][lv];
-                    auto &dst = B->passes[p].p2 < 0 ? items[g] : B->passes[p].type == kPassAdj ? items3 : items2[g];
+                    const int ty = B->passes[p].type;
+                    const int kk = B->passes[p].p2 < 0 ? kKernLds
+                                   : ty == kPassAdj    ? kKernAdj2
+                                   : ty == kPassMeas   ? kKernMeas2
+                                                       : kKernFwd2;
+                    auto &dst = items[g][kk];
                     for (int i = 0; i < B->passes[p].nitems; ++i) dst.push_back(BItem{p, i});
                     const BPass &P = B->passes[p];
                     const bool ends = g ? P.end_flag_grad : (P.flags & kFlagEnd);
                     if (P.type == kPassAdj || (P.flags & kFlagEnergy) || ends) red[g].push_back(p);
                 }
-                L.item_cnt = (int64_t)items[g].size() - L.item_off;
-                L.item2_cnt = (int64_t)items2[g].size() - L.item2_off;
-                L.item3_cnt = (int64_t)items3.size() - L.item3_off;
+                for (int k = 0; k < kKernCount; ++k) L.cnt[k] = (int64_t)items[g][k].size() - L.off[k];
                 L.red_cnt = (int64_t)red[g].size() - L.red_off;
                 B->levels[g].push_back(L);
             }
         }
-        B->n_items[g] = (int64_t)(items[g].size() + items2[g].size() + (g ? items3.size() : 0));
+        B->n_items[g] = 0;
+        for (int k = 0; k < kKernCount; ++k) B->n_items[g] += (int64_t)items[g][k].size();
     }
     B->n_groups = (int)cgroups.size();
     // algorithmic bytes: a rotation pass reads and writes psi (the first one
@@ -671,9 +738,10 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
             for (int p : (g ? chain_grad : chain_fwd)[c]) {
                 const BPass &P = B->passes[p];
                 const double S = (double)((int64_t)ab << circs[c].n);
-                B->bytes[g] += P.type == kPassFwd ? ((P.flags & kFlagInit) ? 1.0 : 2.0) * S
-                               : P.type == kPassHam ? ((P.flags & kFlagAccumulate) ? 3.0 : 2.0) * S
-                                                    : 4.0 * S;
+                B->bytes[g] += P.type == kPassFwd    ? ((P.flags & kFlagInit) ? 1.0 : 2.0) * S
+                               : P.type == kPassHam  ? ((P.flags & kFlagAccumulate) ? 3.0 : 2.0) * S
+                               : P.type == kPassMeas ? S
+                                                     : 4.0 * S;
             }
 
     // one device arena
@@ -681,11 +749,7 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
     std::vector<std::pair<void **, size_t>> parts = {
         {(void **)&B->d_passes, npass * sizeof(BPass)},
         {(void **)&B->d_circs, count * sizeof(BCirc)},
-        {(void **)&B->d_items[0], std::max<size_t>(1, items[0].size()) * sizeof(BItem)},
-        {(void **)&B->d_items[1], std::max<size_t>(1, items[1].size()) * sizeof(BItem)},
-        {(void **)&B->d_items2[0], std::max<size_t>(1, items2[0].size()) * sizeof(BItem)},
-        {(void **)&B->d_items2[1], std::max<size_t>(1, items2[1].size()) * sizeof(BItem)},
-        {(void **)&B->d_items3, std::max<size_t>(1, items3.size()) * sizeof(BItem)},
+        {(void **)&B->d_mw, std::max<size_t>(1, mw_all.size()) * sizeof(double2)},
         {(void **)&B->d_pa, std::max<size_t>(1, pa.size()) * sizeof(PassArgs2)},
         {(void **)&B->d_reduce[0], std::max<size_t>(1, red[0].size()) * sizeof(int)},
         {(void **)&B->d_reduce[1], std::max<size_t>(1, red[1].size()) * sizeof(int)},
@@ -703,6 +767,9 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
         {(void **)&B->d_tstart, count * sizeof(uint64_t)},
         {(void **)&B->d_tend, count * sizeof(uint64_t)},
     };
+    for (int g = 0; g < 2; ++g)
+        for (int k = 0; k < kKernCount; ++k)
+            parts.push_back({(void **)&B->d_items[g][k], std::max<size_t>(1, items[g][k].size()) * sizeof(BItem)});
     size_t total = 0;
     for (auto &p : parts) total += (p.second + 255) & ~(size_t)255;
     cfh_status st = CFH_OK;
@@ -717,11 +784,7 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
     };
     if (!up(B->d_passes, B->passes.data(), npass * sizeof(BPass)) ||
         !up(B->d_circs, circs.data(), count * sizeof(BCirc)) ||
-        !up(B->d_items[0], items[0].data(), items[0].size() * sizeof(BItem)) ||
-        !up(B->d_items[1], items[1].data(), items[1].size() * sizeof(BItem)) ||
-        !up(B->d_items2[0], items2[0].data(), items2[0].size() * sizeof(BItem)) ||
-        !up(B->d_items2[1], items2[1].data(), items2[1].size() * sizeof(BItem)) ||
-        !up(B->d_items3, items3.data(), items3.size() * sizeof(BItem)) ||
+        !up(B->d_mw, mw_all.data(), mw_all.size() * sizeof(double2)) ||
         !up(B->d_pa, pa.data(), pa.size() * sizeof(PassArgs2)) ||
         !up(B->d_reduce[0], red[0].data(), red[0].size() * sizeof(int)) ||
         !up(B->d_reduce[1], red[1].data(), red[1].size() * sizeof(int)) ||
@@ -730,6 +793,9 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
         !up(B->d_terms, tdev.data(), tdev.size() * sizeof(HamTermDev)) ||
         !up(B->d_theta, theta_all.data(), theta_all.size() * sizeof(double)))
         return st;
+    for (int g = 0; g < 2; ++g)
+        for (int k = 0; k < kKernCount; ++k)
+            if (!up(B->d_items[g][k], items[g][k].data(), items[g][k].size() * sizeof(BItem))) return st;
     *out = B.release();
     return CFH_OK;
 }
@@ -781,6 +847,7 @@ cfh_status cfh_batch_run(cfh_batch b, int with_grad, void *stream)
     A.groups = b->d_groups;
     A.terms = b->d_terms;
     A.coef = b->d_coef;
+    A.mw = b->d_mw;
     A.psi = b->d_psi;
     A.lam = b->d_lam;
     A.grad = b->d_grad;
@@ -790,27 +857,30 @@ cfh_status cfh_batch_run(cfh_batch b, int with_grad, void *stream)
     A.t_start = b->d_tstart;
     A.t_end = b->d_tend;
     A.with_grad = g;
+    const bool c128 = b->dtype == CFH_C128;
     for (const auto &L : b->levels[g]) {
-        if (L.item_cnt) {
-            cfh_status st = b->dtype == CFH_C128
-                                ? launch_level<double2>(b->bmax, (unsigned)L.item_cnt, s, A, b->d_items[g] + L.item_off)
-                                : launch_level<float2>(b->bmax, (unsigned)L.item_cnt, s, A, b->d_items[g] + L.item_off);
-            if (st) return st;
-        }
-        if (L.item2_cnt) {
-            cfh_status st = b->dtype == CFH_C128
-                                ? launch_batch_fwd2<double2>((unsigned)L.item2_cnt, s, A, b->d_pa,
-                                                             b->d_items2[g] + L.item2_off)
-                                : launch_batch_fwd2<float2>((unsigned)L.item2_cnt, s, A, b->d_pa,
-                                                            b->d_items2[g] + L.item2_off);
-            if (st) return st;
-        }
-        if (L.item3_cnt) {
-            cfh_status st = b->dtype == CFH_C128
-                                ? launch_batch_adj2<double2>((unsigned)L.item3_cnt, s, A, b->d_pa,
-                                                             b->d_items3 + L.item3_off)
-                                : launch_batch_adj2<float2>((unsigned)L.item3_cnt, s, A, b->d_pa,
-                                                            b->d_items3 + L.item3_off);
+        for (int k = 0; k < kKernCount; ++k) {
+            if (!L.cnt[k]) continue;
+            const unsigned n = (unsigned)L.cnt[k];
+            const BItem *it = b->d_items[g][k] + L.off[k];
+            cfh_status st = CFH_OK;
+            switch (k) {
+            case kKernLds:
+                st = c128 ? launch_level<double2>(b->bmax, n, s, A, it) : launch_level<float2>(b->bmax, n, s, A, it);
+                break;
+            case kKernFwd2:
+                st = c128 ? launch_batch_fwd2<double2>(n, s, A, b->d_pa, it)
+                          : launch_batch_fwd2<float2>(n, s, A, b->d_pa, it);
+                break;
+            case kKernAdj2:
+                st = c128 ? launch_batch_adj2<double2>(n, s, A, b->d_pa, it)
+                          : launch_batch_adj2<float2>(n, s, A, b->d_pa, it);
+                break;
+            default:
+                st = c128 ? launch_batch_meas2<double2>(n, s, A, b->d_pa, it)
+                          : launch_batch_meas2<float2>(n, s, A, b->d_pa, it);
+                break;
+            }
             if (st) return st;
         }
         if (L.red_cnt) {

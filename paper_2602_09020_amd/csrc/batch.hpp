@@ -13,7 +13,9 @@ namespace cfh {
 constexpr int kBThreads = 256;
 constexpr int kBWaves = kBThreads / 64;
 
-enum { kPassFwd = 0, kPassHam = 1, kPassAdj = 2 };
+enum { kPassFwd = 0, kPassHam = 1, kPassAdj = 2, kPassMeas = 3 };
+// Kernels that run a level's work items.
+enum { kKernLds = 0, kKernFwd2 = 1, kKernAdj2 = 2, kKernMeas2 = 3, kKernCount = 4 };
 enum { kFlagInit = 1, kFlagAccumulate = 2, kFlagEnergy = 4, kFlagStart = 8, kFlagEnd = 16 };
 
 struct BPass {
@@ -35,6 +37,7 @@ struct BCirc {
     int64_t theta_off;   // offset of its angles / gradients
     int64_t gpart_off;   // per-item gradient partials (items * kMaxRun doubles)
     int64_t epart_off;   // per-item energy partials (items doubles)
+    int64_t mw_off;      // its observable's term weights c_k i^{(e-|x&z|)} (measurement passes)
     int32_t n, pad;
 };
 
@@ -50,6 +53,7 @@ struct BatchArgs {
     const HamGroupDev *groups;
     const HamTermDev *terms;
     const double2 *coef;
+    const double2 *mw;
     void *psi;
     void *lam;
     double *grad;
@@ -74,6 +78,17 @@ extern template cfh_status launch_batch_fwd2<double2>(unsigned, hipStream_t, con
                                                       const BItem *);
 extern template cfh_status launch_batch_fwd2<float2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
                                                      const BItem *);
+
+// Register-tiled read-only measurement items (forward runs): each adds its
+// share of sum_k w_k <psi|P_k|psi> over its cosets to its energy partial
+// (assigned by the first measurement pass of the circuit, added by the rest).
+template <typename Amp>
+cfh_status launch_batch_meas2(unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,
+                              const BItem *items);
+extern template cfh_status launch_batch_meas2<double2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
+                                                       const BItem *);
+extern template cfh_status launch_batch_meas2<float2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
+                                                      const BItem *);
 
 // Register-tiled adjoint items of one level (half-tile transposes of psi and
 // lam): gradient partials per item as the LDS-staged adjoint items write them.

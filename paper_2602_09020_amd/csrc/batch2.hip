@@ -1,4 +1,4 @@
-// Register-tiled forward and adjoint rotation passes of the batched runs
+// Register-tiled forward, adjoint and measurement passes of the batched runs
 // (cfh_batch_*).
 //
 // Same scheme as the single-state register-tiled pass (k_pass2, compile-time
@@ -211,6 +211,88 @@ k_batch_adj2(const BatchArgs A, const PassArgs2 *__restrict__ pa, const BItem *_
     }
 }
 
+// Measurement items: the terms of the pass on the coset's registers, read
+// only (the single-state measurement pass, per work item).
+template <typename Amp, int B>
+__global__ void __launch_bounds__(1 << (B - kRegDims))
+k_batch_meas2(const BatchArgs A, const PassArgs2 *__restrict__ pa, const BItem *__restrict__ items)
+{
+    constexpr int NW = (1 << (B - kRegDims)) / 64;
+    extern __shared__ unsigned char lds_raw[];
+    Amp *lds = reinterpret_cast<Amp *>(lds_raw);
+    __shared__ double2 tab[kMaxRun];
+    __shared__ double red[NW];
+    const uint32_t t = threadIdx.x;
+    const BItem it = items[blockIdx.x];
+    const BPass &P = A.passes[it.pass];
+    const BCirc &C = A.circs[P.circ];
+    const PassArgs2 &args = pa[P.p2];
+    const Amp *psi = reinterpret_cast<const Amp *>(A.psi) + C.psi_off;
+    const double2 *mw = A.mw + C.mw_off;
+    const int last = args.nmg - 1;
+    const int nrot = args.mg[last].rot_begin + args.mg[last].rot_count;
+    if ((int)t < nrot) tab[t] = mw[args.rot[t].k];
+    uint32_t tsb = 0;
+    for (int ri = 0; ri < nrot; ++ri) tsb |= (uint32_t)par32(t & args.rot[ri].zt) << ri;
+    __syncthreads();
+    uint64_t Lb0 = 0;
+    {
+        const uint32_t b0 = deposit32(t, args.mg[0].npiv);
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+            if ((b0 >> i) & 1) Lb0 ^= args.v[i];
+    }
+    double accr = 0.0, acci = 0.0;
+    const uint64_t ntiles = 1ull << (C.n - args.b);
+    const uint64_t tile0 = (uint64_t)it.idx * (uint64_t)P.tiles_per_item;
+    const uint64_t tile1 = std::min<uint64_t>(ntiles, tile0 + (uint64_t)P.tiles_per_item);
+#pragma unroll 1
+    for (uint64_t tile = tile0; tile < tile1; ++tile) {
+        asm volatile("" : "+v"(Lb0));
+        const uint64_t tb = deposit(tile, args.outer_mask);
+        double2 r[kRegs];
+        const uint64_t y0 = tb ^ Lb0;
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) r[j] = ld(psi[y0 ^ args.LU_first[j]]);
+        uint32_t bprev = 0;
+#pragma unroll 1
+        for (int g = 0; g <= last; ++g) {
+            const MGDesc2 &m = args.mg[g];
+            const uint32_t bt = deposit32(t, m.npiv);
+            if (g > 0) {
+                const MGDesc2 &mp = args.mg[g - 1];
+#pragma unroll
+                for (int j = 0; j < kRegs; ++j) st(lds[bprev ^ mp.U[j]], r[j]);
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < kRegs; ++j) r[j] = ld(lds[bt ^ m.U[j]]);
+                __syncthreads();
+            }
+            bprev = bt;
+#pragma unroll 1
+            for (int ri = m.rot_begin; ri < m.rot_begin + m.rot_count; ++ri) {
+                // the amplitudes do not change between terms: keep the products
+                // of all partner masks from being hoisted out of the loop
+#pragma unroll
+                for (int j = 0; j < kRegs; ++j) asm volatile("" : "+v"(r[j].x), "+v"(r[j].y));
+                const RotDesc2 &d = args.rot[ri];
+                const double2 w = tab[ri];
+                const uint32_t sg = ((tsb >> ri) ^ (uint32_t)par64(tb & d.z)) & 1u;
+                measure_dispatch<3, 0>(d.cx, d.msign, r, flip_if(w.x, sg), flip_if(w.y, sg), accr, acci);
+            }
+        }
+    }
+    accr = wave_sum<64>(accr);
+    if ((t & 63) == 0) red[t >> 6] = accr;
+    __syncthreads();
+    if (t == 0) {
+        double sr = 0.0;
+        for (int i = 0; i < NW; ++i) sr += red[i];
+        double *slot = A.epart + C.epart_off + it.idx;
+        *slot = (P.flags & kFlagAccumulate) ? *slot + sr : sr;
+    }
+}
+
 template <typename KernelFn>
 cfh_status set_lds_limit(KernelFn fn, const char *what)
 {
@@ -244,6 +326,22 @@ cfh_status launch_batch_fwd2(unsigned grid, hipStream_t s, const BatchArgs &A, c
 }
 
 template <typename Amp>
+cfh_status launch_batch_meas2(unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,
+                              const BItem *items)
+{
+    constexpr int B = kBatchRegTile;
+    constexpr int T = 1 << (B - kRegDims);
+    constexpr size_t lds = ((size_t)1 << B) * sizeof(Amp);
+    static bool attr = false;
+    if (!attr) {
+        if (cfh_status st = set_lds_limit(&k_batch_meas2<Amp, B>, "k_batch_meas2: LDS limit")) return st;
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_batch_meas2<Amp, B>), dim3(grid), dim3(T), lds, s, A, pa, items);
+    return last_launch("k_batch_meas2");
+}
+
+template <typename Amp>
 cfh_status launch_batch_adj2(unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,
                              const BItem *items)
 {
@@ -263,6 +361,10 @@ template cfh_status launch_batch_fwd2<double2>(unsigned, hipStream_t, const Batc
                                                const BItem *);
 template cfh_status launch_batch_fwd2<float2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
                                               const BItem *);
+template cfh_status launch_batch_meas2<double2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
+                                                const BItem *);
+template cfh_status launch_batch_meas2<float2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
+                                               const BItem *);
 template cfh_status launch_batch_adj2<double2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
                                                const BItem *);
 template cfh_status launch_batch_adj2<float2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,

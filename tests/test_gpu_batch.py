@@ -139,7 +139,13 @@ def test_batch_hipgraph_replays_are_deterministic():
         (x * 2).sum().item()
     B.graph_launch(False, s)
     fwd = B.results(stream=s)
-    assert np.array_equal(fwd["energy"], ref["energy"])
+    # forward runs take E from read-only measurement passes, gradient runs
+    # from Re <psi|H psi>: equal up to rounding
+    scale = np.array([np.abs(w.coeff).sum() for w in ws])
+    assert np.all(np.abs(fwd["energy"] - ref["energy"]) <= 1e-12 * scale)
+    for rep in range(2):
+        B.graph_launch(False, s)
+        assert np.array_equal(B.results(stream=s)["energy"], fwd["energy"]), rep
 
 
 def test_batch_new_angles():
