@@ -252,21 +252,42 @@ __global__ void __launch_bounds__(kBThreads) k_batch_level(const BatchArgs A, co
 }
 
 // Fixed-order reduction of the per-item partial sums of one pass per workgroup.
+// The items' partials are split over the workgroup (kBThreads / kMaxRun
+// lanes per gradient slot, every lane a strided share of the items) and the
+// lane sums added in a fixed order, so results are bitwise reproducible.
 __global__ void __launch_bounds__(kBThreads) k_batch_reduce(const BatchArgs A, const int *__restrict__ passes)
 {
+    constexpr int LANES = kBThreads / kMaxRun;  // item lanes per gradient slot
+    __shared__ double sh[kBThreads];
     const int t = threadIdx.x;
     const int p = passes[blockIdx.x];
     const BPass &P = A.passes[p];
     const BCirc &C = A.circs[P.circ];
-    if (P.type == kPassAdj && t < P.count) {
+    if (P.type == kPassAdj) {
+        const int r = t % kMaxRun, lane = t / kMaxRun;
         double s = 0.0;
-        for (int i = 0; i < P.nitems; ++i) s += A.gpart[C.gpart_off + (int64_t)i * kMaxRun + t];
-        A.grad[C.theta_off + A.rot[P.first + t].k] = s;
+        if (r < P.count)
+            for (int i = lane; i < P.nitems; i += LANES) s += A.gpart[C.gpart_off + (int64_t)i * kMaxRun + r];
+        sh[t] = s;
+        __syncthreads();
+        if (t < P.count) {
+            double g = 0.0;
+            for (int l = 0; l < LANES; ++l) g += sh[l * kMaxRun + t];
+            A.grad[C.theta_off + A.rot[P.first + t].k] = g;
+        }
+        __syncthreads();
     }
-    if ((P.flags & kFlagEnergy) && t == 0) {
+    if (P.flags & kFlagEnergy) {
         double s = 0.0;
-        for (int i = 0; i < P.nitems; ++i) s += A.epart[C.epart_off + i];
-        A.energy[P.circ] = s;
+        if (t < kMaxRun)
+            for (int i = t; i < P.nitems; i += kMaxRun) s += A.epart[C.epart_off + i];
+        sh[t] = s;
+        __syncthreads();
+        if (t == 0) {
+            double e = 0.0;
+            for (int l = 0; l < kMaxRun; ++l) e += sh[l];
+            A.energy[P.circ] = e;
+        }
     }
     const bool ends = A.with_grad ? P.end_flag_grad : (P.flags & kFlagEnd);
     if (ends && t == 0) A.t_end[P.circ] = wall_clock64();
