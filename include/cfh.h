@@ -90,7 +90,10 @@ typedef struct cfh_tuning {
                               sign mask, real/imaginary) so member signs cost no instructions,
                               5 = as 4 with the transposes between micro-groups done in two
                               halves through half the LDS (tile_bits 10..14).  Every variant but 1
-                              also selects the register-tiled adjoint sweep (1: LDS-staged) */
+                              also selects the register-tiled adjoint sweep (1: LDS-staged).
+                              Batches: 0 = register-tiled forward, adjoint and measurement passes
+                              on 2^12 tiles for circuits with n >= 12 (LDS-staged H psi passes and
+                              small circuits), 2 = LDS-staged passes only */
     int32_t batch_items;   /* batched runs: at most this many work items per pass (0 = 32) */
     int32_t group_mib;     /* batched runs: circuits are scheduled in consecutive groups whose
                               state and lam vectors fit this many MiB (so the 256 MiB Infinity Cache
@@ -286,15 +289,18 @@ typedef struct cfh_circuit_desc {
 } cfh_circuit_desc;
 
 /* Build a batch of `count` independent circuits with their own qubit
- * counts, rotations, angles and observables.  Each circuit is planned into
- * fused rotation passes (tiles of 2^min(n, tile_bits) amplitudes, default
- * 2^10), read-only Hamiltonian passes and adjoint passes; the passes are cut
+ * counts, rotations, angles and observables.  By default (tuning variant 0)
+ * a circuit with n >= 12 is planned into fused rotation passes on register
+ * tiles of 2^12 amplitudes, read-only measurement passes (forward runs),
+ * H psi passes on LDS tiles of 2^min(n, tile_bits) amplitudes (default 2^10)
+ * and register-tiled adjoint passes (gradient runs); smaller circuits, and
+ * every circuit under variant 2, use LDS-staged passes only.  Passes are cut
  * into at most tuning->batch_items work items each and queued level by level
  * across circuits.  States, angles, gradients, partial sums and the queue
  * live in one library-owned device allocation.  tuning may be NULL.
  * Errors: CFH_E_INVAL, CFH_E_RANGE, CFH_E_NOT_HERMITIAN, CFH_E_UNSUPPORTED
- * (n outside 8..30, tile_bits outside 8..11 for c128 or 8..12 for c64),
- * CFH_E_NOMEM, CFH_E_HIP. */
+ * (n outside 8..30, tile_bits outside 8..11 for c128 or 8..12 for c64,
+ * variant other than 0 or 2), CFH_E_NOMEM, CFH_E_HIP. */
 cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, const cfh_tuning *tuning,
                             cfh_batch *out);
 cfh_status cfh_batch_destroy(cfh_batch b);
