@@ -91,9 +91,8 @@ typedef struct cfh_tuning {
                               5 = as 4 with the transposes between micro-groups done in two
                               halves through half the LDS (tile_bits 10..14).  Every variant but 1
                               also selects the register-tiled adjoint sweep (1: LDS-staged).
-                              Batches: 0 = register-tiled forward, adjoint and measurement passes
-                              on 2^12 tiles for circuits with n >= 12 (LDS-staged H psi passes and
-                              small circuits), 2 = LDS-staged passes only */
+                              Batches: 0 = register-tiled passes on 2^12 tiles for circuits with
+                              n >= 12 (LDS-staged for smaller ones), 2 = LDS-staged passes only */
     int32_t batch_items;   /* batched runs: at most this many work items per pass (0 = 32) */
     int32_t group_mib;     /* batched runs: circuits are scheduled in consecutive groups whose
                               state and lam vectors fit this many MiB (so the 256 MiB Infinity Cache
@@ -292,9 +291,9 @@ typedef struct cfh_circuit_desc {
  * counts, rotations, angles and observables.  By default (tuning variant 0)
  * a circuit with n >= 12 is planned into fused rotation passes on register
  * tiles of 2^12 amplitudes, read-only measurement passes (forward runs),
- * H psi passes on LDS tiles of 2^min(n, tile_bits) amplitudes (default 2^10)
- * and register-tiled adjoint passes (gradient runs); smaller circuits, and
- * every circuit under variant 2, use LDS-staged passes only.  Passes are cut
+ * and H psi and adjoint passes on register tiles (gradient runs); smaller
+ * circuits, and every circuit under variant 2, use LDS-staged passes on tiles
+ * of 2^min(n, tile_bits) amplitudes (default 2^10) only.  Passes are cut
  * into at most tuning->batch_items work items each and queued level by level
  * across circuits.  States, angles, gradients, partial sums and the queue
  * live in one library-owned device allocation.  tuning may be NULL.

@@ -517,7 +517,7 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
             while (!todo.empty()) {
                 PassPlan pp = std::move(todo.back());
                 todo.pop_back();
-                if (!build_pass_args2(pp, r, false, false, a2)) {
+                if (!build_pass_args2(pp, r, false, batch_fwd_half((int)ab), a2)) {
                     if (pp.rots.size() < 2)
                         return set_error(CFH_E_INVAL, "cfh_batch_create: a rotation does not fit the register tile");
                     PassPlan hi = pp;
@@ -621,8 +621,11 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
         if (ham_ids.empty()) return set_error(CFH_E_INVAL, "cfh_batch_create: every circuit needs an observable");
         // forward runs of register-tiled circuits need only E: read-only
         // measurement passes on register tiles instead of writing lam = H psi
-        std::vector<int> meas_ids;
+        std::vector<int> meas_ids, ham2_ids;
         if (reg) {
+            // terms planned on register tiles: read-only measurement passes for
+            // forward runs, H psi passes (anchored, half-tile transposes of psi
+            // and lam) for gradient runs
             cfh_tuning t3{};
             t3.tile_bits = kBatchRegTile;
             const TuningResolved tm = resolve_tuning(&t3, d.n, dtype, kTuneMeasure);
@@ -634,42 +637,49 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
                                                                                        g.terms.size(), i + kMaxRun))});
             std::vector<Pauli> tp(d.mh);
             for (int64_t i = 0; i < d.mh; ++i) tp[i] = Pauli{d.terms[i].x, d.terms[i].z, d.terms[i].e & 3};
-            std::vector<PassPlan> todo;
-            for (const HamPass &mp : plan_hamiltonian(d.n, mgr, tm, kMaxGroupsPerPass, kMaxRun)) {
-                std::vector<int> idx;
-                for (int g : mp.groups) idx.insert(idx.end(), mgr[g].terms.begin(), mgr[g].terms.end());
-                PassPlan pp;
-                pp.b = mp.b;
-                pp.outer_mask = mp.outer_mask;
-                pp.v = mp.v;
-                pp.rots = order_for_microgroups(mp.v, tp, idx, false);
-                todo.push_back(std::move(pp));
-            }
-            std::reverse(todo.begin(), todo.end());
-            PassArgs2 a3;
-            while (!todo.empty()) {
-                PassPlan pp = std::move(todo.back());
-                todo.pop_back();
-                if (!build_pass_args2(pp, tp, false, false, a3)) {
-                    if (pp.rots.size() < 2)
-                        return set_error(CFH_E_INVAL, "cfh_batch_create: a term does not fit the register tile");
-                    PassPlan hi = pp;
-                    const size_t half = pp.rots.size() / 2;
-                    hi.rots.assign(pp.rots.begin() + (std::ptrdiff_t)half, pp.rots.end());
-                    pp.rots.resize(half);
-                    todo.push_back(std::move(hi));
+            const std::vector<HamPass> mps = plan_hamiltonian(d.n, mgr, tm, kMaxGroupsPerPass, kMaxRun);
+            for (const bool anchored : {false, true}) {
+                std::vector<int> &ids = anchored ? ham2_ids : meas_ids;
+                std::vector<PassPlan> todo;
+                for (const HamPass &mp : mps) {
+                    std::vector<int> idx;
+                    for (int g : mp.groups) idx.insert(idx.end(), mgr[g].terms.begin(), mgr[g].terms.end());
+                    PassPlan pp;
+                    pp.b = mp.b;
+                    pp.outer_mask = mp.outer_mask;
+                    pp.v = mp.v;
+                    pp.rots = order_for_microgroups(mp.v, tp, idx, anchored);
                     todo.push_back(std::move(pp));
-                    continue;
                 }
-                if (a3.b != kBatchRegTile) return set_error(CFH_E_INVAL, "cfh_batch_create: register tile size");
-                const int id = new_pass(kPassMeas, kBatchRegTile, pp.outer_mask, pp.v, 0, (int)pp.rots.size(),
-                                        meas_ids.empty() ? 0 : kFlagAccumulate);
-                B->passes[id].p2 = (int)pa.size();
-                B->passes[id].nitems = nitems2;
-                B->passes[id].tiles_per_item = tpi2;
-                pa.push_back(a3);
-                meas_ids.push_back(id);
+                std::reverse(todo.begin(), todo.end());
+                PassArgs2 a3;
+                while (!todo.empty()) {
+                    PassPlan pp = std::move(todo.back());
+                    todo.pop_back();
+                    if (!build_pass_args2(pp, tp, false, anchored, a3)) {
+                        if (pp.rots.size() < 2)
+                            return set_error(CFH_E_INVAL, "cfh_batch_create: a term does not fit the register tile");
+                        PassPlan hi = pp;
+                        const size_t half = pp.rots.size() / 2;
+                        hi.rots.assign(pp.rots.begin() + (std::ptrdiff_t)half, pp.rots.end());
+                        pp.rots.resize(half);
+                        todo.push_back(std::move(hi));
+                        todo.push_back(std::move(pp));
+                        continue;
+                    }
+                    if (a3.b != kBatchRegTile) return set_error(CFH_E_INVAL, "cfh_batch_create: register tile size");
+                    const int id = new_pass(anchored ? kPassHam : kPassMeas, kBatchRegTile, pp.outer_mask, pp.v, 0,
+                                            (int)pp.rots.size(), ids.empty() ? 0 : kFlagAccumulate);
+                    B->passes[id].p2 = (int)pa.size();
+                    B->passes[id].nitems = nitems2;
+                    B->passes[id].tiles_per_item = tpi2;
+                    pa.push_back(a3);
+                    ids.push_back(id);
+                }
             }
+            if (meas_ids.empty() || ham2_ids.empty())
+                return set_error(CFH_E_INVAL, "cfh_batch_create: every circuit needs an observable");
+            B->passes[ham2_ids.back()].flags |= kFlagEnergy | kFlagEnd;
             if (meas_ids.empty()) return set_error(CFH_E_INVAL, "cfh_batch_create: every circuit needs an observable");
             B->passes[meas_ids.back()].flags |= kFlagEnergy | kFlagEnd;
         }
@@ -688,7 +698,10 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
         if (meas_ids.empty()) chain.insert(chain.end(), ham_ids.begin(), ham_ids.end());
         chain_fwd[c] = chain;
         chain = fwd_ids;
-        chain.insert(chain.end(), ham_ids.begin(), ham_ids.end());
+        if (reg)
+            chain.insert(chain.end(), ham2_ids.begin(), ham2_ids.end());
+        else
+            chain.insert(chain.end(), ham_ids.begin(), ham_ids.end());
         chain.insert(chain.end(), adj_ids.begin(), adj_ids.end());
         chain_grad[c] = chain;
     }
@@ -735,6 +748,7 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
                     const int kk = B->passes[p].p2 < 0 ? kKernLds
                                    : ty == kPassAdj    ? kKernAdj2
                                    : ty == kPassMeas   ? kKernMeas2
+                                   : ty == kPassHam    ? kKernHam2
                                                        : kKernFwd2;
                     auto &dst = items[g][kk];
                     for (int i = 0; i < B->passes[p].nitems; ++i) dst.push_back(BItem{p, i});
@@ -897,9 +911,13 @@ cfh_status cfh_batch_run(cfh_batch b, int with_grad, void *stream)
                 st = c128 ? launch_batch_adj2<double2>(n, s, A, b->d_pa, it)
                           : launch_batch_adj2<float2>(n, s, A, b->d_pa, it);
                 break;
-            default:
+            case kKernMeas2:
                 st = c128 ? launch_batch_meas2<double2>(n, s, A, b->d_pa, it)
                           : launch_batch_meas2<float2>(n, s, A, b->d_pa, it);
+                break;
+            default:
+                st = c128 ? launch_batch_ham2<double2>(n, s, A, b->d_pa, it)
+                          : launch_batch_ham2<float2>(n, s, A, b->d_pa, it);
                 break;
             }
             if (st) return st;

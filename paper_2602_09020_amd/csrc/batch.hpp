@@ -15,7 +15,7 @@ constexpr int kBWaves = kBThreads / 64;
 
 enum { kPassFwd = 0, kPassHam = 1, kPassAdj = 2, kPassMeas = 3 };
 // Kernels that run a level's work items.
-enum { kKernLds = 0, kKernFwd2 = 1, kKernAdj2 = 2, kKernMeas2 = 3, kKernCount = 4 };
+enum { kKernLds = 0, kKernFwd2 = 1, kKernAdj2 = 2, kKernMeas2 = 3, kKernHam2 = 4, kKernCount = 5 };
 enum { kFlagInit = 1, kFlagAccumulate = 2, kFlagEnergy = 4, kFlagStart = 8, kFlagEnd = 16 };
 
 struct BPass {
@@ -71,6 +71,10 @@ struct BatchArgs {
 // PassArgs2 is pa[passes[item.pass].p2].  The first pass of a circuit builds
 // its basis state instead of reading psi.
 constexpr int kBatchRegTile = 12;
+// Complex128 forward items transpose in two halves through half the LDS
+// (anchored micro-groups), so four workgroups fit on a CU as complex64 ones
+// do with whole-tile transposes.
+constexpr bool batch_fwd_half(int amp_bytes) { return amp_bytes == 16; }
 template <typename Amp>
 cfh_status launch_batch_fwd2(unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,
                              const BItem *items);
@@ -89,6 +93,17 @@ extern template cfh_status launch_batch_meas2<double2>(unsigned, hipStream_t, co
                                                        const BItem *);
 extern template cfh_status launch_batch_meas2<float2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
                                                       const BItem *);
+
+// Register-tiled H psi items (gradient runs): lam (+)= sum_k w_k P_k psi on
+// the pass's terms; the circuit's last such pass also writes the energy
+// partials Re <psi|lam> of its items.
+template <typename Amp>
+cfh_status launch_batch_ham2(unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,
+                             const BItem *items);
+extern template cfh_status launch_batch_ham2<double2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
+                                                      const BItem *);
+extern template cfh_status launch_batch_ham2<float2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
+                                                     const BItem *);
 
 // Register-tiled adjoint items of one level (half-tile transposes of psi and
 // lam): gradient partials per item as the LDS-staged adjoint items write them.

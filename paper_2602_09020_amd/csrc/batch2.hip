@@ -1,5 +1,5 @@
-// Register-tiled forward, adjoint and measurement passes of the batched runs
-// (cfh_batch_*).
+// Register-tiled forward, adjoint, measurement and H psi passes of the
+// batched runs (cfh_batch_*).
 //
 // Same scheme as the single-state register-tiled pass (k_pass2, compile-time
 // pair bodies): a workgroup holds one coset of the pass's 2^b-amplitude tile
@@ -13,7 +13,7 @@
 
 namespace {
 
-template <typename Amp, int B>
+template <typename Amp, int B, bool HALF>
 __global__ void __launch_bounds__(1 << (B - kRegDims))
 k_batch_fwd2(const BatchArgs A, const PassArgs2 *__restrict__ pa, const BItem *__restrict__ items)
 {
@@ -71,12 +71,28 @@ k_batch_fwd2(const BatchArgs A, const PassArgs2 *__restrict__ pa, const BItem *_
             const uint32_t bt = deposit32(t, m.npiv);
             if (g > 0) {
                 const MGDesc2 &mp = args.mg[g - 1];
+                if constexpr (HALF) {
+                    // bprev and bt have 0 at the anchor bit (it is a pivot)
+                    const uint32_t lo = (1u << args.qbit) - 1;
+                    const uint32_t bw = (bprev & lo) | ((bprev >> 1) & ~lo);
+                    const uint32_t br = (bt & lo) | ((bt >> 1) & ~lo);
 #pragma unroll
-                for (int j = 0; j < kRegs; ++j) st(lds[bprev ^ mp.U[j]], r[j]);
-                __syncthreads();
+                    for (int h = 0; h < 2; ++h) {
 #pragma unroll
-                for (int j = 0; j < kRegs; ++j) r[j] = ld(lds[bt ^ m.U[j]]);
-                __syncthreads();
+                        for (int j = h; j < kRegs; j += 2) st(lds[bw ^ mp.UC[j]], r[j]);
+                        __syncthreads();
+#pragma unroll
+                        for (int j = h; j < kRegs; j += 2) r[j] = ld(lds[br ^ m.UC[j]]);
+                        __syncthreads();
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < kRegs; ++j) st(lds[bprev ^ mp.U[j]], r[j]);
+                    __syncthreads();
+#pragma unroll
+                    for (int j = 0; j < kRegs; ++j) r[j] = ld(lds[bt ^ m.U[j]]);
+                    __syncthreads();
+                }
             }
             bprev = bt;
 #pragma unroll 1
@@ -293,6 +309,162 @@ k_batch_meas2(const BatchArgs A, const PassArgs2 *__restrict__ pa, const BItem *
     }
 }
 
+// One term on the registers: lam_j += sigma_j w beta psi_{j ^ CX} for every
+// register j (beta = 1, or i when IMAG), sigma_j the register sign from msign.
+template <int CX, bool IMAG>
+__device__ __forceinline__ void ham_body(const double2 (&r)[kRegs], double2 (&l)[kRegs], double w, uint32_t msign)
+{
+#pragma unroll
+    for (int j = 0; j < kRegs; ++j) {
+        const double wj = flip_if(w, msign >> j);
+        const double2 v = r[j ^ CX];
+        if (IMAG) {
+            l[j].x = fma(-wj, v.y, l[j].x);
+            l[j].y = fma(wj, v.x, l[j].y);
+        } else {
+            l[j].x = fma(wj, v.x, l[j].x);
+            l[j].y = fma(wj, v.y, l[j].y);
+        }
+    }
+}
+
+// Uniform branch tree over the partner mask (bits 3..0) and real/imaginary w.
+template <int BIT, int ACC>
+__device__ __forceinline__ void ham_dispatch(uint32_t cx, bool imag, const double2 (&r)[kRegs], double2 (&l)[kRegs],
+                                             double w, uint32_t msign)
+{
+    if constexpr (BIT < 0) {
+        if (imag)
+            ham_body<ACC, true>(r, l, w, msign);
+        else
+            ham_body<ACC, false>(r, l, w, msign);
+    } else {
+        if (cx & (1u << BIT))
+            ham_dispatch<BIT - 1, ACC | (1 << BIT)>(cx, imag, r, l, w, msign);
+        else
+            ham_dispatch<BIT - 1, ACC>(cx, imag, r, l, w, msign);
+    }
+}
+
+// H psi items (gradient runs): psi and lam of a coset in registers (half-tile
+// transposes of both), lam += sum_k w_k P_k psi over the pass's terms (lam
+// starts at zero on the circuit's first such pass), lam written back; the
+// last pass also adds Re <psi|lam> over the item's cosets to its energy
+// partial.
+template <typename Amp, int B>
+__global__ void __launch_bounds__(1 << (B - kRegDims))
+k_batch_ham2(const BatchArgs A, const PassArgs2 *__restrict__ pa, const BItem *__restrict__ items)
+{
+    constexpr int NW = (1 << (B - kRegDims)) / 64;
+    constexpr int LB = B - 1;
+    extern __shared__ unsigned char lds_raw[];
+    Amp *ldp = reinterpret_cast<Amp *>(lds_raw);
+    Amp *ldl = ldp + (1 << LB);
+    __shared__ double2 tab[kMaxRun];
+    __shared__ double red[NW];
+    const uint32_t t = threadIdx.x;
+    const BItem it = items[blockIdx.x];
+    const BPass &P = A.passes[it.pass];
+    const BCirc &C = A.circs[P.circ];
+    const PassArgs2 &args = pa[P.p2];
+    const Amp *psi = reinterpret_cast<const Amp *>(A.psi) + C.psi_off;
+    Amp *lam = reinterpret_cast<Amp *>(A.lam) + C.psi_off;
+    const double2 *mw = A.mw + C.mw_off;
+    const int last = args.nmg - 1;
+    const int nrot = args.mg[last].rot_begin + args.mg[last].rot_count;
+    if ((int)t < nrot) tab[t] = mw[args.rot[t].k];
+    uint32_t tsb = 0;
+    for (int ri = 0; ri < nrot; ++ri) tsb |= (uint32_t)par32(t & args.rot[ri].zt) << ri;
+    __syncthreads();
+    uint64_t Lb0 = 0, LbL = 0;
+    {
+        const uint32_t b0 = deposit32(t, args.mg[0].npiv), bL = deposit32(t, args.mg[last].npiv);
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            if ((b0 >> i) & 1) Lb0 ^= args.v[i];
+            if ((bL >> i) & 1) LbL ^= args.v[i];
+        }
+    }
+    const bool accumulate = P.flags & kFlagAccumulate;
+    const bool energy = P.flags & kFlagEnergy;
+    double eacc = 0.0;
+    const uint64_t ntiles = 1ull << (C.n - args.b);
+    const uint64_t tile0 = (uint64_t)it.idx * (uint64_t)P.tiles_per_item;
+    const uint64_t tile1 = std::min<uint64_t>(ntiles, tile0 + (uint64_t)P.tiles_per_item);
+#pragma unroll 1
+    for (uint64_t tile = tile0; tile < tile1; ++tile) {
+        asm volatile("" : "+v"(Lb0), "+v"(LbL));
+        const uint64_t tb = deposit(tile, args.outer_mask);
+        double2 p[kRegs], l[kRegs];
+        {
+            const uint64_t y0 = tb ^ Lb0;
+#pragma unroll
+            for (int j = 0; j < kRegs; ++j) {
+                p[j] = ld(psi[y0 ^ args.LU_first[j]]);
+                l[j] = accumulate ? ld(lam[y0 ^ args.LU_first[j]]) : make_double2(0.0, 0.0);
+            }
+        }
+        uint32_t bprev = 0;
+#pragma unroll 1
+        for (int g = 0; g <= last; ++g) {
+            const MGDesc2 &m = args.mg[g];
+            const uint32_t bt = deposit32(t, m.npiv);
+            if (g > 0) {
+                const MGDesc2 &mp = args.mg[g - 1];
+                // bprev and bt have 0 at the anchor bit (it is a pivot)
+                const uint32_t lo = (1u << args.qbit) - 1;
+                const uint32_t bw = (bprev & lo) | ((bprev >> 1) & ~lo);
+                const uint32_t br = (bt & lo) | ((bt >> 1) & ~lo);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                    for (int j = h; j < kRegs; j += 2) {
+                        st(ldp[bw ^ mp.UC[j]], p[j]);
+                        st(ldl[bw ^ mp.UC[j]], l[j]);
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int j = h; j < kRegs; j += 2) {
+                        p[j] = ld(ldp[br ^ m.UC[j]]);
+                        l[j] = ld(ldl[br ^ m.UC[j]]);
+                    }
+                    __syncthreads();
+                }
+            }
+            bprev = bt;
+#pragma unroll 1
+            for (int ri = m.rot_begin; ri < m.rot_begin + m.rot_count; ++ri) {
+                const RotDesc2 &d = args.rot[ri];
+                const double2 w = tab[ri];
+                const bool imag = w.y != 0.0;
+                const uint32_t sg = ((tsb >> ri) ^ (uint32_t)par64(tb & d.z)) & 1u;
+                ham_dispatch<3, 0>(d.cx, imag, p, l, flip_if(imag ? w.y : w.x, sg), d.msign);
+            }
+        }
+        const uint64_t yL = tb ^ LbL;
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) {
+            st(lam[yL ^ args.LU_last[j]], l[j]);
+            if (energy) {
+                Amp stored;  // lam as stored (rounded to the storage type)
+                st(stored, l[j]);
+                const double2 o = ld(stored);
+                eacc += p[j].x * o.x + p[j].y * o.y;
+            }
+        }
+    }
+    if (energy) {
+        eacc = wave_sum<64>(eacc);
+        if ((t & 63) == 0) red[t >> 6] = eacc;
+        __syncthreads();
+        if (t == 0) {
+            double sr = 0.0;
+            for (int i = 0; i < NW; ++i) sr += red[i];
+            A.epart[C.epart_off + it.idx] = sr;
+        }
+    }
+}
+
 template <typename KernelFn>
 cfh_status set_lds_limit(KernelFn fn, const char *what)
 {
@@ -315,13 +487,14 @@ cfh_status launch_batch_fwd2(unsigned grid, hipStream_t s, const BatchArgs &A, c
 {
     constexpr int B = kBatchRegTile;
     constexpr int T = 1 << (B - kRegDims);
-    constexpr size_t lds = ((size_t)1 << B) * sizeof(Amp);
+    constexpr bool HALF = batch_fwd_half((int)sizeof(Amp));
+    constexpr size_t lds = ((size_t)1 << (HALF ? B - 1 : B)) * sizeof(Amp);
     static bool attr = false;
     if (!attr) {
-        if (cfh_status st = set_lds_limit(&k_batch_fwd2<Amp, B>, "k_batch_fwd2: LDS limit")) return st;
+        if (cfh_status st = set_lds_limit(&k_batch_fwd2<Amp, B, HALF>, "k_batch_fwd2: LDS limit")) return st;
         attr = true;
     }
-    hipLaunchKernelGGL((k_batch_fwd2<Amp, B>), dim3(grid), dim3(T), lds, s, A, pa, items);
+    hipLaunchKernelGGL((k_batch_fwd2<Amp, B, HALF>), dim3(grid), dim3(T), lds, s, A, pa, items);
     return last_launch("k_batch_fwd2");
 }
 
@@ -339,6 +512,22 @@ cfh_status launch_batch_meas2(unsigned grid, hipStream_t s, const BatchArgs &A, 
     }
     hipLaunchKernelGGL((k_batch_meas2<Amp, B>), dim3(grid), dim3(T), lds, s, A, pa, items);
     return last_launch("k_batch_meas2");
+}
+
+template <typename Amp>
+cfh_status launch_batch_ham2(unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,
+                             const BItem *items)
+{
+    constexpr int B = kBatchRegTile;
+    constexpr int T = 1 << (B - kRegDims);
+    constexpr size_t lds = 2 * ((size_t)1 << (B - 1)) * sizeof(Amp);  // half-tile buffers of psi and lam
+    static bool attr = false;
+    if (!attr) {
+        if (cfh_status st = set_lds_limit(&k_batch_ham2<Amp, B>, "k_batch_ham2: LDS limit")) return st;
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_batch_ham2<Amp, B>), dim3(grid), dim3(T), lds, s, A, pa, items);
+    return last_launch("k_batch_ham2");
 }
 
 template <typename Amp>
@@ -365,6 +554,10 @@ template cfh_status launch_batch_meas2<double2>(unsigned, hipStream_t, const Bat
                                                 const BItem *);
 template cfh_status launch_batch_meas2<float2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
                                                const BItem *);
+template cfh_status launch_batch_ham2<double2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
+                                               const BItem *);
+template cfh_status launch_batch_ham2<float2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
+                                              const BItem *);
 template cfh_status launch_batch_adj2<double2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
                                                const BItem *);
 template cfh_status launch_batch_adj2<float2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,

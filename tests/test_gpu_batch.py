@@ -62,9 +62,14 @@ def test_batch_register_tiled_forward_vs_oracle(dtype, tol):
     for i, n in enumerate((12, 13, 14, 15, 12)):
         w = W.make_workload(f"r{i}", n, seed=300 + i, n_prefix=2 * n, n_rot=int(rng.integers(60, 160)), n_ham=25)
         if i == 4:
-            # dense random strings: every partner mask and register sign mask
+            # dense random strings: every partner mask and register sign mask;
+            # the observable gains dense and diagonal (Z-only) terms
             w.rot = rng.integers(0, 4, size=(200, n)).astype(np.uint8)
             w.theta = rng.uniform(-np.pi, np.pi, size=200)
+            extra = np.concatenate([rng.integers(0, 4, size=(30, n)),
+                                    np.where(rng.integers(0, 2, size=(10, n)) == 1, 3, 0)]).astype(np.uint8)
+            w.ham = np.concatenate([w.ham, extra])
+            w.coeff = np.concatenate([w.coeff, rng.normal(size=extra.shape[0])])
         ws.append(w)
     out = {}
     for variant in (0, 2):
@@ -79,7 +84,12 @@ def test_batch_register_tiled_forward_vs_oracle(dtype, tol):
         assert abs(out[0][0][i] - sim.energy(psi, w.n, w.ham, w.coeff)) <= tol * scale, i
         assert np.abs(out[0][1][i] - out[2][1][i]).max() <= tol, i
     if dtype == torch.complex128:
-        g = [W.make_workload(f"rg{i}", 12, seed=400 + i, n_prefix=20, n_rot=30, n_ham=15) for i in range(2)]
+        g = [W.make_workload(f"rg{i}", 12 + i, seed=400 + i, n_prefix=20, n_rot=30, n_ham=15) for i in range(2)]
+        # dense and diagonal terms in the observable of the second circuit
+        extra = np.concatenate([rng.integers(0, 4, size=(12, 13)),
+                                np.where(rng.integers(0, 2, size=(6, 13)) == 1, 3, 0)]).astype(np.uint8)
+        g[1].ham = np.concatenate([g[1].ham, extra])
+        g[1].coeff = np.concatenate([g[1].coeff, rng.normal(size=extra.shape[0])])
         B = hybrid.Batch(g, dtype)
         B.run(with_grad=True)
         r = B.results()
