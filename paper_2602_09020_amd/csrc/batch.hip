@@ -490,9 +490,9 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
             B->passes.push_back(P);
             return (int)B->passes.size() - 1;
         };
-        // LDS-staged plan: the forward passes of small circuits (or of tuning
-        // variant 2) and, walked backwards, the adjoint passes of every circuit
-        const std::vector<PassPlan> fw = plan_rotations(d.n, r, tu);
+        // LDS-staged plan of circuits below the register tile (or under tuning
+        // variant 2): forward passes and, walked backwards, adjoint passes
+        const std::vector<PassPlan> fw = reg ? std::vector<PassPlan>() : plan_rotations(d.n, r, tu);
         std::vector<int> fw_lds;  // LDS-staged pass of fw[i]
         for (size_t i = 0; i < fw.size(); ++i) {
             const int first = (int)rots.size();
@@ -588,7 +588,7 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
             }
         }
         std::vector<int> ham_ids;
-        const std::vector<HamPass> hp = plan_hamiltonian(d.n, groups, tu);
+        const std::vector<HamPass> hp = reg ? std::vector<HamPass>() : plan_hamiltonian(d.n, groups, tu);
         for (size_t i = 0; i < hp.size(); ++i) {
             const int first = (int)gdev.size();
             for (int g : hp[i].groups) {
@@ -618,7 +618,8 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
             ham_ids.push_back(new_pass(kPassHam, hp[i].b, hp[i].outer_mask, hp[i].v, first,
                                        (int)hp[i].groups.size(), flags));
         }
-        if (ham_ids.empty()) return set_error(CFH_E_INVAL, "cfh_batch_create: every circuit needs an observable");
+        if (!reg && ham_ids.empty())
+            return set_error(CFH_E_INVAL, "cfh_batch_create: every circuit needs an observable");
         // forward runs of register-tiled circuits need only E: read-only
         // measurement passes on register tiles instead of writing lam = H psi
         std::vector<int> meas_ids, ham2_ids;
