@@ -177,7 +177,7 @@ def main():
     energy = float(e_out[0].item())
     value = K / (ms_per_step * 1e-3)
     tb, var = infos[0]["tile_bits"], infos[0]["variant"]
-    kname = f"k_pass2<double2,{tb},{ {2: 1, 3: 0, 4: 2, 5: 6}[var]}>" if var >= 2 else \
+    kname = f"k_pass2<double2,{tb},{ {2: 1, 3: 0, 4: 18, 5: 22}[var]}>" if var >= 2 else \
         f"k_pass<double2,{tb}>"
     traffic = counter_traffic(f"{kname.split('<')[0]}_n{n}_c128_counters.json", kname)
     del keep

@@ -88,6 +88,8 @@ typedef struct cfh_tuning {
                               needs tile_bits in 10..13), 3 = register-tiled without the prefetch,
                               4 = register-tiled, one unrolled body per (partner mask, register
                               sign mask, real/imaginary) so member signs cost no instructions,
+                              rotations with |sin| <= |cos| in the tangent form (4 FMAs a pair,
+                              the product of their cosines applied once per coset),
                               5 = as 4 with the transposes between micro-groups done in two
                               halves through half the LDS (tile_bits 10..14).  Every variant but 1
                               also selects the register-tiled adjoint sweep (1: LDS-staged).

@@ -711,7 +711,7 @@ struct cfh_plan_s {
     std::vector<PassPlan> passes;
     std::vector<PassArgs> args;
     bool v2 = false;                      // register-tiled kernel for the forward/inverse sweep
-    int mode2 = 0;                        // its prefetch / non-temporal mode bits
+    int mode2 = 0;                        // k_pass2 MODE bits of the forward passes
     std::vector<PassArgs2> args2, args2_inv;
     double2 *coef = nullptr;     // device, m entries
     double *gpart = nullptr;     // device, adj_grid * kMaxRun
@@ -855,7 +855,9 @@ cfh_status cfh_plan_create(int n, int dtype, const cfh_pauli *rot, size_t m, con
         int v = p->tu.variant;
         if (v == 0) v = b == 14 ? 5 : (b >= 10 && b <= 13) ? 4 : 1;
         p->tu.variant = v;
-        p->mode2 = v == 2 ? 1 : v == 4 ? 2 : v == 5 ? 6 : 0;
+        // compile-time bodies in the tangent form (MODE bit 4), half-tile
+        // transposes for variant 5
+        p->mode2 = v == 2 ? 1 : v == 4 ? 18 : v == 5 ? 22 : 0;
         if (v >= 2) {
             // A run that needs more micro-groups than the kernel carries (long
             // runs of dense masks) is split in two on the same tile basis; the

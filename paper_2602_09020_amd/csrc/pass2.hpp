@@ -95,9 +95,14 @@ __device__ __forceinline__ void mg_dispatch(int cx, double2 (&r)[kRegs], double 
 // the signs become negations of FMA operands instead of sign arithmetic.
 constexpr bool cpar(int v) { return __builtin_popcount(v) & 1; }
 
-template <int KASE>
-__device__ __forceinline__ void kase_body(double2 (&r)[kRegs], double c, double s)
+// TAN: the tangent form of the same update, c(u + t sigma beta v) with
+// t = s / c: the factor c is left out (the caller applies the product of the
+// pass's factors at the end), so a pair costs 4 FMAs instead of 4 MULs and
+// 4 FMAs.  Callers pass c = 1 and s = t.
+template <int KASE, bool TAN = false>
+__device__ __forceinline__ void kase_body(double2 (&r)[kRegs], double c_in, double s)
 {
+    const double c = TAN ? 1.0 : c_in;
     constexpr int CX = KASE & 15, ZR = (KASE >> 4) & 15;
     constexpr bool IMAG = (KASE >> 8) & 1;
     if constexpr (CX == 0) {
@@ -127,16 +132,16 @@ __device__ __forceinline__ void kase_body(double2 (&r)[kRegs], double c, double 
 }
 
 // Uniform branch tree over the nine bits of kase (one leaf per body).
-template <int BIT, int ACC>
+template <int BIT, int ACC, bool TAN = false>
 __device__ __forceinline__ void kase_dispatch(uint32_t kase, double2 (&r)[kRegs], double c, double s)
 {
     if constexpr (BIT < 0) {
-        kase_body<ACC>(r, c, s);
+        kase_body<ACC, TAN>(r, c, s);
     } else {
         if (kase & (1u << BIT))
-            kase_dispatch<BIT - 1, ACC | (1 << BIT)>(kase, r, c, s);
+            kase_dispatch<BIT - 1, ACC | (1 << BIT), TAN>(kase, r, c, s);
         else
-            kase_dispatch<BIT - 1, ACC>(kase, r, c, s);
+            kase_dispatch<BIT - 1, ACC, TAN>(kase, r, c, s);
     }
 }
 
@@ -226,7 +231,9 @@ k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2
     constexpr bool CT = MODE & 2;
     constexpr bool HALF = MODE & 4;
     constexpr bool MEAS = MODE & 8;
+    constexpr bool TANF = MODE & 16;
     static_assert(!MEAS || (CT && !PF), "measurement uses the compile-time bodies without prefetch");
+    static_assert(!TANF || (CT && !MEAS), "the tangent form needs the compile-time rotation bodies");
     constexpr int NW = (1 << (B - kRegDims)) / 64;  // waves per workgroup
     extern __shared__ unsigned char lds_raw[];
     Amp *lds = reinterpret_cast<Amp *>(lds_raw);
@@ -235,6 +242,8 @@ k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2
     const uint32_t t = threadIdx.x;
     const int last = args.nmg - 1;
     uint32_t tsb = 0;  // bit ri: parity(t & zt) of rotation ri
+    uint32_t tanm = 0; // bit ri: rotation ri runs in the tangent form (|s| <= |c|)
+    double gscale = 1.0;  // product of c over the tangent-form rotations
     double accr = 0.0, acci = 0.0;
     if constexpr (CT) {
         const int nrot = args.mg[last].rot_begin + args.mg[last].rot_count;
@@ -251,6 +260,19 @@ k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2
         }
         for (int ri = 0; ri < nrot; ++ri) tsb |= (uint32_t)par32(t & args.rot[ri].zt) << ri;
         __syncthreads();
+        if constexpr (TANF) {
+            // every thread forms the same mask and product, in the same order
+            for (int ri = 0; ri < nrot; ++ri) {
+                const double2 cs = tab[ri];
+                if (fabs(cs.y) <= fabs(cs.x)) {
+                    tanm |= 1u << ri;
+                    gscale *= cs.x;
+                }
+            }
+            __syncthreads();
+            if ((int)t < nrot && ((tanm >> t) & 1)) tab[t].y = tab[t].y / tab[t].x;
+            __syncthreads();
+        }
     }
     uint64_t Lb0 = 0, LbL = 0;
     {
@@ -338,7 +360,10 @@ k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2
                     const RotDesc2 &d = args.rot[ri];
                     const double2 cs = tab[ri];
                     const uint32_t sg = ((tsb >> ri) ^ (uint32_t)par64(tb & d.z)) & 1u;
-                    kase_dispatch<8, 0>(d.kase, r, cs.x, flip_if(cs.y, sg));
+                    if (TANF && ((tanm >> ri) & 1))
+                        kase_dispatch<8, 0, true>(d.kase, r, 1.0, flip_if(cs.y, sg));
+                    else
+                        kase_dispatch<8, 0>(d.kase, r, cs.x, flip_if(cs.y, sg));
                 }
             } else {
 #pragma unroll 1
@@ -357,6 +382,10 @@ k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2
             }
         }
         if constexpr (!MEAS) {
+            if constexpr (TANF) {
+#pragma unroll
+                for (int j = 0; j < kRegs; ++j) r[j] = make_double2(r[j].x * gscale, r[j].y * gscale);
+            }
             const uint64_t yL = tb ^ LbL;
 #pragma unroll
             for (int j = 0; j < kRegs; ++j) st(psi[yL ^ args.LU_last[j]], r[j]);
@@ -646,8 +675,8 @@ cfh_status launch_pass2_m(uint64_t ntiles, hipStream_t s, Amp *psi, const double
 {
     switch (mode) {
     case 1: return launch_pass2_b<Amp, B, 1>(ntiles, s, psi, coef, a, partial, max_grid);
-    case 2: return launch_pass2_b<Amp, B, 2>(ntiles, s, psi, coef, a, partial, max_grid);
-    case 6: return launch_pass2_b<Amp, B, 6>(ntiles, s, psi, coef, a, partial, max_grid);
+    case 18: return launch_pass2_b<Amp, B, 18>(ntiles, s, psi, coef, a, partial, max_grid);
+    case 22: return launch_pass2_b<Amp, B, 22>(ntiles, s, psi, coef, a, partial, max_grid);
     case 10: return launch_pass2_b<Amp, B, 10>(ntiles, s, psi, coef, a, partial, max_grid);
     case 14: return launch_pass2_b<Amp, B, 14>(ntiles, s, psi, coef, a, partial, max_grid);
     default: return launch_pass2_b<Amp, B, 0>(ntiles, s, psi, coef, a, partial, max_grid);
@@ -689,7 +718,7 @@ cfh_status launch_pass2(uint64_t ntiles, hipStream_t s, Amp *psi, const double2 
     case 13: return launch_pass2_m<Amp, 13>(ntiles, s, psi, coef, a, mode, partial, max_grid);
     case 14:
         // 1024-thread workgroups; only the half-tile transposes fit 2^14 complex128 in LDS
-        if (mode == 6) return launch_pass2_b<Amp, 14, 6>(ntiles, s, psi, coef, a, partial, max_grid);
+        if (mode == 22) return launch_pass2_b<Amp, 14, 22>(ntiles, s, psi, coef, a, partial, max_grid);
         if (mode == 14) return launch_pass2_b<Amp, 14, 14>(ntiles, s, psi, coef, a, partial, max_grid);
         return set_error(CFH_E_UNSUPPORTED, "tile_bits 14 needs the half-tile register-tiled kernel");
     default: return set_error(CFH_E_UNSUPPORTED, "register-tiled pass needs tile_bits in 10..14");
