@@ -203,6 +203,29 @@ def test_fused_equals_unfused_and_inverse_roundtrip(variant):
     assert (psi_f - ref).abs().max().item() <= 1e-12
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("variant,tb", [(4, 13), (5, 14), (5, 11)])
+def test_tangent_form_large_and_exact_angles(dtype, variant, tb):
+    """Rotations with |sin| <= |cos| run in the tangent form (the cosines'
+    product applied once per coset), the others in the full form: angles of
+    exactly +-pi, 3 pi, 0, tiny and near pi/2 in one run agree with the
+    unfused path and the oracle, and the inverse plan returns the basis state."""
+    w = W.config(3, n=16, n_rot=300, n_ham=5)
+    rng = np.random.default_rng(tb)
+    special = np.array([np.pi, -np.pi, 3 * np.pi, 0.0, 1e-12, np.pi / 2, -np.pi / 2 + 1e-9, np.pi - 1e-9])
+    idx = rng.choice(w.n_rot, size=120, replace=False)
+    w.theta[idx] = special[rng.integers(0, len(special), size=idx.size)]
+    psi_f, _, rot, _, plan, _, theta = run_workload(w, dtype, {"variant": variant, "tile_bits": tb})
+    psi_u, *_ = run_workload(w, dtype, {"unfused": 1})
+    assert (psi_f - psi_u).abs().max().item() <= TOL[dtype]
+    _, phi_ref = sim.simulate(w)
+    assert maxdiff(psi_f, phi_ref) <= TOL[dtype]
+    plan.apply(psi_f, theta, inverse=True)
+    ref = torch.zeros_like(psi_f)
+    ref[w.init] = 1
+    assert (psi_f - ref).abs().max().item() <= TOL[dtype]
+
+
 def test_device_frame_conjugation_matches_host():
     w = W.config(1, n=24, n_rot=500)
     f = hybrid.Frame(w.n)
