@@ -254,6 +254,31 @@ def main():
                              "avg_launch_ms": l_ms / lp, "achieved_gbs": pass_bytes / (l_ms / lp * 1e-3) / 1e9}
         del pl
 
+        # frame flush (amplitude readout) of the 28-qubit state after a dense
+        # random Clifford prefix of 10n gates: rotation list, plan and passes
+        rng_f = np.random.default_rng(7)
+        gates = []
+        for _ in range(10 * n):
+            if rng_f.random() < 0.45:
+                qa, qb = rng_f.choice(n, size=2, replace=False)
+                gates.append((int(rng_f.integers(6, 9)), int(qa), int(qb)))
+            else:
+                gates.append((int(rng_f.integers(0, 6)), int(rng_f.integers(0, n)), -1))
+        gates = np.array(gates, np.int32)
+        ff = hybrid.Frame(n)
+        ff.apply_gates(gates)
+        frot, _ = ff.flush_rotations()
+        cfh.cfh_state_set_basis(psi, n, w.init)
+        plan.apply(psi, theta)
+        torch.cuda.synchronize()
+        t0f = time.perf_counter()
+        ff.flush(psi, stream)
+        f_ms = (time.perf_counter() - t0f) * 1e3
+        f_passes = hybrid.Plan(n, dtype, frot).info()["n_passes"]
+        out["flush"] = {"clifford_gates": int(gates.shape[0]), "rotations": int(frot.shape[0]),
+                        "passes": f_passes, "ms": f_ms}
+        del ff
+
         # complex64 storage, full workload, error against the complex128 result
         cfh.cfh_state_set_basis(psi, n, w.init)
         plan.apply(psi, theta)

@@ -271,6 +271,29 @@ cfh_status cfh_ham_apply(cfh_ham h, const void *psi, void *out, void *stream);
 cfh_status cfh_adjoint_grad(cfh_plan p, cfh_ham h, void *psi, void *lam, const double *theta_dev,
                             double *grad_dev, void *stream);
 
+/* ----------------------------------- frame flush / amplitude readout */
+
+/* The Clifford rotations R_1..R_m (angles theta_k of pi/2 or pi, each
+ * exp(-i theta_k/2 P_k)) that carry the frame back to the identity frame
+ * (Sec. 4.3 and the constructive algorithm of App. A): applied to Phi in
+ * order they give U Phi, the physical state, up to a global phase.
+ * Two rotations per qubit reduce the frame to one-qubit pairs, at most four
+ * one-qubit rotations per qubit turn each pair into (Z, X), and the rows are
+ * moved to their own qubits by SWAPs written as three commuting pi/2
+ * rotations about X_aX_b, Y_aY_b and Z_aZ_b: m <= 9n - 3.  rot and theta are
+ * host arrays of cap entries; *m receives the count.  Host only; the frame is
+ * not changed.  Errors: CFH_E_INVAL (null argument), CFH_E_RANGE (m > cap,
+ * *m set). */
+cfh_status cfh_frame_flush_rotations(cfh_frame f, cfh_pauli *rot, double *theta, size_t cap, size_t *m);
+
+/* Flush the frame into the state: psi (device, 2^n amplitudes of dtype, n
+ * the frame's) becomes U psi up to a global phase, through a fused plan of
+ * the rotations above on `stream`, and the frame becomes the identity, so
+ * the amplitudes of psi are the physical ones.  Synchronous (the call waits
+ * for the device work); allocates and frees the plan and an angle buffer.
+ * Errors: those of cfh_frame_flush_rotations and cfh_plan_create, CFH_E_HIP. */
+cfh_status cfh_frame_flush(cfh_frame f, void *psi, int dtype, void *stream);
+
 /* ----------------------------------------------- a10: batched circuits */
 
 /* One circuit of a batch: n qubits (8..30), its initial basis state, m

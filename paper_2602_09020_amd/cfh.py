@@ -67,6 +67,8 @@ _SIGS = {
     "cfh_frame_conjugate": (C.c_int32, [_vp, _P(cfh_pauli), _P(cfh_pauli)]),
     "cfh_frame_conjugate_many": (C.c_int32, [_vp, _vp, _vp, C.c_size_t]),
     "cfh_frame_conjugate_device": (C.c_int32, [_vp, _vp, _vp, C.c_size_t, _vp]),
+    "cfh_frame_flush_rotations": (C.c_int32, [_vp, _vp, _vp, C.c_size_t, _P(C.c_size_t)]),
+    "cfh_frame_flush": (C.c_int32, [_vp, _vp, C.c_int, _vp]),
     "cfh_state_set_basis": (C.c_int32, [_vp, C.c_int, C.c_int, C.c_uint64, _vp]),
     "cfh_apply_pauli_rotation": (C.c_int32, [_vp, C.c_int, C.c_int, C.c_uint64, C.c_uint64, C.c_int,
                                              C.c_double, _vp]),
@@ -232,6 +234,20 @@ def cfh_frame_conjugate_many(f: int, paulis: np.ndarray) -> np.ndarray:
 
 def cfh_frame_conjugate_device(f: int, in_dev, out_dev, m: int, stream=None) -> None:
     _call("cfh_frame_conjugate_device", f, _dev_ptr(in_dev, "in"), _dev_ptr(out_dev, "out"), m, _stream(stream))
+
+
+def cfh_frame_flush_rotations(f: int, n: int):
+    """(paulis, theta): the rotations that flush the frame into Phi (host only)."""
+    cap = 9 * n + 8
+    rot = np.zeros(cap, PAULI_DTYPE)
+    theta = np.zeros(cap, np.float64)
+    m = C.c_size_t()
+    _call("cfh_frame_flush_rotations", f, rot.ctypes.data, theta.ctypes.data, cap, C.byref(m))
+    return rot[:m.value].copy(), theta[:m.value].copy()
+
+
+def cfh_frame_flush(f: int, psi, stream=None) -> None:
+    _call("cfh_frame_flush", f, _dev_ptr(psi, "psi"), _dtype_code(psi), _stream(stream))
 
 
 # ------------------------------------------------------------------ state

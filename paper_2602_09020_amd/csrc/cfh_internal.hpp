@@ -207,3 +207,11 @@ struct cfh_frame_s {
     int n;
     std::vector<cfh::Pauli> zf, xf;  // effZ_q, effX_q
 };
+
+namespace cfh {
+// Rotations (angles pi/2 or pi) whose product applied to Phi, in order, gives
+// U Phi up to a global phase; the frame is not changed.
+cfh_status frame_flush_rotations(const cfh_frame_s &f, std::vector<Pauli> &rot, std::vector<double> &theta);
+// Rows back to the identity frame (effZ_q = Z_q, effX_q = X_q).
+void frame_reset(cfh_frame_s &f);
+} // namespace cfh

@@ -3,6 +3,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "cfh_internal.hpp"
 
@@ -26,6 +27,133 @@ cfh_status check_pauli(const cfh_pauli &p, int n, bool need_hermitian, const cha
     if (need_hermitian && (p.e & 1))
         return set_error(CFH_E_NOT_HERMITIAN, std::string(what) + ": odd phase exponent (not Hermitian)");
     return CFH_OK;
+}
+
+// P conjugated by the Clifford rotation exp(-i theta/2 Q): a P that commutes
+// with Q is left as it is; otherwise theta = pi/2 gives -i Q P and theta = pi
+// (exp(-i pi/2 Q) = -i Q) gives -P (App. A, note on pi/4 conjugation).
+static Pauli conj_by_rotation(const Pauli &P, const Pauli &Q, bool half_turn)
+{
+    if (!anticommute(P.x, P.z, Q.x, Q.z)) return P;
+    if (half_turn) {
+        Pauli r = P;
+        r.e = (r.e + 2) & 3;
+        return r;
+    }
+    Pauli r = pauli_mul(Q, P);
+    r.e = (r.e + 3) & 3;
+    return r;
+}
+
+// Rotations R_1..R_m (angles pi/2 or pi) with R_m...R_1 U^dag = phase * I for
+// the Clifford U of the frame, so that U Phi = phase * R_m...R_1 Phi: applying
+// them to Phi, in order, flushes the frame into the state (Sec. 4.3, App. A).
+// Conjugating the rows by each rotation tracks U^dag; the rows end as the
+// identity frame, which is checked.
+//  1. For each qubit q, a row i not yet placed whose effZ_i acts on q is
+//     brought to a one-qubit s1 on q by Q = i s1 effZ_i (s1 anticommuting
+//     with effZ_i's letter on q), then its effX_i to a one-qubit s2 on q by
+//     Q' = i s2 effX_i (s2 neither s1 nor effX_i's letter on q); Q' commutes
+//     with s1.  The other rows commute with both, so they no longer act on q,
+//     and later rotations (which do not act on q) leave row i alone.
+//  2. Each row's one-qubit pair is turned into (+Z, +X) by pi/2 rotations
+//     about one-qubit Paulis and pi rotations for the signs.
+//  3. Rows are moved to their own qubits by SWAPs, each the product of the
+//     commuting pi/2 rotations about X_a X_b, Y_a Y_b and Z_a Z_b (a SWAP up
+//     to a global phase).
+cfh_status frame_flush_rotations(const cfh_frame_s &f, std::vector<Pauli> &rot, std::vector<double> &theta)
+{
+    const int n = f.n;
+    std::vector<Pauli> zf = f.zf, xf = f.xf;
+    rot.clear();
+    theta.clear();
+    auto apply = [&](const Pauli &Q, bool half_turn) {
+        for (int i = 0; i < n; ++i) {
+            zf[i] = conj_by_rotation(zf[i], Q, half_turn);
+            xf[i] = conj_by_rotation(xf[i], Q, half_turn);
+        }
+        rot.push_back(Q);
+        theta.push_back(half_turn ? 3.14159265358979323846 : 1.57079632679489661923);
+    };
+    auto single = [](int q, int letter) {  // letters 1 = X, 2 = Y, 3 = Z
+        Pauli p;
+        p.x = (letter == 1 || letter == 2) ? 1ull << q : 0;
+        p.z = (letter == 3 || letter == 2) ? 1ull << q : 0;
+        return p;
+    };
+    auto letter_at = [](const Pauli &p, int q) {
+        const int xb = (int)((p.x >> q) & 1), zb = (int)((p.z >> q) & 1);
+        return xb ? (zb ? 2 : 1) : (zb ? 3 : 0);
+    };
+    auto only_on = [](const Pauli &p, int q) { return ((p.x | p.z) & ~(1ull << q)) == 0; };
+    // Q = i s P for anticommuting s and P: Hermitian, and conjugation maps P to s
+    auto mover = [](const Pauli &s, const Pauli &P) {
+        Pauli Q = pauli_mul(s, P);
+        Q.e = (Q.e + 1) & 3;
+        return Q;
+    };
+    std::vector<int> pos(n, -1);
+    std::vector<char> placed(n, 0);
+    for (int q = 0; q < n; ++q) {
+        int i = -1;
+        for (int k = 0; k < n && i < 0; ++k)
+            if (!placed[k] && (((zf[k].x | zf[k].z) >> q) & 1)) i = k;
+        if (i < 0) return set_error(CFH_E_INVAL, "cfh_frame_flush: the frame rows are not a symplectic basis");
+        const int sig = letter_at(zf[i], q);
+        int s1 = sig;
+        if (!only_on(zf[i], q)) {
+            s1 = sig == 3 ? 1 : 3;
+            apply(mover(single(q, s1), zf[i]), false);
+        }
+        if (!only_on(xf[i], q)) {
+            const int s2 = 6 - s1 - letter_at(xf[i], q);
+            apply(mover(single(q, s2), xf[i]), false);
+        }
+        placed[i] = 1;
+        pos[i] = q;
+    }
+    for (int i = 0; i < n; ++i) {
+        const int q = pos[i];
+        const int zl = letter_at(zf[i], q);
+        if (zl == 1) apply(single(q, 2), false);       // X -> -i Y X = -Z
+        else if (zl == 2) apply(single(q, 1), false);  // Y -> -i X Y = Z
+        if (letter_at(xf[i], q) == 2) apply(single(q, 3), false);  // Y -> -i Z Y = -X
+        if (zf[i].e == 2) apply(single(q, 1), true);   // -Z -> X (-Z) X = Z
+        if (xf[i].e == 2) apply(single(q, 3), true);   // -X -> Z (-X) Z = X
+    }
+    for (int i = 0; i < n; ++i) {
+        const int q = pos[i];
+        if (q == i) continue;
+        const uint64_t m = (1ull << q) | (1ull << i);
+        Pauli xx, yy, zz;
+        xx.x = m;
+        yy.x = m;
+        yy.z = m;
+        zz.z = m;
+        apply(xx, false);
+        apply(yy, false);
+        apply(zz, false);
+        for (int k = 0; k < n; ++k)
+            if (pos[k] == i) {
+                pos[k] = q;
+                break;
+            }
+        pos[i] = i;
+    }
+    for (int i = 0; i < n; ++i)
+        if (zf[i].x || zf[i].z != (1ull << i) || zf[i].e || xf[i].x != (1ull << i) || xf[i].z || xf[i].e)
+            return set_error(CFH_E_INVAL, "cfh_frame_flush: the frame did not reduce to the identity");
+    for (const Pauli &Q : rot)
+        if (Q.e & 1) return set_error(CFH_E_INVAL, "cfh_frame_flush: a flush rotation is not Hermitian");
+    return CFH_OK;
+}
+
+void frame_reset(cfh_frame_s &f)
+{
+    for (int q = 0; q < f.n; ++q) {
+        f.zf[q] = Pauli{0, 1ull << q, 0};
+        f.xf[q] = Pauli{1ull << q, 0, 0};
+    }
 }
 
 } // namespace cfh
@@ -200,6 +328,23 @@ cfh_status cfh_frame_conjugate_many(cfh_frame f, const cfh_pauli *in, cfh_pauli 
         cfh_status s = cfh_frame_conjugate(f, &in[i], &t);
         if (s) return s;
         out[i] = t;
+    }
+    return CFH_OK;
+}
+
+cfh_status cfh_frame_flush_rotations(cfh_frame f, cfh_pauli *rot, double *theta, size_t cap, size_t *m)
+{
+    if (!f || !m) return set_error(CFH_E_INVAL, "cfh_frame_flush_rotations: null argument");
+    std::vector<Pauli> q;
+    std::vector<double> th;
+    cfh_status s = frame_flush_rotations(*f, q, th);
+    if (s) return s;
+    *m = q.size();
+    if (q.size() > cap) return set_error(CFH_E_RANGE, "cfh_frame_flush_rotations: more rotations than cap");
+    if (!q.empty() && (!rot || !theta)) return set_error(CFH_E_INVAL, "cfh_frame_flush_rotations: null output");
+    for (size_t i = 0; i < q.size(); ++i) {
+        rot[i] = cfh_pauli{q[i].x, q[i].z, q[i].e, 0};
+        theta[i] = th[i];
     }
     return CFH_OK;
 }

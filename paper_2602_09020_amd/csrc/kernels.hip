@@ -1346,4 +1346,35 @@ cfh_status cfh_frame_conjugate_device(cfh_frame f, const cfh_pauli *in_dev, cfh_
     return st ? st : st2;
 }
 
+cfh_status cfh_frame_flush(cfh_frame f, void *psi, int dtype, void *stream)
+{
+    if (!f || !psi) return set_error(CFH_E_INVAL, "cfh_frame_flush: null argument");
+    std::vector<Pauli> q;
+    std::vector<double> th;
+    cfh_status st = frame_flush_rotations(*f, q, th);
+    if (st) return st;
+    if (!q.empty()) {
+        std::vector<cfh_pauli> rot(q.size());
+        for (size_t i = 0; i < q.size(); ++i) rot[i] = cfh_pauli{q[i].x, q[i].z, q[i].e, 0};
+        cfh_plan p = nullptr;
+        st = cfh_plan_create(f->n, dtype, rot.data(), rot.size(), nullptr, &p);
+        if (st) return st;
+        double *d = nullptr;
+        hipStream_t s = (hipStream_t)stream;
+        if (hip_ok(hipMalloc(&d, th.size() * sizeof(double)), "cfh_frame_flush: hipMalloc", &st) &&
+            hip_ok(hipMemcpyAsync(d, th.data(), th.size() * sizeof(double), hipMemcpyHostToDevice, s),
+                   "cfh_frame_flush: copy", &st)) {
+            st = cfh_apply_plan(p, psi, d, 0, stream);
+            cfh_status st2 = CFH_OK;
+            hip_ok(hipStreamSynchronize(s), "cfh_frame_flush: sync", &st2);
+            if (!st) st = st2;
+        }
+        if (d) (void)hipFree(d);
+        cfh_plan_destroy(p);
+        if (st) return st;
+    }
+    frame_reset(*f);
+    return CFH_OK;
+}
+
 } // extern "C"

@@ -45,6 +45,14 @@ class Frame:
     def conjugate_device(self, paulis_dev: torch.Tensor, out_dev: torch.Tensor, m: int, stream=None) -> None:
         _c.cfh_frame_conjugate_device(self.h, paulis_dev, out_dev, m, stream)
 
+    def flush_rotations(self):
+        """(paulis, theta) whose rotations, applied in order, take Phi to U Phi."""
+        return _c.cfh_frame_flush_rotations(self.h, self.n)
+
+    def flush(self, psi: torch.Tensor, stream=None) -> None:
+        """psi <- U psi (up to a global phase) on the device; the frame becomes the identity."""
+        _c.cfh_frame_flush(self.h, psi, stream)
+
 
 class Plan:
     """Fused (or unfused) schedule of a rotation sequence on n qubits."""

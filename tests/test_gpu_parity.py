@@ -512,3 +512,31 @@ def test_xcd_coset_order_vs_oracle_and_index_order(dtype, n, tb, lb):
     ref_psi, _ = sim.simulate(w)
     assert abs(out[0][1].real - sim.energy(ref_psi, n, w.ham, w.coeff)) <= tol
     assert np.abs(out[0][2] - out[1][2]).max() <= (1e-11 if dtype == torch.complex128 else 2e-3) * max(1.0, scale)
+
+
+# ------------------------------------------------------------- frame flush
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n,n_prefix", [(6, 20), (12, 120), (17, 300), (24, 500)])
+def test_frame_flush_gives_the_physical_state(dtype, n, n_prefix):
+    """After the rotations, flushing the frame into Phi on the device gives the
+    oracle's physical state (gates and rotations applied directly) up to one
+    global phase; the frame is then the identity and <H> is unchanged."""
+    w = W.make_workload("flush", n, seed=n, n_prefix=n_prefix, n_rot=80, n_ham=30)
+    frame, rot, terms, plan, ham = hybrid.prepare(w, dtype)
+    psi = hybrid.new_state(n, dtype, index=w.init)
+    plan.apply(psi, torch.tensor(w.theta, device=DEV))
+    e_before = ham.expval(psi)
+    frame.flush(psi)
+    phys, _ = sim.simulate(w)
+    got = psi.cpu().to(torch.complex128).numpy()
+    k = int(np.argmax(np.abs(phys)))
+    ph = got[k] / phys[k]
+    tol = TOL[dtype] * (10 if dtype == torch.complex128 else 1)
+    assert abs(abs(ph) - 1) <= tol
+    assert np.abs(got - ph * phys).max() <= tol
+    for q in range(n):
+        assert frame.row(q) == ((0, 1 << q, 0), (1 << q, 0, 0))
+    # the identity frame: terms are their own images, and <H> is the same
+    h_id = hybrid.Hamiltonian(n, dtype, cfh.cfh_pauli_encode(w.ham), w.coeff)
+    assert abs(h_id.expval(psi) - e_before) <= (1e-11 if dtype == torch.complex128 else 1e-4) * np.abs(w.coeff).sum()
