@@ -279,6 +279,36 @@ def main():
                         "passes": f_passes, "ms": f_ms}
         del ff
 
+        # random k-local Hamiltonians (Sec. 5.2): 24 qubits, 100 terms, locality
+        # 4..24, one Trotter step compiled to CNOT staircases and dispatched
+        # through the frame (the gate-level comparison is in cpu_baseline)
+        kl = {"qubits": 24, "terms": 100, "localities": []}
+        psi24 = torch.empty(1 << 24, dtype=dtype, device=dev)
+        for L in (4, 8, 12, 16, 20, 24):
+            g, a_, letters_k, coeff_k = W.klocal_trotter_circuit(24, L, 100, seed=L)
+            fk = hybrid.Frame(24)
+            cfh.cfh_state_set_basis(psi24, 24, 0)
+            torch.cuda.synchronize()
+            t0k = time.perf_counter()
+            fk.run_circuit(g, a_, psi24, stream=stream)
+            run_ms = (time.perf_counter() - t0k) * 1e3
+            fk2 = hybrid.Frame(24)
+            rk, tk = fk2.translate(g, a_)
+            pk = hybrid.Plan(24, dtype, rk)
+            thk = torch.tensor(tk, device=dev)
+            pk.apply(psi24, thk)
+            ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ea.record(stream)
+            pk.apply(psi24, thk)
+            eb.record(stream)
+            torch.cuda.synchronize()
+            kl["localities"].append({"L": L, "gate_rows": int(g.shape[0]), "passes": pk.info()["n_passes"],
+                                     "dispatch_ms": run_ms, "device_ms": ea.elapsed_time(eb)})
+            del pk, fk, fk2
+        out["klocal"] = kl
+        del psi24
+        torch.cuda.empty_cache()
+
         # complex64 storage, full workload, error against the complex128 result
         cfh.cfh_state_set_basis(psi, n, w.init)
         plan.apply(psi, theta)
@@ -388,6 +418,17 @@ def main():
                                "kind": "oracle",
                                "sample": f"first {kc} rotations of the {n}-qubit workload, dense complex128, "
                                          f"gate-by-gate CNOT-ladder decomposition ({cpu_s:.1f} s)"}
+        # the same oracle as a gate-level simulator of the k-local circuits (the
+        # klocal leg's workloads): the rows of their first 4 terms, per term
+        kgl = []
+        for L in (4, 8, 12, 16, 20, 24):
+            g, a_, _, _ = W.klocal_trotter_circuit(24, L, 100, seed=L)
+            cut = int(round(4 * g.shape[0] / 100))
+            v24 = sim.basis_state(24, 0)
+            t0 = time.perf_counter()
+            sim.apply_circuit(v24, 24, g[:cut], a_[:cut])
+            kgl.append({"L": L, "s_per_term": (time.perf_counter() - t0) / 4})
+        out["cpu_baseline"]["klocal_gate_by_gate"] = kgl
     print(json.dumps(out), flush=True)
 
 

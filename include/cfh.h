@@ -60,10 +60,13 @@ enum {
 typedef enum { CFH_C64 = 0, CFH_C128 = 1 } cfh_dtype;
 
 /* Clifford gate codes (Sec. 2.1 generators H, S, CNOT, plus their common
- * products).  CNOT takes q0 = control, q1 = target. */
+ * products).  CNOT takes q0 = control, q1 = target.  The one-qubit rotations
+ * RX, RY, RZ (exp(-i theta/2 sigma_q), angle given beside the gate) are only
+ * for circuits (cfh_circuit_translate / cfh_circuit_run). */
 typedef enum {
     CFH_GATE_H = 0, CFH_GATE_S = 1, CFH_GATE_SDG = 2, CFH_GATE_X = 3, CFH_GATE_Y = 4,
-    CFH_GATE_Z = 5, CFH_GATE_CNOT = 6, CFH_GATE_CZ = 7, CFH_GATE_SWAP = 8
+    CFH_GATE_Z = 5, CFH_GATE_CNOT = 6, CFH_GATE_CZ = 7, CFH_GATE_SWAP = 8,
+    CFH_GATE_RX = 9, CFH_GATE_RY = 10, CFH_GATE_RZ = 11
 } cfh_gate;
 
 /* P = i^e (x)_j sigma(x_j, z_j).  24 bytes, 8-byte aligned. */
@@ -293,6 +296,32 @@ cfh_status cfh_frame_flush_rotations(cfh_frame f, cfh_pauli *rot, double *theta,
  * for the device work); allocates and frees the plan and an angle buffer.
  * Errors: those of cfh_frame_flush_rotations and cfh_plan_create, CFH_E_HIP. */
 cfh_status cfh_frame_flush(cfh_frame f, void *psi, int dtype, void *stream);
+
+/* ------------------------------------------- gate-stream circuits */
+
+/* The hybrid dispatch of a compiled circuit (Sec. 4.3, Eq. single_to_multirot):
+ * m gate rows (code, q0, q1) of int32 in circuit order, angles[i] the angle
+ * of row i when it is RX/RY/RZ (angles may be NULL when there is none).
+ * Clifford rows update the frame (cfh_frame_apply_clifford); a rotation of
+ * sigma on qubit q becomes the rotation exp(-i theta/2 F(sigma_q)) on Phi,
+ * its axis read from the frame as it stands at that point.  The frame ends
+ * updated; rot/theta (host, cap entries) receive the rotations on Phi in
+ * order and *nrot their count.  Host only.  Errors: CFH_E_INVAL (null
+ * argument, bad code or qubit, q1 != -1 on a rotation), CFH_E_RANGE
+ * (more rotations than cap, *nrot set, the frame then holds the whole
+ * circuit's Cliffords). */
+cfh_status cfh_circuit_translate(cfh_frame f, const int32_t *gates, const double *angles, size_t m,
+                                 cfh_pauli *rot, double *theta, size_t cap, size_t *nrot);
+
+/* Translate the circuit as above and apply its rotations to psi (device,
+ * 2^n amplitudes of dtype, n the frame's) as one fused plan on `stream`:
+ * afterwards (frame, psi) is the circuit's output state in the hybrid
+ * representation; cfh_frame_flush turns it into physical amplitudes.
+ * tuning as for cfh_plan_create, may be NULL.  Synchronous; allocates and
+ * frees the plan and an angle buffer.  Errors: those of
+ * cfh_circuit_translate and cfh_plan_create, CFH_E_HIP. */
+cfh_status cfh_circuit_run(cfh_frame f, const int32_t *gates, const double *angles, size_t m, void *psi, int dtype,
+                           const cfh_tuning *tuning, void *stream);
 
 /* ----------------------------------------------- a10: batched circuits */
 

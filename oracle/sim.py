@@ -75,6 +75,20 @@ def apply_gates(psi: np.ndarray, n: int, gates: np.ndarray, inverse: bool = Fals
     _check(lib().orc_apply_gates(psi, n, g, g.shape[0], int(inverse)), "apply_gates")
 
 
+def apply_circuit(psi: np.ndarray, n: int, gates: np.ndarray, angles: np.ndarray) -> None:
+    """In place, gate by gate: Clifford rows as apply_gate, rows 9/10/11 as the
+    one-qubit rotations exp(-i theta/2 X_q / Y_q / Z_q) (the gate-level
+    simulation a circuit simulator performs, with no frame)."""
+    g = np.ascontiguousarray(gates, dtype=np.int32).reshape(-1, 3)
+    for (code, q0, q1), th in zip(g, np.asarray(angles, np.float64)):
+        if code in (9, 10, 11):
+            letters = np.zeros(n, np.uint8)
+            letters[q0] = {9: 1, 10: 2, 11: 3}[int(code)]
+            rotation(psi, n, letters, float(th))
+        else:
+            apply_gate(psi, n, int(code), int(q0), int(q1))
+
+
 def rotation(psi: np.ndarray, n: int, letters: np.ndarray, theta: float, sign: int = 1) -> None:
     """In place: psi <- exp(-i theta/2 * sign * P) psi via basis change, CNOT ladder, RZ."""
     l = np.ascontiguousarray(letters, dtype=np.uint8)

@@ -21,7 +21,7 @@ CFH_OK, CFH_E_INVAL, CFH_E_RANGE, CFH_E_NOT_HERMITIAN = 0, -1, -2, -3
 CFH_E_NOMEM, CFH_E_HIP, CFH_E_UNSUPPORTED = -4, -5, -6
 CFH_C64, CFH_C128 = 0, 1
 (CFH_GATE_H, CFH_GATE_S, CFH_GATE_SDG, CFH_GATE_X, CFH_GATE_Y, CFH_GATE_Z,
- CFH_GATE_CNOT, CFH_GATE_CZ, CFH_GATE_SWAP) = range(9)
+ CFH_GATE_CNOT, CFH_GATE_CZ, CFH_GATE_SWAP, CFH_GATE_RX, CFH_GATE_RY, CFH_GATE_RZ) = range(12)
 
 PAULI_DTYPE = np.dtype([("x", "<u8"), ("z", "<u8"), ("e", "<i4"), ("reserved", "<i4")])
 
@@ -69,6 +69,8 @@ _SIGS = {
     "cfh_frame_conjugate_device": (C.c_int32, [_vp, _vp, _vp, C.c_size_t, _vp]),
     "cfh_frame_flush_rotations": (C.c_int32, [_vp, _vp, _vp, C.c_size_t, _P(C.c_size_t)]),
     "cfh_frame_flush": (C.c_int32, [_vp, _vp, C.c_int, _vp]),
+    "cfh_circuit_translate": (C.c_int32, [_vp, _vp, _vp, C.c_size_t, _vp, _vp, C.c_size_t, _P(C.c_size_t)]),
+    "cfh_circuit_run": (C.c_int32, [_vp, _vp, _vp, C.c_size_t, _vp, C.c_int, _P(cfh_tuning), _vp]),
     "cfh_state_set_basis": (C.c_int32, [_vp, C.c_int, C.c_int, C.c_uint64, _vp]),
     "cfh_apply_pauli_rotation": (C.c_int32, [_vp, C.c_int, C.c_int, C.c_uint64, C.c_uint64, C.c_int,
                                              C.c_double, _vp]),
@@ -248,6 +250,33 @@ def cfh_frame_flush_rotations(f: int, n: int):
 
 def cfh_frame_flush(f: int, psi, stream=None) -> None:
     _call("cfh_frame_flush", f, _dev_ptr(psi, "psi"), _dtype_code(psi), _stream(stream))
+
+
+def _gate_rows(gates, angles):
+    g = np.ascontiguousarray(gates, dtype=np.int32).reshape(-1, 3)
+    a = None if angles is None else np.ascontiguousarray(angles, dtype=np.float64).reshape(-1)
+    if a is not None and a.shape[0] != g.shape[0]:
+        raise ValueError("one angle per gate row")
+    return g, a
+
+
+def cfh_circuit_translate(f: int, gates, angles=None):
+    """(paulis, theta) of the circuit's rotations on Phi; the frame absorbs its Cliffords."""
+    g, a = _gate_rows(gates, angles)
+    cap = max(1, int(np.isin(g[:, 0], (CFH_GATE_RX, CFH_GATE_RY, CFH_GATE_RZ)).sum()))
+    rot = np.zeros(cap, PAULI_DTYPE)
+    theta = np.zeros(cap, np.float64)
+    m = C.c_size_t()
+    _call("cfh_circuit_translate", f, g.ctypes.data, a.ctypes.data if a is not None else None, g.shape[0],
+          rot.ctypes.data, theta.ctypes.data, cap, C.byref(m))
+    return rot[:m.value].copy(), theta[:m.value].copy()
+
+
+def cfh_circuit_run(f: int, gates, angles, psi, tuning=None, stream=None) -> None:
+    g, a = _gate_rows(gates, angles)
+    t = _tuning(tuning)
+    _call("cfh_circuit_run", f, g.ctypes.data, a.ctypes.data if a is not None else None, g.shape[0],
+          _dev_ptr(psi, "psi"), _dtype_code(psi), C.byref(t) if t is not None else None, _stream(stream))
 
 
 # ------------------------------------------------------------------ state

@@ -148,6 +148,33 @@ cfh_status frame_flush_rotations(const cfh_frame_s &f, std::vector<Pauli> &rot, 
     return CFH_OK;
 }
 
+cfh_status circuit_translate(cfh_frame_s &f, const int32_t *gates, const double *angles, size_t m,
+                             std::vector<cfh_pauli> &rot, std::vector<double> &theta)
+{
+    rot.clear();
+    theta.clear();
+    for (size_t i = 0; i < m; ++i) {
+        const int code = gates[3 * i], q0 = gates[3 * i + 1], q1 = gates[3 * i + 2];
+        if (code == CFH_GATE_RX || code == CFH_GATE_RY || code == CFH_GATE_RZ) {
+            if (q0 < 0 || q0 >= f.n || q1 != -1)
+                return set_error(CFH_E_INVAL, "cfh_circuit_translate: a rotation needs q0 in range and q1 = -1");
+            if (!angles) return set_error(CFH_E_INVAL, "cfh_circuit_translate: rotation gate without angles");
+            // R_sigma(theta) U = U R_{F(sigma)}(theta), F(sigma) = U^dag sigma U
+            const uint64_t b = 1ull << q0;
+            const cfh_pauli s{code == CFH_GATE_RZ ? 0 : b, code == CFH_GATE_RX ? 0 : b, 0, 0};
+            cfh_pauli a{};
+            cfh_status st = cfh_frame_conjugate(&f, &s, &a);
+            if (st) return st;
+            rot.push_back(a);
+            theta.push_back(angles[i]);
+        } else {
+            cfh_status st = cfh_frame_apply_clifford(&f, code, q0, q1);
+            if (st) return st;
+        }
+    }
+    return CFH_OK;
+}
+
 void frame_reset(cfh_frame_s &f)
 {
     for (int q = 0; q < f.n; ++q) {
@@ -328,6 +355,24 @@ cfh_status cfh_frame_conjugate_many(cfh_frame f, const cfh_pauli *in, cfh_pauli 
         cfh_status s = cfh_frame_conjugate(f, &in[i], &t);
         if (s) return s;
         out[i] = t;
+    }
+    return CFH_OK;
+}
+
+cfh_status cfh_circuit_translate(cfh_frame f, const int32_t *gates, const double *angles, size_t m,
+                                 cfh_pauli *rot, double *theta, size_t cap, size_t *nrot)
+{
+    if (!f || !nrot || (m && !gates)) return set_error(CFH_E_INVAL, "cfh_circuit_translate: null argument");
+    std::vector<cfh_pauli> r;
+    std::vector<double> th;
+    cfh_status s = circuit_translate(*f, gates, angles, m, r, th);
+    if (s) return s;
+    *nrot = r.size();
+    if (r.size() > cap) return set_error(CFH_E_RANGE, "cfh_circuit_translate: more rotations than cap");
+    if (!r.empty() && (!rot || !theta)) return set_error(CFH_E_INVAL, "cfh_circuit_translate: null output");
+    for (size_t i = 0; i < r.size(); ++i) {
+        rot[i] = r[i];
+        theta[i] = th[i];
     }
     return CFH_OK;
 }

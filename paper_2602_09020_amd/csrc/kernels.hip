@@ -1346,6 +1346,37 @@ cfh_status cfh_frame_conjugate_device(cfh_frame f, const cfh_pauli *in_dev, cfh_
     return st ? st : st2;
 }
 
+} // extern "C"
+
+namespace {
+
+// Plan the rotations, apply them to psi on `stream` and wait (the angle buffer
+// and the plan are freed before returning).
+cfh_status run_rotations(int n, int dtype, const std::vector<cfh_pauli> &rot, const std::vector<double> &th,
+                         const cfh_tuning *tuning, void *psi, void *stream, const char *what)
+{
+    if (rot.empty()) return CFH_OK;
+    cfh_plan p = nullptr;
+    cfh_status st = cfh_plan_create(n, dtype, rot.data(), rot.size(), tuning, &p);
+    if (st) return st;
+    double *d = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    if (hip_ok(hipMalloc(&d, th.size() * sizeof(double)), what, &st) &&
+        hip_ok(hipMemcpyAsync(d, th.data(), th.size() * sizeof(double), hipMemcpyHostToDevice, s), what, &st)) {
+        st = cfh_apply_plan(p, psi, d, 0, stream);
+        cfh_status st2 = CFH_OK;
+        hip_ok(hipStreamSynchronize(s), what, &st2);
+        if (!st) st = st2;
+    }
+    if (d) (void)hipFree(d);
+    cfh_plan_destroy(p);
+    return st;
+}
+
+} // namespace
+
+extern "C" {
+
 cfh_status cfh_frame_flush(cfh_frame f, void *psi, int dtype, void *stream)
 {
     if (!f || !psi) return set_error(CFH_E_INVAL, "cfh_frame_flush: null argument");
@@ -1353,28 +1384,23 @@ cfh_status cfh_frame_flush(cfh_frame f, void *psi, int dtype, void *stream)
     std::vector<double> th;
     cfh_status st = frame_flush_rotations(*f, q, th);
     if (st) return st;
-    if (!q.empty()) {
-        std::vector<cfh_pauli> rot(q.size());
-        for (size_t i = 0; i < q.size(); ++i) rot[i] = cfh_pauli{q[i].x, q[i].z, q[i].e, 0};
-        cfh_plan p = nullptr;
-        st = cfh_plan_create(f->n, dtype, rot.data(), rot.size(), nullptr, &p);
-        if (st) return st;
-        double *d = nullptr;
-        hipStream_t s = (hipStream_t)stream;
-        if (hip_ok(hipMalloc(&d, th.size() * sizeof(double)), "cfh_frame_flush: hipMalloc", &st) &&
-            hip_ok(hipMemcpyAsync(d, th.data(), th.size() * sizeof(double), hipMemcpyHostToDevice, s),
-                   "cfh_frame_flush: copy", &st)) {
-            st = cfh_apply_plan(p, psi, d, 0, stream);
-            cfh_status st2 = CFH_OK;
-            hip_ok(hipStreamSynchronize(s), "cfh_frame_flush: sync", &st2);
-            if (!st) st = st2;
-        }
-        if (d) (void)hipFree(d);
-        cfh_plan_destroy(p);
-        if (st) return st;
-    }
+    std::vector<cfh_pauli> rot(q.size());
+    for (size_t i = 0; i < q.size(); ++i) rot[i] = cfh_pauli{q[i].x, q[i].z, q[i].e, 0};
+    st = run_rotations(f->n, dtype, rot, th, nullptr, psi, stream, "cfh_frame_flush");
+    if (st) return st;
     frame_reset(*f);
     return CFH_OK;
+}
+
+cfh_status cfh_circuit_run(cfh_frame f, const int32_t *gates, const double *angles, size_t m, void *psi, int dtype,
+                           const cfh_tuning *tuning, void *stream)
+{
+    if (!f || !psi || (m && !gates)) return set_error(CFH_E_INVAL, "cfh_circuit_run: null argument");
+    std::vector<cfh_pauli> rot;
+    std::vector<double> th;
+    cfh_status st = circuit_translate(*f, gates, angles, m, rot, th);
+    if (st) return st;
+    return run_rotations(f->n, dtype, rot, th, tuning, psi, stream, "cfh_circuit_run");
 }
 
 } // extern "C"

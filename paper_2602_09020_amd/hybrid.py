@@ -49,6 +49,15 @@ class Frame:
         """(paulis, theta) whose rotations, applied in order, take Phi to U Phi."""
         return _c.cfh_frame_flush_rotations(self.h, self.n)
 
+    def translate(self, gates: np.ndarray, angles: Optional[np.ndarray] = None):
+        """Absorb the circuit's Cliffords; return its rotations on Phi (paulis, theta)."""
+        return _c.cfh_circuit_translate(self.h, gates, angles)
+
+    def run_circuit(self, gates: np.ndarray, angles: Optional[np.ndarray], psi: torch.Tensor,
+                    tuning: Optional[dict] = None, stream=None) -> None:
+        """Cliffords into the frame, rotations onto psi as one fused plan (synchronous)."""
+        _c.cfh_circuit_run(self.h, gates, angles, psi, tuning, stream)
+
     def flush(self, psi: torch.Tensor, stream=None) -> None:
         """psi <- U psi (up to a global phase) on the device; the frame becomes the identity."""
         _c.cfh_frame_flush(self.h, psi, stream)

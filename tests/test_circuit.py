@@ -1,0 +1,106 @@
+"""Gate-stream circuits (Sec. 4.3, Eq. single_to_multirot; Sec. 5.1-5.2):
+the staircase compilation of the k-local workload and the host translation of
+a circuit into frame updates plus rotations on Phi, both pinned against dense
+unitaries built by the oracle (scipy matrix exponentials).  No GPU."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import dense, sim
+from paper_2602_09020_amd import cfh, hybrid
+
+
+def dense_circuit(gates, angles, n):
+    """Product of the rows' dense matrices, first row first."""
+    U = np.eye(1 << n, dtype=complex)
+    for (code, q0, q1), th in zip(np.asarray(gates).reshape(-1, 3), angles):
+        if code in (9, 10, 11):
+            letters = np.zeros(n, np.uint8)
+            letters[q0] = {9: 1, 10: 2, 11: 3}[int(code)]
+            G = dense.rotation(letters, th)
+        else:
+            G = dense.gate(int(code), int(q0), int(q1), n)
+        U = G @ U
+    return U
+
+
+def letters_of(p, n):
+    x, z = int(p["x"]), int(p["z"])
+    return np.array([2 if (x >> j) & 1 and (z >> j) & 1 else 1 if (x >> j) & 1 else 3 if (z >> j) & 1 else 0
+                     for j in range(n)], np.uint8)
+
+
+@pytest.mark.parametrize("n", [3, 5])
+def test_staircase_compilation_equals_the_pauli_rotation(n):
+    rng = np.random.default_rng(n)
+    for k in range(1, n + 1):
+        letters = W.random_klocal_strings(rng, n, k, 3)
+        theta = rng.uniform(-np.pi, np.pi, size=3)
+        g, a = W.staircase_circuit(letters, theta)
+        ref = np.eye(1 << n, dtype=complex)
+        for row, th in zip(letters, theta):
+            ref = dense.rotation(row, th) @ ref
+        assert np.abs(dense_circuit(g, a, n) - ref).max() <= 1e-12, k
+
+
+def test_oracle_circuit_simulation_matches_its_rotations():
+    """The oracle's gate-by-gate run of a compiled 10-qubit Trotter step equals
+    its direct Pauli rotations (two independent code paths of the oracle)."""
+    n = 10
+    g, a, letters, coeff = W.klocal_trotter_circuit(n, 6, 12, seed=3)
+    psi = sim.basis_state(n, 5)
+    sim.apply_circuit(psi, n, g, a)
+    ref = sim.basis_state(n, 5)
+    sim.rotations(ref, n, letters, 2.0 * coeff)
+    assert np.abs(psi - ref).max() <= 1e-12
+
+
+def random_circuit(n, count, rng):
+    gates, angles = [], []
+    for _ in range(count):
+        r = rng.random()
+        if r < 0.3:
+            gates.append((int(rng.integers(9, 12)), int(rng.integers(0, n)), -1))
+            angles.append(float(rng.uniform(-np.pi, np.pi)))
+        elif r < 0.6 and n >= 2:
+            a, b = rng.choice(n, size=2, replace=False)
+            gates.append((int(rng.integers(6, 9)), int(a), int(b)))
+            angles.append(0.0)
+        else:
+            gates.append((int(rng.integers(0, 6)), int(rng.integers(0, n)), -1))
+            angles.append(0.0)
+    return np.array(gates, np.int32), np.array(angles)
+
+
+@pytest.mark.parametrize("n", [1, 2, 4])
+def test_translate_is_exact_frame_times_rotations(n):
+    """Circuit = U_F R_m...R_1 exactly (no global phase): U_F the product of the
+    circuit's Clifford rows alone, R_k the returned rotations on Phi."""
+    rng = np.random.default_rng(20 + n)
+    for trial in range(6):
+        g, a = random_circuit(n, 8 * n + 4, rng)
+        f = hybrid.Frame(n)
+        rot, theta = f.translate(g, a)
+        assert rot.shape[0] == int(np.isin(g[:, 0], (9, 10, 11)).sum())
+        R = np.eye(1 << n, dtype=complex)
+        for p, th in zip(rot, theta):
+            R = dense.rotation(letters_of(p, n), th, int(p["e"])) @ R
+        cl = g[~np.isin(g[:, 0], (9, 10, 11))]
+        UF = dense.circuit_unitary(cl, n)
+        assert np.abs(dense_circuit(g, a, n) - UF @ R).max() <= 1e-12, trial
+        # the frame holds exactly the Clifford part
+        f2 = hybrid.Frame(n)
+        f2.apply_gates(cl)
+        assert [f.row(q) for q in range(n)] == [f2.row(q) for q in range(n)]
+
+
+def test_translate_rejects_bad_rows():
+    f = hybrid.Frame(3)
+    for g, a in [(np.array([[11, 0, 1]], np.int32), np.zeros(1)), (np.array([[11, 3, -1]], np.int32), np.zeros(1)),
+                 (np.array([[12, 0, -1]], np.int32), np.zeros(1))]:
+        with pytest.raises(cfh.CfhError) as e:
+            f.translate(g, a)
+        assert e.value.code == cfh.CFH_E_INVAL
+    with pytest.raises(cfh.CfhError):
+        cfh._call("cfh_circuit_translate", f.h, np.array([[11, 0, -1]], np.int32).ctypes.data, None, 1,
+                  None, None, 0, __import__("ctypes").byref(__import__("ctypes").c_size_t()))

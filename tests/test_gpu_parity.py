@@ -540,3 +540,31 @@ def test_frame_flush_gives_the_physical_state(dtype, n, n_prefix):
     # the identity frame: terms are their own images, and <H> is the same
     h_id = hybrid.Hamiltonian(n, dtype, cfh.cfh_pauli_encode(w.ham), w.coeff)
     assert abs(h_id.expval(psi) - e_before) <= (1e-11 if dtype == torch.complex128 else 1e-4) * np.abs(w.coeff).sum()
+
+
+# ------------------------------------------------------ gate-stream circuits
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n,k,terms,steps", [(10, 4, 20, 2), (14, 14, 30, 1), (16, 8, 50, 1), (18, 2, 40, 1)])
+def test_circuit_run_vs_oracle_gate_by_gate(dtype, n, k, terms, steps):
+    """A compiled k-local Trotter circuit (basis changes, CNOT staircases, RZ)
+    dispatched through the frame: <H> read from (frame, Phi) and the flushed
+    state against the oracle's gate-by-gate simulation of the same rows."""
+    g, a, letters, coeff = W.klocal_trotter_circuit(n, k, terms, seed=n + k, t=0.7, steps=steps)
+    init = (1 << (n // 2)) - 1
+    frame = hybrid.Frame(n)
+    psi = hybrid.new_state(n, dtype, index=init)
+    frame.run_circuit(g, a, psi)
+    phys = sim.basis_state(n, init)
+    sim.apply_circuit(phys, n, g, a)
+    scale = np.abs(coeff).sum()
+    tol = TOL[dtype] * (10 if dtype == torch.complex128 else 1)
+    # <H> in the hybrid representation (Eq. chfsexp) against the oracle's physical state
+    ham = hybrid.Hamiltonian(n, dtype, frame.conjugate(cfh.cfh_pauli_encode(letters)), coeff)
+    assert abs(ham.expval(psi).real - sim.energy(phys, n, letters, coeff)) <= tol * scale
+    frame.flush(psi)
+    got = psi.cpu().to(torch.complex128).numpy()
+    j = int(np.argmax(np.abs(phys)))
+    ph = got[j] / phys[j]
+    assert abs(abs(ph) - 1) <= tol
+    assert np.abs(got - ph * phys).max() <= tol

@@ -21,6 +21,7 @@ import numpy as np
 
 LETTER_I, LETTER_X, LETTER_Y, LETTER_Z = 0, 1, 2, 3
 GATE_H, GATE_S, GATE_SDG, GATE_X, GATE_Y, GATE_Z, GATE_CNOT, GATE_CZ, GATE_SWAP = range(9)
+GATE_RX, GATE_RY, GATE_RZ = 9, 10, 11  # exp(-i theta/2 sigma_q), the angle beside the gate row
 
 # The eight two-body letter patterns at (a, b, c, d) with an even number of Y.
 _TWO_BODY_PATTERNS = np.array(
@@ -113,6 +114,62 @@ def random_klocal_strings(rng: np.random.Generator, n: int, k: int, m: int) -> n
         seen.add(key)
         out.append(row)
     return np.stack(out)
+
+
+def klocal_hamiltonian(n: int, k: int, n_terms: int, seed: int = 0):
+    """Random k-local Hamiltonian of Sec. 5.2: ``n_terms`` distinct weight-k
+    strings and real coefficients drawn uniformly from [0, 1), normalized to
+    unit 2-norm.  Returns (letters, coeff)."""
+    rng = np.random.default_rng(seed)
+    letters = random_klocal_strings(rng, n, k, n_terms)
+    c = rng.uniform(0.0, 1.0, size=n_terms)
+    return letters, c / np.linalg.norm(c)
+
+
+def staircase_circuit(letters: np.ndarray, theta: np.ndarray):
+    """Gate rows for the rotations exp(-i theta_j/2 P_j), one after the other,
+    each compiled as in Sec. 5.1 (Fig. cnot_ladder): a one-qubit basis change
+    on every qubit of the support (H for X; S^dagger then H for Y), a CNOT
+    staircase that gathers the parity of the support on its last qubit, RZ
+    there, then the staircase and the basis changes undone.  Returns (gates,
+    angles) with one angle per gate row (0 for Clifford rows)."""
+    gates, angles = [], []
+    for row, th in zip(np.asarray(letters, np.uint8), np.asarray(theta, np.float64)):
+        supp = np.flatnonzero(row)
+        if supp.size == 0:
+            continue
+        for q in supp:
+            if row[q] == LETTER_X:
+                gates.append((GATE_H, q, -1))
+            elif row[q] == LETTER_Y:
+                gates.append((GATE_SDG, q, -1))
+                gates.append((GATE_H, q, -1))
+        for a, b in zip(supp[:-1], supp[1:]):
+            gates.append((GATE_CNOT, a, b))
+        gates.append((GATE_RZ, supp[-1], -1))
+        angles_here = len(gates) - 1
+        for a, b in reversed(list(zip(supp[:-1], supp[1:]))):
+            gates.append((GATE_CNOT, a, b))
+        for q in supp:
+            if row[q] == LETTER_X:
+                gates.append((GATE_H, q, -1))
+            elif row[q] == LETTER_Y:
+                gates.append((GATE_H, q, -1))
+                gates.append((GATE_S, q, -1))
+        angles.extend([0.0] * (len(gates) - len(angles)))
+        angles[angles_here] = float(th)
+    return np.array(gates, np.int32).reshape(-1, 3), np.array(angles, np.float64)
+
+
+def klocal_trotter_circuit(n: int, k: int, n_terms: int, seed: int = 0, t: float = 1.0, steps: int = 1):
+    """The first-order Trotter circuit (Eq. trotter) of a random k-local
+    Hamiltonian, compiled to H, S, S^dagger, CNOT and RZ rows: every step
+    applies exp(-i c_j t/steps P_j) for j in order, i.e. theta_j = 2 c_j t /
+    steps.  Returns (gates, angles, letters, coeff)."""
+    letters, coeff = klocal_hamiltonian(n, k, n_terms, seed)
+    th = 2.0 * coeff * t / steps
+    g, a = staircase_circuit(np.tile(letters, (steps, 1)), np.tile(th, steps))
+    return g, a, letters, coeff
 
 
 def clifford_prefix(rng: np.random.Generator, n: int, g: int) -> np.ndarray:
