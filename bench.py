@@ -279,6 +279,17 @@ def main():
                         "passes": f_passes, "ms": f_ms}
         del ff
 
+        # one multi-qubit Pauli measurement (<P>, then the collapse pass) on the 28-qubit state
+        mletters = np.zeros(n, np.uint8)
+        mletters[rng_f.choice(n, size=n // 2, replace=False)] = rng_f.integers(1, 4, size=n // 2)
+        mp = cfh.cfh_pauli_encode(mletters[None, :])[0]
+        torch.cuda.synchronize()
+        t0m = time.perf_counter()
+        m_out, m_pp = cfh.cfh_measure_pauli(psi, n, int(mp["x"]), int(mp["z"]), int(mp["e"]), 0.5, stream)
+        torch.cuda.synchronize()
+        out["measure"] = {"weight": int(n // 2), "ms": (time.perf_counter() - t0m) * 1e3, "outcome": m_out,
+                          "prob_plus": m_pp}
+
         # random k-local Hamiltonians (Sec. 5.2): 24 qubits, 100 terms, locality
         # 4..24, one Trotter step compiled to CNOT staircases and dispatched
         # through the frame (the gate-level comparison is in cpu_baseline)

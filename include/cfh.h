@@ -66,7 +66,9 @@ typedef enum { CFH_C64 = 0, CFH_C128 = 1 } cfh_dtype;
 typedef enum {
     CFH_GATE_H = 0, CFH_GATE_S = 1, CFH_GATE_SDG = 2, CFH_GATE_X = 3, CFH_GATE_Y = 4,
     CFH_GATE_Z = 5, CFH_GATE_CNOT = 6, CFH_GATE_CZ = 7, CFH_GATE_SWAP = 8,
-    CFH_GATE_RX = 9, CFH_GATE_RY = 10, CFH_GATE_RZ = 11
+    CFH_GATE_RX = 9, CFH_GATE_RY = 10, CFH_GATE_RZ = 11,
+    CFH_GATE_MEASURE = 12, /* measure Z_q0 (cfh_circuit_run only; uniform number beside the row) */
+    CFH_GATE_RESET = 13    /* prepare |0> on q0: measure Z_q0, then X_q0 on outcome -1 (same) */
 } cfh_gate;
 
 /* P = i^e (x)_j sigma(x_j, z_j).  24 bytes, 8-byte aligned. */
@@ -309,19 +311,38 @@ cfh_status cfh_frame_flush(cfh_frame f, void *psi, int dtype, void *stream);
  * order and *nrot their count.  Host only.  Errors: CFH_E_INVAL (null
  * argument, bad code or qubit, q1 != -1 on a rotation), CFH_E_RANGE
  * (more rotations than cap, *nrot set, the frame then holds the whole
- * circuit's Cliffords). */
+ * circuit's Cliffords), CFH_E_UNSUPPORTED (a measurement or reset row:
+ * those need the state, see cfh_circuit_run). */
 cfh_status cfh_circuit_translate(cfh_frame f, const int32_t *gates, const double *angles, size_t m,
                                  cfh_pauli *rot, double *theta, size_t cap, size_t *nrot);
 
-/* Translate the circuit as above and apply its rotations to psi (device,
- * 2^n amplitudes of dtype, n the frame's) as one fused plan on `stream`:
- * afterwards (frame, psi) is the circuit's output state in the hybrid
- * representation; cfh_frame_flush turns it into physical amplitudes.
- * tuning as for cfh_plan_create, may be NULL.  Synchronous; allocates and
- * frees the plan and an angle buffer.  Errors: those of
- * cfh_circuit_translate and cfh_plan_create, CFH_E_HIP. */
+/* Measure the Hermitian Pauli P on psi (device, 2^n amplitudes of dtype):
+ * P(+1) = (1 + <P>)/2, the outcome s is +1 when u < P(+1) (u in [0, 1), the
+ * caller's uniform random number) and -1 otherwise, and psi collapses to
+ * (psi + s P psi) / (2 sqrt(P(s))) in one pass of the pair kernel.  In the
+ * hybrid state, measuring sigma_q is measuring F(sigma_q) on Phi (the frame
+ * axis, Sec. 4.3 and the gate flow of App. B).  *outcome = s, *prob_plus =
+ * P(+1) (may be NULL).  Synchronous (the outcome is read on the host).
+ * Errors: CFH_E_INVAL (null, u outside [0, 1)), CFH_E_RANGE,
+ * CFH_E_NOT_HERMITIAN, CFH_E_UNSUPPORTED, CFH_E_HIP. */
+cfh_status cfh_measure_pauli(void *psi, int n, int dtype, const cfh_pauli *p, double u, int32_t *outcome,
+                             double *prob_plus, void *stream);
+
+/* Run the circuit on (frame, psi): psi device, 2^n amplitudes of dtype, n
+ * the frame's.  The rows between two measurement or reset rows are
+ * translated as above and their rotations applied as one fused plan on
+ * `stream`; a MEASURE row on q measures F(Z_q) on psi with angles[i] as its
+ * uniform number and writes the outcome (+1/-1) to outcomes[i]; a RESET row
+ * does the same and then applies F(X_q) when the outcome was -1.  Afterwards
+ * (frame, psi) is the circuit's output state in the hybrid representation
+ * (up to a global phase after resets); cfh_frame_flush turns it into
+ * physical amplitudes.  tuning as for cfh_plan_create, may be NULL;
+ * outcomes (host, m entries) may be NULL when there is no measurement or
+ * reset row.  Synchronous; allocates and frees each segment's plan and angle
+ * buffer.  Errors: those of cfh_circuit_translate, cfh_plan_create and
+ * cfh_measure_pauli, CFH_E_HIP. */
 cfh_status cfh_circuit_run(cfh_frame f, const int32_t *gates, const double *angles, size_t m, void *psi, int dtype,
-                           const cfh_tuning *tuning, void *stream);
+                           const cfh_tuning *tuning, int32_t *outcomes, void *stream);
 
 /* ----------------------------------------------- a10: batched circuits */
 

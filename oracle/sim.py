@@ -75,18 +75,51 @@ def apply_gates(psi: np.ndarray, n: int, gates: np.ndarray, inverse: bool = Fals
     _check(lib().orc_apply_gates(psi, n, g, g.shape[0], int(inverse)), "apply_gates")
 
 
-def apply_circuit(psi: np.ndarray, n: int, gates: np.ndarray, angles: np.ndarray) -> None:
+def measure_z(psi: np.ndarray, n: int, q: int, u: float) -> Tuple[int, float]:
+    """In place: measure Z_q with the uniform number u (outcome +1 when
+    u < P(+1)), then collapse and renormalize.  Returns (outcome, P(+1))."""
+    bit = (np.arange(1 << n, dtype=np.int64) >> q) & 1
+    p_plus = float(np.sum(np.abs(psi[bit == 0]) ** 2))
+    s = 1 if u < p_plus else -1
+    keep = bit == (0 if s > 0 else 1)
+    psi[~keep] = 0.0
+    psi /= np.sqrt(p_plus if s > 0 else 1.0 - p_plus)
+    return s, p_plus
+
+
+def measure_pauli(psi: np.ndarray, n: int, letters: np.ndarray, u: float, phase: int = 0) -> Tuple[int, float]:
+    """In place: measure the Hermitian i^phase P with the uniform number u:
+    P(+1) = (1 + <P>)/2, psi <- (psi + s P psi) / (2 sqrt(P(s)))."""
+    p_plus = min(1.0, max(0.0, 0.5 * (1.0 + expval(psi, n, letters, phase).real)))
+    s = 1 if u < p_plus else -1
+    ps = p_plus if s > 0 else 1.0 - p_plus
+    ppsi = apply_pauli_sum(psi, n, np.asarray(letters, np.uint8).reshape(1, n), np.array([1.0]),
+                           np.array([phase]))
+    psi[:] = (psi + s * ppsi) / (2.0 * np.sqrt(ps))
+    return s, p_plus
+
+
+def apply_circuit(psi: np.ndarray, n: int, gates: np.ndarray, angles: np.ndarray) -> np.ndarray:
     """In place, gate by gate: Clifford rows as apply_gate, rows 9/10/11 as the
-    one-qubit rotations exp(-i theta/2 X_q / Y_q / Z_q) (the gate-level
-    simulation a circuit simulator performs, with no frame)."""
+    one-qubit rotations exp(-i theta/2 X_q / Y_q / Z_q), row 12 a Z_q
+    measurement and row 13 a reset to |0> (measure, then X_q on -1), both with
+    the row's angle as their uniform number (the gate-level simulation a
+    circuit simulator performs, with no frame).  Returns the outcomes (+1/-1
+    at measurement and reset rows, else 0)."""
     g = np.ascontiguousarray(gates, dtype=np.int32).reshape(-1, 3)
-    for (code, q0, q1), th in zip(g, np.asarray(angles, np.float64)):
+    out = np.zeros(g.shape[0], np.int32)
+    for i, ((code, q0, q1), th) in enumerate(zip(g, np.asarray(angles, np.float64))):
         if code in (9, 10, 11):
             letters = np.zeros(n, np.uint8)
             letters[q0] = {9: 1, 10: 2, 11: 3}[int(code)]
             rotation(psi, n, letters, float(th))
+        elif code in (12, 13):
+            out[i], _ = measure_z(psi, n, int(q0), float(th))
+            if code == 13 and out[i] < 0:
+                apply_gate(psi, n, 3, int(q0), -1)
         else:
             apply_gate(psi, n, int(code), int(q0), int(q1))
+    return out
 
 
 def rotation(psi: np.ndarray, n: int, letters: np.ndarray, theta: float, sign: int = 1) -> None:

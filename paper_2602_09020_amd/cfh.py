@@ -21,7 +21,8 @@ CFH_OK, CFH_E_INVAL, CFH_E_RANGE, CFH_E_NOT_HERMITIAN = 0, -1, -2, -3
 CFH_E_NOMEM, CFH_E_HIP, CFH_E_UNSUPPORTED = -4, -5, -6
 CFH_C64, CFH_C128 = 0, 1
 (CFH_GATE_H, CFH_GATE_S, CFH_GATE_SDG, CFH_GATE_X, CFH_GATE_Y, CFH_GATE_Z,
- CFH_GATE_CNOT, CFH_GATE_CZ, CFH_GATE_SWAP, CFH_GATE_RX, CFH_GATE_RY, CFH_GATE_RZ) = range(12)
+ CFH_GATE_CNOT, CFH_GATE_CZ, CFH_GATE_SWAP, CFH_GATE_RX, CFH_GATE_RY, CFH_GATE_RZ,
+ CFH_GATE_MEASURE, CFH_GATE_RESET) = range(14)
 
 PAULI_DTYPE = np.dtype([("x", "<u8"), ("z", "<u8"), ("e", "<i4"), ("reserved", "<i4")])
 
@@ -70,7 +71,9 @@ _SIGS = {
     "cfh_frame_flush_rotations": (C.c_int32, [_vp, _vp, _vp, C.c_size_t, _P(C.c_size_t)]),
     "cfh_frame_flush": (C.c_int32, [_vp, _vp, C.c_int, _vp]),
     "cfh_circuit_translate": (C.c_int32, [_vp, _vp, _vp, C.c_size_t, _vp, _vp, C.c_size_t, _P(C.c_size_t)]),
-    "cfh_circuit_run": (C.c_int32, [_vp, _vp, _vp, C.c_size_t, _vp, C.c_int, _P(cfh_tuning), _vp]),
+    "cfh_circuit_run": (C.c_int32, [_vp, _vp, _vp, C.c_size_t, _vp, C.c_int, _P(cfh_tuning), _vp, _vp]),
+    "cfh_measure_pauli": (C.c_int32, [_vp, C.c_int, C.c_int, _P(cfh_pauli), C.c_double, _P(C.c_int32),
+                                      _P(C.c_double), _vp]),
     "cfh_state_set_basis": (C.c_int32, [_vp, C.c_int, C.c_int, C.c_uint64, _vp]),
     "cfh_apply_pauli_rotation": (C.c_int32, [_vp, C.c_int, C.c_int, C.c_uint64, C.c_uint64, C.c_int,
                                              C.c_double, _vp]),
@@ -272,11 +275,24 @@ def cfh_circuit_translate(f: int, gates, angles=None):
     return rot[:m.value].copy(), theta[:m.value].copy()
 
 
-def cfh_circuit_run(f: int, gates, angles, psi, tuning=None, stream=None) -> None:
+def cfh_circuit_run(f: int, gates, angles, psi, tuning=None, stream=None) -> np.ndarray:
+    """Runs the circuit; returns the outcomes array (+1/-1 at measurement and reset rows, else 0)."""
     g, a = _gate_rows(gates, angles)
     t = _tuning(tuning)
+    out = np.zeros(max(1, g.shape[0]), np.int32)
     _call("cfh_circuit_run", f, g.ctypes.data, a.ctypes.data if a is not None else None, g.shape[0],
-          _dev_ptr(psi, "psi"), _dtype_code(psi), C.byref(t) if t is not None else None, _stream(stream))
+          _dev_ptr(psi, "psi"), _dtype_code(psi), C.byref(t) if t is not None else None, out.ctypes.data,
+          _stream(stream))
+    return out[:g.shape[0]]
+
+
+def cfh_measure_pauli(psi, n: int, x: int, z: int, e: int, u: float, stream=None):
+    """(outcome, P(+1)) of measuring the Pauli (x, z, e) on psi, which collapses in place."""
+    p = cfh_pauli(x, z, e, 0)
+    o, pp = C.c_int32(), C.c_double()
+    _call("cfh_measure_pauli", _dev_ptr(psi, "psi"), n, _dtype_code(psi), C.byref(p), float(u), C.byref(o),
+          C.byref(pp), _stream(stream))
+    return int(o.value), float(pp.value)
 
 
 # ------------------------------------------------------------------ state

@@ -212,10 +212,11 @@ namespace cfh {
 // Rotations (angles pi/2 or pi) whose product applied to Phi, in order, gives
 // U Phi up to a global phase; the frame is not changed.
 cfh_status frame_flush_rotations(const cfh_frame_s &f, std::vector<Pauli> &rot, std::vector<double> &theta);
-// Gate rows in circuit order: Clifford rows update the frame, RX/RY/RZ rows
-// become rotations about the frame image of their one-qubit Pauli.
-cfh_status circuit_translate(cfh_frame_s &f, const int32_t *gates, const double *angles, size_t m,
-                             std::vector<cfh_pauli> &rot, std::vector<double> &theta);
+// Gate rows begin.. in circuit order: Clifford rows update the frame, RX/RY/RZ
+// rows become rotations about the frame image of their one-qubit Pauli; stops
+// at the first measurement or reset row (*stop = its index, else m).
+cfh_status circuit_translate(cfh_frame_s &f, const int32_t *gates, const double *angles, size_t begin, size_t m,
+                             std::vector<cfh_pauli> &rot, std::vector<double> &theta, size_t *stop);
 // Rows back to the identity frame (effZ_q = Z_q, effX_q = X_q).
 void frame_reset(cfh_frame_s &f);
 } // namespace cfh

@@ -148,13 +148,18 @@ cfh_status frame_flush_rotations(const cfh_frame_s &f, std::vector<Pauli> &rot, 
     return CFH_OK;
 }
 
-cfh_status circuit_translate(cfh_frame_s &f, const int32_t *gates, const double *angles, size_t m,
-                             std::vector<cfh_pauli> &rot, std::vector<double> &theta)
+cfh_status circuit_translate(cfh_frame_s &f, const int32_t *gates, const double *angles, size_t begin, size_t m,
+                             std::vector<cfh_pauli> &rot, std::vector<double> &theta, size_t *stop)
 {
     rot.clear();
     theta.clear();
-    for (size_t i = 0; i < m; ++i) {
+    *stop = m;
+    for (size_t i = begin; i < m; ++i) {
         const int code = gates[3 * i], q0 = gates[3 * i + 1], q1 = gates[3 * i + 2];
+        if (code == CFH_GATE_MEASURE || code == CFH_GATE_RESET) {
+            *stop = i;
+            return CFH_OK;
+        }
         if (code == CFH_GATE_RX || code == CFH_GATE_RY || code == CFH_GATE_RZ) {
             if (q0 < 0 || q0 >= f.n || q1 != -1)
                 return set_error(CFH_E_INVAL, "cfh_circuit_translate: a rotation needs q0 in range and q1 = -1");
@@ -365,8 +370,12 @@ cfh_status cfh_circuit_translate(cfh_frame f, const int32_t *gates, const double
     if (!f || !nrot || (m && !gates)) return set_error(CFH_E_INVAL, "cfh_circuit_translate: null argument");
     std::vector<cfh_pauli> r;
     std::vector<double> th;
-    cfh_status s = circuit_translate(*f, gates, angles, m, r, th);
+    size_t stop = 0;
+    cfh_status s = circuit_translate(*f, gates, angles, 0, m, r, th, &stop);
     if (s) return s;
+    if (stop < m)
+        return set_error(CFH_E_UNSUPPORTED,
+                         "cfh_circuit_translate: measurement and reset rows need the state (cfh_circuit_run)");
     *nrot = r.size();
     if (r.size() > cap) return set_error(CFH_E_RANGE, "cfh_circuit_translate: more rotations than cap");
     if (!r.empty() && (!rot || !theta)) return set_error(CFH_E_INVAL, "cfh_circuit_translate: null output");

@@ -682,11 +682,15 @@ cfh_status check_state_args(const void *psi, int n, int dtype, const char *what)
     return CFH_OK;
 }
 
+// psi_y <- c psi_y + s omega (-1)^{|y&z|} psi_{y^x} with omega = i^w,
+// w = (e - |x&z| + wadd) mod 4: wadd = 3 is the rotation exp(-i theta/2 P)
+// (omega = -i i^{e-|x&z|}, c = cos, s = sin of theta/2); wadd = 0 gives
+// c psi + s P psi, the projector (1 + s P)/2 for c = s = 1/2.
 template <typename Amp>
 cfh_status rot_one(Amp *psi, int n, uint64_t x, uint64_t z, int e, double c, double s,
-                   const double2 *coef, int k, double ssign, hipStream_t st)
+                   const double2 *coef, int k, double ssign, hipStream_t st, int wadd = 3)
 {
-    const int w = (e - popc(x & z) + 3) & 3;
+    const int w = (e - popc(x & z) + wadd) & 3;
     const uint64_t per = (uint64_t)kR1Threads * kR1Pairs;
     if (x == 0) {
         const uint64_t N = 1ull << n;
@@ -819,6 +823,34 @@ cfh_status cfh_apply_pauli_rotation(void *psi, int n, int dtype, uint64_t x, uin
     if (dtype == CFH_C128)
         return rot_one((double2 *)psi, n, x, z, e, c, s, nullptr, 0, 1.0, (hipStream_t)stream);
     return rot_one((float2 *)psi, n, x, z, e, c, s, nullptr, 0, 1.0, (hipStream_t)stream);
+}
+
+cfh_status cfh_measure_pauli(void *psi, int n, int dtype, const cfh_pauli *p, double u, int32_t *outcome,
+                             double *prob_plus, void *stream)
+{
+    cfh_status st = check_state_args(psi, n, dtype, "cfh_measure_pauli");
+    if (st) return st;
+    if (!p || !outcome) return set_error(CFH_E_INVAL, "cfh_measure_pauli: null argument");
+    st = check_pauli(*p, n, true, "cfh_measure_pauli");
+    if (st) return st;
+    if (!(u >= 0.0 && u < 1.0)) return set_error(CFH_E_INVAL, "cfh_measure_pauli: u must be in [0, 1)");
+    // P(+1) = (1 + <P>)/2; the outcome s is +1 when u < P(+1)
+    const double one = 1.0;
+    double ev[2] = {0.0, 0.0};
+    st = cfh_expval(psi, n, dtype, p, &one, 1, ev, stream);
+    if (st) return st;
+    const double pp = std::min(1.0, std::max(0.0, 0.5 * (1.0 + ev[0])));
+    const int sgn = u < pp ? 1 : -1;
+    const double ps = sgn > 0 ? pp : 1.0 - pp;
+    // collapse: psi <- (psi + s P psi) / (2 sqrt(P(s)))
+    const double a = 0.5 / std::sqrt(ps);
+    st = dtype == CFH_C128
+             ? rot_one((double2 *)psi, n, p->x, p->z, p->e, a, sgn * a, nullptr, 0, 1.0, (hipStream_t)stream, 0)
+             : rot_one((float2 *)psi, n, p->x, p->z, p->e, a, sgn * a, nullptr, 0, 1.0, (hipStream_t)stream, 0);
+    if (st) return st;
+    *outcome = sgn;
+    if (prob_plus) *prob_plus = pp;
+    return CFH_OK;
 }
 
 cfh_status cfh_plan_create(int n, int dtype, const cfh_pauli *rot, size_t m, const cfh_tuning *tuning,
@@ -1393,14 +1425,42 @@ cfh_status cfh_frame_flush(cfh_frame f, void *psi, int dtype, void *stream)
 }
 
 cfh_status cfh_circuit_run(cfh_frame f, const int32_t *gates, const double *angles, size_t m, void *psi, int dtype,
-                           const cfh_tuning *tuning, void *stream)
+                           const cfh_tuning *tuning, int32_t *outcomes, void *stream)
 {
     if (!f || !psi || (m && !gates)) return set_error(CFH_E_INVAL, "cfh_circuit_run: null argument");
     std::vector<cfh_pauli> rot;
     std::vector<double> th;
-    cfh_status st = circuit_translate(*f, gates, angles, m, rot, th);
-    if (st) return st;
-    return run_rotations(f->n, dtype, rot, th, tuning, psi, stream, "cfh_circuit_run");
+    size_t i = 0;
+    while (true) {
+        // the rows up to the next measurement or reset: frame updates and rotations
+        size_t stop = 0;
+        cfh_status st = circuit_translate(*f, gates, angles, i, m, rot, th, &stop);
+        if (st) return st;
+        st = run_rotations(f->n, dtype, rot, th, tuning, psi, stream, "cfh_circuit_run");
+        if (st) return st;
+        if (stop >= m) return CFH_OK;
+        const int code = gates[3 * stop], q = gates[3 * stop + 1];
+        if (q < 0 || q >= f->n || gates[3 * stop + 2] != -1 || !angles || !outcomes)
+            return set_error(CFH_E_INVAL, "cfh_circuit_run: a measurement or reset needs q0 in range, q1 = -1, "
+                                          "its uniform number in angles and an outcomes array");
+        // measuring Z_q on U Phi is measuring F(Z_q) on Phi (the frame axis)
+        cfh_pauli zq{0, 1ull << q, 0, 0}, pz{}, px{};
+        st = cfh_frame_conjugate(f, &zq, &pz);
+        if (st) return st;
+        int32_t out = 0;
+        st = cfh_measure_pauli(psi, f->n, dtype, &pz, angles[stop], &out, nullptr, stream);
+        if (st) return st;
+        outcomes[stop] = out;
+        if (code == CFH_GATE_RESET && out < 0) {
+            // X_q on U Phi is F(X_q) on Phi; exp(-i pi/2 Q) = -i Q applies it up to a global phase
+            cfh_pauli xq{1ull << q, 0, 0, 0};
+            st = cfh_frame_conjugate(f, &xq, &px);
+            if (st) return st;
+            st = cfh_apply_pauli_rotation(psi, f->n, dtype, px.x, px.z, px.e, 3.14159265358979323846, stream);
+            if (st) return st;
+        }
+        i = stop + 1;
+    }
 }
 
 } // extern "C"

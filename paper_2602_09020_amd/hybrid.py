@@ -54,9 +54,10 @@ class Frame:
         return _c.cfh_circuit_translate(self.h, gates, angles)
 
     def run_circuit(self, gates: np.ndarray, angles: Optional[np.ndarray], psi: torch.Tensor,
-                    tuning: Optional[dict] = None, stream=None) -> None:
-        """Cliffords into the frame, rotations onto psi as one fused plan (synchronous)."""
-        _c.cfh_circuit_run(self.h, gates, angles, psi, tuning, stream)
+                    tuning: Optional[dict] = None, stream=None) -> np.ndarray:
+        """Cliffords into the frame, rotations onto psi as fused plans between
+        measurements (synchronous); returns the measurement/reset outcomes."""
+        return _c.cfh_circuit_run(self.h, gates, angles, psi, tuning, stream)
 
     def flush(self, psi: torch.Tensor, stream=None) -> None:
         """psi <- U psi (up to a global phase) on the device; the frame becomes the identity."""

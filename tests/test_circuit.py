@@ -97,10 +97,47 @@ def test_translate_is_exact_frame_times_rotations(n):
 def test_translate_rejects_bad_rows():
     f = hybrid.Frame(3)
     for g, a in [(np.array([[11, 0, 1]], np.int32), np.zeros(1)), (np.array([[11, 3, -1]], np.int32), np.zeros(1)),
-                 (np.array([[12, 0, -1]], np.int32), np.zeros(1))]:
+                 (np.array([[14, 0, -1]], np.int32), np.zeros(1))]:
         with pytest.raises(cfh.CfhError) as e:
             f.translate(g, a)
         assert e.value.code == cfh.CFH_E_INVAL
     with pytest.raises(cfh.CfhError):
         cfh._call("cfh_circuit_translate", f.h, np.array([[11, 0, -1]], np.int32).ctypes.data, None, 1,
                   None, None, 0, __import__("ctypes").byref(__import__("ctypes").c_size_t()))
+
+
+def test_oracle_measurement_definitions():
+    """The oracle's Pauli measurement against dense projectors (1 + s P)/2 and
+    against its own Z-basis measurement; the collapsed state is the s
+    eigenstate and normalized."""
+    n = 4
+    rng = np.random.default_rng(7)
+    for trial in range(12):
+        v = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+        v /= np.linalg.norm(v)
+        letters = rng.integers(0, 4, size=n).astype(np.uint8)
+        if not letters.any():
+            letters[0] = 3
+        P = dense.pauli(letters)
+        p_plus = 0.5 * (1 + np.vdot(v, P @ v).real)
+        u = float(rng.uniform())
+        w = v.copy()
+        s, pp = sim.measure_pauli(w, n, letters, u)
+        assert abs(pp - p_plus) <= 1e-12 and s == (1 if u < p_plus else -1)
+        ref = 0.5 * (np.eye(1 << n) + s * P) @ v
+        ref /= np.linalg.norm(ref)
+        assert np.abs(w - ref).max() <= 1e-12
+        assert abs(np.vdot(w, P @ w).real - s) <= 1e-12
+        q = int(rng.integers(0, n))
+        zl = np.zeros(n, np.uint8)
+        zl[q] = 3
+        a, b = v.copy(), v.copy()
+        assert sim.measure_z(a, n, q, u) == pytest.approx(sim.measure_pauli(b, n, zl, u))
+        assert np.abs(a - b).max() <= 1e-12
+
+
+def test_translate_rejects_measurement_rows():
+    f = hybrid.Frame(3)
+    with pytest.raises(cfh.CfhError) as e:
+        f.translate(np.array([[0, 0, -1], [12, 0, -1]], np.int32), np.array([0.0, 0.5]))
+    assert e.value.code == cfh.CFH_E_UNSUPPORTED

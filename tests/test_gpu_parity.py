@@ -568,3 +568,71 @@ def test_circuit_run_vs_oracle_gate_by_gate(dtype, n, k, terms, steps):
     ph = got[j] / phys[j]
     assert abs(abs(ph) - 1) <= tol
     assert np.abs(got - ph * phys).max() <= tol
+
+
+# ------------------------------------------------------ measurement, reset
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_measure_pauli_vs_oracle(dtype):
+    """Born probability and collapsed state of multi-qubit Pauli measurements
+    (weights 1..n, Y letters, diagonal and off-diagonal) against the oracle's
+    projector definition, for u on both sides of P(+1)."""
+    n = 12
+    rng = np.random.default_rng(31)
+    tol = TOL[dtype] * (10 if dtype == torch.complex128 else 1)
+    for trial in range(10):
+        v = rand_state(n, 100 + trial)
+        letters = rng.integers(0, 4, size=n).astype(np.uint8)
+        if trial % 3 == 0:
+            letters[letters != 0] = 3          # diagonal
+        if not letters.any():
+            letters[0] = 1
+        p = cfh.cfh_pauli_encode(letters[None, :])[0]
+        for u in (0.02 + 0.9 * rng.uniform(), rng.uniform() * 0.05):
+            psi = to_dev(v, dtype)
+            w = v.copy()
+            s_ref, pp_ref = sim.measure_pauli(w, n, letters, u)
+            if abs(u - pp_ref) < 1e-9:
+                continue                        # outcome decided by rounding: not comparable
+            s, pp = cfh.cfh_measure_pauli(psi, n, int(p["x"]), int(p["z"]), int(p["e"]), u)
+            assert s == s_ref and abs(pp - pp_ref) <= tol
+            assert maxdiff(psi, w) <= tol
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [8, 14])
+def test_circuit_with_measurements_and_resets_vs_oracle(dtype, n):
+    """Circuits of Cliffords, RX/RY/RZ, Z measurements and resets: outcomes and
+    the flushed final state (up to phase) against the oracle's gate-by-gate
+    run with the same uniform numbers."""
+    rng = np.random.default_rng(n)
+    tol = TOL[dtype] * (10 if dtype == torch.complex128 else 1)
+    for trial in range(4):
+        gates, angles = [], []
+        for _ in range(30 * n):
+            r = rng.random()
+            if r < 0.3:
+                gates.append((int(rng.integers(9, 12)), int(rng.integers(0, n)), -1))
+                angles.append(float(rng.uniform(-np.pi, np.pi)))
+            elif r < 0.34:
+                gates.append((int(rng.integers(12, 14)), int(rng.integers(0, n)), -1))
+                angles.append(float(rng.uniform()))
+            elif r < 0.65:
+                a, b = rng.choice(n, size=2, replace=False)
+                gates.append((int(rng.integers(6, 9)), int(a), int(b)))
+                angles.append(0.0)
+            else:
+                gates.append((int(rng.integers(0, 6)), int(rng.integers(0, n)), -1))
+                angles.append(0.0)
+        g, a = np.array(gates, np.int32), np.array(angles)
+        phys = sim.basis_state(n, 0)
+        out_ref = sim.apply_circuit(phys, n, g, a)
+        frame = hybrid.Frame(n)
+        psi = hybrid.new_state(n, dtype, index=0)
+        out = frame.run_circuit(g, a, psi)
+        assert np.array_equal(out, out_ref), trial
+        frame.flush(psi)
+        got = psi.cpu().to(torch.complex128).numpy()
+        j = int(np.argmax(np.abs(phys)))
+        ph = got[j] / phys[j]
+        assert abs(abs(ph) - 1) <= tol and np.abs(got - ph * phys).max() <= tol, trial
