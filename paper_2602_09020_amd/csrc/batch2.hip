@@ -309,43 +309,6 @@ k_batch_meas2(const BatchArgs A, const PassArgs2 *__restrict__ pa, const BItem *
     }
 }
 
-// One term on the registers: lam_j += sigma_j w beta psi_{j ^ CX} for every
-// register j (beta = 1, or i when IMAG), sigma_j the register sign from msign.
-template <int CX, bool IMAG>
-__device__ __forceinline__ void ham_body(const double2 (&r)[kRegs], double2 (&l)[kRegs], double w, uint32_t msign)
-{
-#pragma unroll
-    for (int j = 0; j < kRegs; ++j) {
-        const double wj = flip_if(w, msign >> j);
-        const double2 v = r[j ^ CX];
-        if (IMAG) {
-            l[j].x = fma(-wj, v.y, l[j].x);
-            l[j].y = fma(wj, v.x, l[j].y);
-        } else {
-            l[j].x = fma(wj, v.x, l[j].x);
-            l[j].y = fma(wj, v.y, l[j].y);
-        }
-    }
-}
-
-// Uniform branch tree over the partner mask (bits 3..0) and real/imaginary w.
-template <int BIT, int ACC>
-__device__ __forceinline__ void ham_dispatch(uint32_t cx, bool imag, const double2 (&r)[kRegs], double2 (&l)[kRegs],
-                                             double w, uint32_t msign)
-{
-    if constexpr (BIT < 0) {
-        if (imag)
-            ham_body<ACC, true>(r, l, w, msign);
-        else
-            ham_body<ACC, false>(r, l, w, msign);
-    } else {
-        if (cx & (1u << BIT))
-            ham_dispatch<BIT - 1, ACC | (1 << BIT)>(cx, imag, r, l, w, msign);
-        else
-            ham_dispatch<BIT - 1, ACC>(cx, imag, r, l, w, msign);
-    }
-}
-
 // H psi items (gradient runs): psi and lam of a coset in registers (half-tile
 // transposes of both), lam += sum_k w_k P_k psi over the pass's terms (lam
 // starts at zero on the circuit's first such pass), lam written back; the

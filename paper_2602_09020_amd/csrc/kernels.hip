@@ -743,6 +743,8 @@ struct cfh_ham_s {
     int64_t n_groups = 0;
     // register-tiled measurement passes for <H> (used when mmode != 0)
     std::vector<PassArgs2> margs;
+    // register-tiled H psi passes (psi and lam in registers), when not empty
+    std::vector<PassArgs2> hargs;
     double2 *mw = nullptr;              // per-term weight c_k i^{(e-|x&z|)}
     int mmode = 0;
     static constexpr unsigned kMeasureGrid = 2048;
@@ -756,6 +758,51 @@ struct cfh_ham_s {
 };
 
 namespace {
+
+// Register-tiled passes over the terms of an observable: the x-groups (split
+// to at most kMaxRun terms) planned onto tiles, each pass's terms ordered so
+// consecutive ones share register micro-groups (anchored for half-tile
+// transposes), runs that need more micro-groups split in two.
+cfh_status term_passes(int n, int dtype, const std::vector<HamGroup> &groups, const std::vector<Pauli> &tp,
+                       const TuningResolved &tm, bool anchor, std::vector<PassArgs2> &out, const char *what)
+{
+    std::vector<HamGroup> mg;
+    for (const HamGroup &g : groups)
+        for (size_t i = 0; i < g.terms.size(); i += kMaxRun)
+            mg.push_back(HamGroup{g.x, std::vector<int>(g.terms.begin() + (std::ptrdiff_t)i,
+                                                        g.terms.begin() +
+                                                            (std::ptrdiff_t)std::min(g.terms.size(), i + kMaxRun))});
+    std::vector<PassPlan> todo;
+    for (const HamPass &hp : plan_hamiltonian(n, mg, tm, kMaxGroupsPerPass, kMaxRun)) {
+        std::vector<int> idx;
+        for (int g : hp.groups) idx.insert(idx.end(), mg[g].terms.begin(), mg[g].terms.end());
+        PassPlan pp;
+        pp.b = hp.b;
+        pp.outer_mask = hp.outer_mask;
+        pp.v = hp.v;
+        pp.rots = order_for_microgroups(hp.v, tp, idx, anchor);
+        todo.push_back(std::move(pp));
+    }
+    std::reverse(todo.begin(), todo.end());
+    PassArgs2 a2;
+    while (!todo.empty()) {
+        PassPlan pp = std::move(todo.back());
+        todo.pop_back();
+        if (build_pass_args2(pp, tp, false, anchor, a2)) {
+            a2.xrot = line_share_bits(a2.outer_mask, n, a2.b, (int)amp_bytes(dtype), tm.tile_order);
+            out.push_back(a2);
+            continue;
+        }
+        if (pp.rots.size() < 2) return set_error(CFH_E_INVAL, std::string(what) + ": a term does not fit the tile");
+        PassPlan hi = pp;
+        const size_t half = pp.rots.size() / 2;
+        hi.rots.assign(pp.rots.begin() + (std::ptrdiff_t)half, pp.rots.end());
+        pp.rots.resize(half);
+        todo.push_back(std::move(hi));
+        todo.push_back(std::move(pp));
+    }
+    return CFH_OK;
+}
 
 unsigned persistent_grid(uint64_t ntiles)
 {
@@ -1150,43 +1197,18 @@ cfh_status cfh_ham_create(int n, int dtype, const cfh_pauli *terms, const double
         TuningResolved tm = resolve_tuning(tuning, n, dtype, kTuneMeasure);
         if (tm.variant != 1 && tm.tile_bits >= 10 && tm.tile_bits <= 14 && m > 0) {
             const bool anchor = tm.tile_bits == 14;
-            std::vector<HamGroup> mg;
-            for (const HamGroup &g : groups)
-                for (size_t i = 0; i < g.terms.size(); i += kMaxRun)
-                    mg.push_back(HamGroup{g.x, std::vector<int>(g.terms.begin() + (std::ptrdiff_t)i,
-                                                                g.terms.begin() + (std::ptrdiff_t)std::min(
-                                                                                      g.terms.size(), i + kMaxRun))});
             std::vector<Pauli> tp(m);
             for (size_t i = 0; i < m; ++i) tp[i] = Pauli{terms[i].x, terms[i].z, terms[i].e & 3};
-            std::vector<PassPlan> todo;
-            for (const HamPass &hp : plan_hamiltonian(n, mg, tm, kMaxGroupsPerPass, kMaxRun)) {
-                std::vector<int> idx;
-                for (int g : hp.groups) idx.insert(idx.end(), mg[g].terms.begin(), mg[g].terms.end());
-                PassPlan pp;
-                pp.b = hp.b;
-                pp.outer_mask = hp.outer_mask;
-                pp.v = hp.v;
-                pp.rots = order_for_microgroups(hp.v, tp, idx, anchor);
-                todo.push_back(std::move(pp));
-            }
-            std::reverse(todo.begin(), todo.end());
-            PassArgs2 a2;
-            while (!todo.empty()) {
-                PassPlan pp = std::move(todo.back());
-                todo.pop_back();
-                if (build_pass_args2(pp, tp, false, anchor, a2)) {
-                    a2.xrot = line_share_bits(a2.outer_mask, n, a2.b, (int)amp_bytes(dtype), tm.tile_order);
-                    h->margs.push_back(a2);
-                    continue;
-                }
-                if (pp.rots.size() < 2) return set_error(CFH_E_INVAL, "cfh_ham_create: a term does not fit the tile");
-                PassPlan hi = pp;
-                const size_t half = pp.rots.size() / 2;
-                hi.rots.assign(pp.rots.begin() + (std::ptrdiff_t)half, pp.rots.end());
-                pp.rots.resize(half);
-                todo.push_back(std::move(hi));
-                todo.push_back(std::move(pp));
-            }
+            st = term_passes(n, dtype, groups, tp, tm, anchor, h->margs, "cfh_ham_create");
+            if (st) return st;
+            // H psi (the adjoint's lam) on the same kernel family: psi and lam in
+            // registers, both moved through half-tile LDS buffers, so the tile is
+            // at most 2^13 complex128 / 2^14 complex64
+            TuningResolved th = tm;
+            th.tile_bits = std::min(tm.tile_bits, dtype == CFH_C128 ? 13 : 14);
+            if (th.tile_bits < n) th.low_bits = std::min(th.low_bits, th.tile_bits - 1);
+            st = term_passes(n, dtype, groups, tp, th, true, h->hargs, "cfh_ham_create");
+            if (st) return st;
             std::vector<double2> w(m);
             for (size_t i = 0; i < m; ++i) {
                 const int wp = (terms[i].e - popc(terms[i].x & terms[i].z)) & 3;  // i^wp
@@ -1270,6 +1292,17 @@ cfh_status cfh_ham_apply(cfh_ham h, const void *psi, void *out, void *stream)
         hipLaunchKernelGGL(k_zero_d, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, (double *)out,
                            (int64_t)cnt);
         return last_launch("k_zero_d");
+    }
+    if (!h->hargs.empty()) {
+        for (size_t i = 0; i < h->hargs.size(); ++i) {
+            const PassArgs2 &a = h->hargs[i];
+            const uint64_t ntiles = 1ull << (h->n - a.b);
+            cfh_status st = h->dtype == CFH_C128
+                                ? launch_ham2(ntiles, s, (const double2 *)psi, (double2 *)out, h->mw, a, i > 0)
+                                : launch_ham2(ntiles, s, (const float2 *)psi, (float2 *)out, h->mw, a, i > 0);
+            if (st) return st;
+        }
+        return CFH_OK;
     }
     for (size_t i = 0; i < h->args.size(); ++i) {
         const HamPassArgs &a = h->args[i];

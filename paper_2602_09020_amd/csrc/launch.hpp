@@ -43,4 +43,15 @@ extern template cfh_status launch_adj2<double2>(uint64_t, hipStream_t, double2 *
 extern template cfh_status launch_adj2<float2>(uint64_t, hipStream_t, float2 *, float2 *, const double2 *,
                                                const PassArgs2 &, bool, double *, unsigned, double *);
 
+// Register-tiled H psi pass over every coset: lam (+)= sum_k w_k P_k psi over
+// the pass's terms (w in device memory, indexed by the descriptors' k); lam
+// is read only when accumulate is set.
+template <typename Amp>
+cfh_status launch_ham2(uint64_t ntiles, hipStream_t s, const Amp *psi, Amp *lam, const double2 *mw,
+                       const PassArgs2 &a, int accumulate);
+extern template cfh_status launch_ham2<double2>(uint64_t, hipStream_t, const double2 *, double2 *, const double2 *,
+                                                const PassArgs2 &, int);
+extern template cfh_status launch_ham2<float2>(uint64_t, hipStream_t, const float2 *, float2 *, const double2 *,
+                                               const PassArgs2 &, int);
+
 } // namespace cfh

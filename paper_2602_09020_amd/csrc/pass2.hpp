@@ -587,6 +587,129 @@ k_adj2(Amp *__restrict__ psi, Amp *__restrict__ lam, const double2 *__restrict__
     }
 }
 
+// One term on the registers: lam_j += sigma_j w beta psi_{j ^ CX} for every
+// register j (beta = 1, or i when IMAG), sigma_j the register sign from msign.
+template <int CX, bool IMAG>
+__device__ __forceinline__ void ham_body(const double2 (&r)[kRegs], double2 (&l)[kRegs], double w, uint32_t msign)
+{
+#pragma unroll
+    for (int j = 0; j < kRegs; ++j) {
+        const double wj = flip_if(w, msign >> j);
+        const double2 v = r[j ^ CX];
+        if (IMAG) {
+            l[j].x = fma(-wj, v.y, l[j].x);
+            l[j].y = fma(wj, v.x, l[j].y);
+        } else {
+            l[j].x = fma(wj, v.x, l[j].x);
+            l[j].y = fma(wj, v.y, l[j].y);
+        }
+    }
+}
+
+// Uniform branch tree over the partner mask (bits 3..0) and real/imaginary w.
+template <int BIT, int ACC>
+__device__ __forceinline__ void ham_dispatch(uint32_t cx, bool imag, const double2 (&r)[kRegs], double2 (&l)[kRegs],
+                                             double w, uint32_t msign)
+{
+    if constexpr (BIT < 0) {
+        if (imag)
+            ham_body<ACC, true>(r, l, w, msign);
+        else
+            ham_body<ACC, false>(r, l, w, msign);
+    } else {
+        if (cx & (1u << BIT))
+            ham_dispatch<BIT - 1, ACC | (1 << BIT)>(cx, imag, r, l, w, msign);
+        else
+            ham_dispatch<BIT - 1, ACC>(cx, imag, r, l, w, msign);
+    }
+}
+
+// Persistent H psi pass (the adjoint's lam): psi and lam of a coset in
+// registers, moved together through half-tile LDS buffers between
+// micro-groups; lam (+)= sum_k w_k P_k psi over the pass's terms, lam read
+// only when accumulating onto earlier passes.
+template <typename Amp, int B>
+__global__ void __launch_bounds__(1 << (B - kRegDims))
+k_ham2(const Amp *__restrict__ psi, Amp *__restrict__ lam, const double2 *__restrict__ mw, const PassArgs2 args,
+       uint64_t ntiles, int accumulate)
+{
+    constexpr int LB = B - 1;
+    extern __shared__ unsigned char lds_raw[];
+    Amp *ldp = reinterpret_cast<Amp *>(lds_raw);
+    Amp *ldl = ldp + (1 << LB);
+    __shared__ double2 tab[kMaxRun];
+    const uint32_t t = threadIdx.x;
+    const int last = args.nmg - 1;
+    const int nrot = args.mg[last].rot_begin + args.mg[last].rot_count;
+    if ((int)t < nrot) tab[t] = mw[args.rot[t].k];
+    uint32_t tsb = 0;
+    for (int ri = 0; ri < nrot; ++ri) tsb |= (uint32_t)par32(t & args.rot[ri].zt) << ri;
+    __syncthreads();
+    uint64_t Lb0 = 0, LbL = 0;
+    {
+        const uint32_t b0 = deposit32(t, args.mg[0].npiv), bL = deposit32(t, args.mg[last].npiv);
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            if ((b0 >> i) & 1) Lb0 ^= args.v[i];
+            if ((bL >> i) & 1) LbL ^= args.v[i];
+        }
+    }
+#pragma unroll 1
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        asm volatile("" : "+v"(Lb0), "+v"(LbL));
+        const uint64_t tb = deposit(coset_of(tile, args.xrot), args.outer_mask);
+        double2 p[kRegs], l[kRegs];
+        {
+            const uint64_t y0 = tb ^ Lb0;
+#pragma unroll
+            for (int j = 0; j < kRegs; ++j) {
+                p[j] = ld(psi[y0 ^ args.LU_first[j]]);
+                l[j] = accumulate ? ld(lam[y0 ^ args.LU_first[j]]) : make_double2(0.0, 0.0);
+            }
+        }
+        uint32_t bprev = 0;
+#pragma unroll 1
+        for (int g = 0; g <= last; ++g) {
+            const MGDesc2 &m = args.mg[g];
+            const uint32_t bt = deposit32(t, m.npiv);
+            if (g > 0) {
+                const MGDesc2 &mp = args.mg[g - 1];
+                // bprev and bt have 0 at the anchor bit (it is a pivot)
+                const uint32_t lo = (1u << args.qbit) - 1;
+                const uint32_t bw = (bprev & lo) | ((bprev >> 1) & ~lo);
+                const uint32_t br = (bt & lo) | ((bt >> 1) & ~lo);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                    for (int j = h; j < kRegs; j += 2) {
+                        st(ldp[bw ^ mp.UC[j]], p[j]);
+                        st(ldl[bw ^ mp.UC[j]], l[j]);
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int j = h; j < kRegs; j += 2) {
+                        p[j] = ld(ldp[br ^ m.UC[j]]);
+                        l[j] = ld(ldl[br ^ m.UC[j]]);
+                    }
+                    __syncthreads();
+                }
+            }
+            bprev = bt;
+#pragma unroll 1
+            for (int ri = m.rot_begin; ri < m.rot_begin + m.rot_count; ++ri) {
+                const RotDesc2 &d = args.rot[ri];
+                const double2 w = tab[ri];
+                const bool imag = w.y != 0.0;
+                const uint32_t sg = ((tsb >> ri) ^ (uint32_t)par64(tb & d.z)) & 1u;
+                ham_dispatch<3, 0>(d.cx, imag, p, l, flip_if(imag ? w.y : w.x, sg), d.msign);
+            }
+        }
+        const uint64_t yL = tb ^ LbL;
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) st(lam[yL ^ args.LU_last[j]], l[j]);
+    }
+}
+
 // grad[k of rotation ri] = sum over the pass's workgroups of their partials (fixed order).
 __global__ void k_grad_reduce2(const double *__restrict__ gpart, int nblocks, const PassArgs2 args,
                                double *__restrict__ grad)
@@ -683,9 +806,51 @@ cfh_status launch_pass2_m(uint64_t ntiles, hipStream_t s, Amp *psi, const double
     }
 }
 
+template <typename Amp, int B>
+cfh_status launch_ham2_b(uint64_t ntiles, hipStream_t s, const Amp *psi, Amp *lam, const double2 *mw,
+                         const PassArgs2 &a, int accumulate)
+{
+    if constexpr (2 * ((size_t)1 << (B - 1)) * sizeof(Amp) > 128 * 1024) {
+        return set_error(CFH_E_UNSUPPORTED, "H psi tile too large for LDS");
+    } else {
+        constexpr int T = 1 << (B - kRegDims);
+        const size_t lds = a.nmg > 1 ? 2 * ((size_t)1 << (B - 1)) * sizeof(Amp) : 0;
+        const void *fn = reinterpret_cast<const void *>(&k_ham2<Amp, B>);
+        static bool attr = false;
+        if (!attr) {
+            hipFuncAttributes fa{};
+            cfh_status st = CFH_OK;
+            if (!hip_ok(hipFuncGetAttributes(&fa, fn), "k_ham2: hipFuncGetAttributes", &st)) return st;
+            if (!hip_ok(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)(160 * 1024 - fa.sharedSizeBytes)),
+                        "k_ham2: hipFuncSetAttribute", &st))
+                return st;
+            attr = true;
+        }
+        unsigned grid = (unsigned)std::min<uint64_t>(ntiles, resident_grid(fn, T, lds));
+        if (a.xrot > 0) grid &= ~7u;  // coset_of: one line group per XCD
+        hipLaunchKernelGGL((k_ham2<Amp, B>), dim3(grid), dim3(T), lds, s, psi, lam, mw, a, ntiles, accumulate);
+        return last_launch("k_ham2");
+    }
+}
+
 } // namespace
 
 namespace cfh {
+
+template <typename Amp>
+cfh_status launch_ham2(uint64_t ntiles, hipStream_t s, const Amp *psi, Amp *lam, const double2 *mw,
+                       const PassArgs2 &a, int accumulate)
+{
+    switch (a.b) {
+    case 10: return launch_ham2_b<Amp, 10>(ntiles, s, psi, lam, mw, a, accumulate);
+    case 11: return launch_ham2_b<Amp, 11>(ntiles, s, psi, lam, mw, a, accumulate);
+    case 12: return launch_ham2_b<Amp, 12>(ntiles, s, psi, lam, mw, a, accumulate);
+    case 13: return launch_ham2_b<Amp, 13>(ntiles, s, psi, lam, mw, a, accumulate);
+    case 14: return launch_ham2_b<Amp, 14>(ntiles, s, psi, lam, mw, a, accumulate);
+    default: return set_error(CFH_E_UNSUPPORTED, "register-tiled H psi needs tile_bits in 10..14");
+    }
+}
 
 template <typename Amp>
 cfh_status launch_adj2(uint64_t ntiles, hipStream_t s, Amp *psi, Amp *lam, const double2 *coef, const PassArgs2 &a,

@@ -636,3 +636,33 @@ def test_circuit_with_measurements_and_resets_vs_oracle(dtype, n):
         j = int(np.argmax(np.abs(phys)))
         ph = got[j] / phys[j]
         assert abs(abs(ph) - 1) <= tol and np.abs(got - ph * phys).max() <= tol, trial
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n,tb", [(12, 10), (15, 12), (16, 13), (17, 14)])
+def test_ham_apply_register_tiled_vs_oracle(dtype, n, tb):
+    """H psi on register tiles (psi and lam in registers, half-tile transposes;
+    the tile capped at 2^13 complex128): JW, dense, diagonal and shared-x terms
+    against the oracle's letter-by-letter H psi and against the LDS-staged
+    passes."""
+    rng = np.random.default_rng(n * tb)
+    v = rand_state(n, n + tb)
+    rows = np.concatenate([W.jw_strings(rng, n, 40), rng.integers(0, 4, size=(60, n)).astype(np.uint8),
+                           np.where(rng.integers(0, 2, size=(15, n)) == 1, 3, 0).astype(np.uint8)])
+    same = np.where(rng.integers(0, 2, size=(35, n)) == 1, 3, 0).astype(np.uint8)
+    same[:, 1] = 1
+    same[:, 4] = 2
+    rows = np.concatenate([rows, same])
+    coeff = rng.normal(size=rows.shape[0])
+    terms = cfh.cfh_pauli_encode(rows)
+    psi = to_dev(v, dtype)
+    h_reg = hybrid.Hamiltonian(n, dtype, terms, coeff, {"tile_bits": tb})
+    h_lds = hybrid.Hamiltonian(n, dtype, terms, coeff, {"tile_bits": min(tb, 13), "variant": 1})
+    out_r, out_l = torch.empty_like(psi), torch.empty_like(psi)
+    h_reg.apply(psi, out_r)
+    h_lds.apply(psi, out_l)
+    torch.cuda.synchronize()
+    ref = sim.apply_pauli_sum(psi.cpu().to(torch.complex128).numpy(), n, rows, coeff)
+    tol = (1e-12 if dtype == torch.complex128 else 1e-4) * np.abs(coeff).sum()
+    assert maxdiff(out_r, ref) <= tol
+    assert (out_r - out_l).abs().max().item() <= tol
