@@ -666,3 +666,39 @@ def test_ham_apply_register_tiled_vs_oracle(dtype, n, tb):
     tol = (1e-12 if dtype == torch.complex128 else 1e-4) * np.abs(coeff).sum()
     assert maxdiff(out_r, ref) <= tol
     assert (out_r - out_l).abs().max().item() <= tol
+
+
+# ------------------------------------------------------------ graph capture
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_plan_and_expval_captured_in_a_graph(dtype):
+    """cfh_state_set_basis, cfh_apply_plan and cfh_expval_async allocate
+    nothing and never synchronize, so they can be captured in a HIP graph: every
+    replay (eager work in between) gives the eager state and <H> bit for bit."""
+    w = W.config(1, n=18, n_rot=400)
+    frame, rot, terms, plan, ham = hybrid.prepare(w, dtype)
+    n = w.n
+    psi = hybrid.new_state(n, dtype, index=w.init)
+    th = torch.tensor(w.theta, device=DEV)
+    out = torch.zeros(2, dtype=torch.float64, device=DEV)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        cfh.cfh_state_set_basis(psi, n, w.init, s)
+        plan.apply(psi, th, stream=s)
+        ham.expval_async(psi, out, s)
+    s.synchronize()
+    ref_psi, ref_e = psi.clone(), out.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        cfh.cfh_state_set_basis(psi, n, w.init, s)
+        plan.apply(psi, th, stream=s)
+        ham.expval_async(psi, out, s)
+    for rep in range(4):
+        psi.zero_()
+        out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(psi, ref_psi), rep
+        assert torch.equal(out, ref_e), rep
+        x = torch.randn(1 << 16, device=DEV)
+        (x * 3).sum().item()
