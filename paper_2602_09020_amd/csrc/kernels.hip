@@ -1206,6 +1206,8 @@ cfh_status cfh_ham_create(int n, int dtype, const cfh_pauli *terms, const double
             // at most 2^13 complex128 / 2^14 complex64
             TuningResolved th = tm;
             th.tile_bits = std::min(tm.tile_bits, dtype == CFH_C128 ? 13 : 14);
+            // two vectors per workgroup, as in the adjoint: at least 256 tiles
+            th.tile_bits = std::min(th.tile_bits, std::max(n - 8, std::min(n, 10)));
             if (th.tile_bits < n) th.low_bits = std::min(th.low_bits, th.tile_bits - 1);
             st = term_passes(n, dtype, groups, tp, th, true, h->hargs, "cfh_ham_create");
             if (st) return st;

@@ -17,15 +17,18 @@ TuningResolved resolve_tuning(const cfh_tuning *t, int n, int dtype, int kind)
     // 128-byte contiguous chunks (8 complex128 / 16 complex64 amplitudes),
     // which leaves the most free dimensions per pass at full cache-line use;
     // complex128 on 2^14-amplitude tiles (half-tile transposes), complex64 on
-    // 2^13.  Small states keep at least 512 tiles per pass so every CU gets
-    // work.  The adjoint holds two tiles in LDS and uses 2^11 (c128) / 2^12
+    // 2^13.  Small states keep at least 128 tiles per pass: their passes are
+    // short and latency-bound, so fewer, larger passes win until the grid gets
+    // too small (measured at 18-24 qubits).  The adjoint holds two tiles in LDS and uses 2^11 (c128) / 2^12
     // (c64).  The read-only Hamiltonian passes use 2^12 / 2^13 tiles with
     // 32-amplitude chunks.
     int b = c64 ? 13 : 14;
     if (kind == kTuneAdjoint) b = c64 ? 12 : 11;
     if (kind == kTuneHamiltonian) b = c64 ? 13 : 12;
     if (kind == kTuneAdjoint2) b = c64 ? 14 : 13;
-    b = std::max(std::min(b, n - 9), std::min(n, 10));
+    // the adjoint holds two vectors per workgroup (fewer workgroups per CU),
+    // so it keeps at least 256 tiles
+    b = std::max(std::min(b, n - (kind == kTuneAdjoint2 ? 8 : 7)), std::min(n, 10));
     r.tile_bits = (t && t->tile_bits > 0) ? t->tile_bits : b;
     const int c_def = kind == kTuneHamiltonian ? 5
                       : ((kind == kTuneForward || kind == kTuneMeasure || kind == kTuneAdjoint2) && !c64) ? 3
