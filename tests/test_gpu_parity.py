@@ -702,3 +702,54 @@ def test_plan_and_expval_captured_in_a_graph(dtype):
         assert torch.equal(out, ref_e), rep
         x = torch.randn(1 << 16, device=DEV)
         (x * 3).sum().item()
+
+
+# ----------------------------------------------------------- degenerate cases
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_degenerate_inputs(dtype):
+    """Empty plans, circuits and observables; one qubit; zero angles; the
+    identity measured; an identity frame flushed: all leave the state as the
+    definitions say."""
+    n = 9
+    v = rand_state(n, 5)
+    psi = to_dev(v, dtype)
+    ref = psi.clone()
+    tol = TOL[dtype]
+    # empty plan, empty circuit, identity-frame flush: no change
+    hybrid.Plan(n, dtype, np.zeros(0, cfh.PAULI_DTYPE)).apply(psi, torch.zeros(0, dtype=torch.float64, device=DEV))
+    f = hybrid.Frame(n)
+    assert f.run_circuit(np.zeros((0, 3), np.int32), None, psi).shape == (0,)
+    f.flush(psi)
+    torch.cuda.synchronize()
+    assert torch.equal(psi, ref)
+    # zero angles: identity up to rounding of cos(0) = 1, sin(0) = 0 (exact)
+    rows = np.random.default_rng(1).integers(0, 4, size=(50, n)).astype(np.uint8)
+    p = hybrid.Plan(n, dtype, cfh.cfh_pauli_encode(rows))
+    p.apply(psi, torch.zeros(50, dtype=torch.float64, device=DEV))
+    torch.cuda.synchronize()
+    assert (psi - ref).abs().max().item() <= tol
+    # the identity measured: outcome +1 with probability 1, no change
+    s, pp = cfh.cfh_measure_pauli(psi, n, 0, 0, 0, 0.999)
+    assert s == 1 and abs(pp - 1) <= 1e-12 and (psi - ref).abs().max().item() <= tol
+    # an observable without terms: <H> = 0 and H psi = 0
+    h0 = hybrid.Hamiltonian(n, dtype, np.zeros(0, cfh.PAULI_DTYPE), np.zeros(0))
+    assert h0.expval(psi) == 0
+    out = torch.ones_like(psi)
+    h0.apply(psi, out)
+    torch.cuda.synchronize()
+    assert out.abs().max().item() == 0
+    # one qubit: rotation, <Y>, measurement and flush against closed forms
+    q = hybrid.new_state(1, dtype, index=0)
+    fr = hybrid.Frame(1)
+    g = np.array([[0, 0, -1], [9, 0, -1], [1, 0, -1]], np.int32)       # H, RX(0.7), S
+    fr.run_circuit(g, np.array([0.0, 0.7, 0.0]), q)
+    phys = sim.basis_state(1, 0)
+    sim.apply_circuit(phys, 1, g, np.array([0.0, 0.7, 0.0]))
+    hy = hybrid.Hamiltonian(1, dtype, fr.conjugate(cfh.cfh_pauli_encode(np.array([[2]], np.uint8))), np.ones(1))
+    assert abs(hy.expval(q).real - sim.expval(phys, 1, np.array([2], np.uint8)).real) <= tol
+    fr.flush(q)
+    got = q.cpu().to(torch.complex128).numpy()
+    j = int(np.argmax(np.abs(phys)))
+    ph = got[j] / phys[j]
+    assert abs(abs(ph) - 1) <= tol and np.abs(got - ph * phys).max() <= tol
