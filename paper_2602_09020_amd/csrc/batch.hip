@@ -539,14 +539,14 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
                 done.push_back(std::move(pp));
                 first_pass = false;
             }
-            // adjoint passes: the same runs walked backwards with anchored
-            // micro-groups (half-tile transposes); a run that needs more
-            // micro-groups anchored is split, its later half walked first
+            // adjoint passes: the same runs walked backwards (anchored
+            // micro-groups and half-tile transposes at complex128); a run that
+            // needs more micro-groups so is split, its later half walked first
             std::vector<PassPlan> rtodo(done.begin(), done.end());
             while (!rtodo.empty()) {
                 PassPlan pp = std::move(rtodo.back());
                 rtodo.pop_back();
-                if (!build_pass_args2(pp, r, true, true, a2)) {
+                if (!build_pass_args2(pp, r, true, batch_fwd_half((int)ab), a2)) {
                     if (pp.rots.size() < 2)
                         return set_error(CFH_E_INVAL, "cfh_batch_create: a rotation does not fit the register tile");
                     PassPlan hi = pp;
@@ -625,8 +625,8 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
         std::vector<int> meas_ids, ham2_ids;
         if (reg) {
             // terms planned on register tiles: read-only measurement passes for
-            // forward runs, H psi passes (anchored, half-tile transposes of psi
-            // and lam) for gradient runs
+            // forward runs, H psi passes (psi and lam in registers; anchored,
+            // half-tile transposes at complex128) for gradient runs
             cfh_tuning t3{};
             t3.tile_bits = kBatchRegTile;
             const TuningResolved tm = resolve_tuning(&t3, d.n, dtype, kTuneMeasure);
@@ -639,8 +639,10 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
             std::vector<Pauli> tp(d.mh);
             for (int64_t i = 0; i < d.mh; ++i) tp[i] = Pauli{d.terms[i].x, d.terms[i].z, d.terms[i].e & 3};
             const std::vector<HamPass> mps = plan_hamiltonian(d.n, mgr, tm, kMaxGroupsPerPass, kMaxRun);
-            for (const bool anchored : {false, true}) {
-                std::vector<int> &ids = anchored ? ham2_ids : meas_ids;
+            for (const bool ham : {false, true}) {
+                // H psi items use half-tile transposes where the forward items do
+                const bool anchored = ham && batch_fwd_half((int)ab);
+                std::vector<int> &ids = ham ? ham2_ids : meas_ids;
                 std::vector<PassPlan> todo;
                 for (const HamPass &mp : mps) {
                     std::vector<int> idx;
@@ -669,7 +671,7 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
                         continue;
                     }
                     if (a3.b != kBatchRegTile) return set_error(CFH_E_INVAL, "cfh_batch_create: register tile size");
-                    const int id = new_pass(anchored ? kPassHam : kPassMeas, kBatchRegTile, pp.outer_mask, pp.v, 0,
+                    const int id = new_pass(ham ? kPassHam : kPassMeas, kBatchRegTile, pp.outer_mask, pp.v, 0,
                                             (int)pp.rots.size(), ids.empty() ? 0 : kFlagAccumulate);
                     B->passes[id].p2 = (int)pa.size();
                     B->passes[id].nitems = nitems2;

@@ -71,9 +71,9 @@ struct BatchArgs {
 // PassArgs2 is pa[passes[item.pass].p2].  The first pass of a circuit builds
 // its basis state instead of reading psi.
 constexpr int kBatchRegTile = 12;
-// Complex128 forward items transpose in two halves through half the LDS
-// (anchored micro-groups), so four workgroups fit on a CU as complex64 ones
-// do with whole-tile transposes.
+// Complex128 items transpose in two halves through half the LDS (anchored
+// micro-groups), so as many workgroups fit on a CU as complex64 ones do with
+// whole-tile transposes.
 constexpr bool batch_fwd_half(int amp_bytes) { return amp_bytes == 16; }
 template <typename Amp>
 cfh_status launch_batch_fwd2(unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,

@@ -114,12 +114,12 @@ k_batch_fwd2(const BatchArgs A, const PassArgs2 *__restrict__ pa, const BItem *_
 // vectors), each rotation's share of g_k = Im <lam|P_k|psi> summed per wave
 // over the item's cosets and written to the item's gradient partials, which
 // the level's reduction adds in a fixed order.
-template <typename Amp, int B>
+template <typename Amp, int B, bool HALF>
 __global__ void __launch_bounds__(1 << (B - kRegDims))
 k_batch_adj2(const BatchArgs A, const PassArgs2 *__restrict__ pa, const BItem *__restrict__ items)
 {
     constexpr int NW = (1 << (B - kRegDims)) / 64;
-    constexpr int LB = B - 1;
+    constexpr int LB = HALF ? B - 1 : B;
     extern __shared__ unsigned char lds_raw[];
     Amp *ldp = reinterpret_cast<Amp *>(lds_raw);
     Amp *ldl = ldp + (1 << LB);
@@ -178,22 +178,37 @@ k_batch_adj2(const BatchArgs A, const PassArgs2 *__restrict__ pa, const BItem *_
             const uint32_t bt = deposit32(t, m.npiv);
             if (g > 0) {
                 const MGDesc2 &mp = args.mg[g - 1];
-                // bprev and bt have 0 at the anchor bit (it is a pivot)
-                const uint32_t lo = (1u << args.qbit) - 1;
-                const uint32_t bw = (bprev & lo) | ((bprev >> 1) & ~lo);
-                const uint32_t br = (bt & lo) | ((bt >> 1) & ~lo);
+                if constexpr (HALF) {
+                    // bprev and bt have 0 at the anchor bit (it is a pivot)
+                    const uint32_t lo = (1u << args.qbit) - 1;
+                    const uint32_t bw = (bprev & lo) | ((bprev >> 1) & ~lo);
+                    const uint32_t br = (bt & lo) | ((bt >> 1) & ~lo);
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
+                    for (int h = 0; h < 2; ++h) {
 #pragma unroll
-                    for (int j = h; j < kRegs; j += 2) {
-                        st(ldp[bw ^ mp.UC[j]], p[j]);
-                        st(ldl[bw ^ mp.UC[j]], l[j]);
+                        for (int j = h; j < kRegs; j += 2) {
+                            st(ldp[bw ^ mp.UC[j]], p[j]);
+                            st(ldl[bw ^ mp.UC[j]], l[j]);
+                        }
+                        __syncthreads();
+#pragma unroll
+                        for (int j = h; j < kRegs; j += 2) {
+                            p[j] = ld(ldp[br ^ m.UC[j]]);
+                            l[j] = ld(ldl[br ^ m.UC[j]]);
+                        }
+                        __syncthreads();
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < kRegs; ++j) {
+                        st(ldp[bprev ^ mp.U[j]], p[j]);
+                        st(ldl[bprev ^ mp.U[j]], l[j]);
                     }
                     __syncthreads();
 #pragma unroll
-                    for (int j = h; j < kRegs; j += 2) {
-                        p[j] = ld(ldp[br ^ m.UC[j]]);
-                        l[j] = ld(ldl[br ^ m.UC[j]]);
+                    for (int j = 0; j < kRegs; ++j) {
+                        p[j] = ld(ldp[bt ^ m.U[j]]);
+                        l[j] = ld(ldl[bt ^ m.U[j]]);
                     }
                     __syncthreads();
                 }
@@ -314,12 +329,12 @@ k_batch_meas2(const BatchArgs A, const PassArgs2 *__restrict__ pa, const BItem *
 // starts at zero on the circuit's first such pass), lam written back; the
 // last pass also adds Re <psi|lam> over the item's cosets to its energy
 // partial.
-template <typename Amp, int B>
+template <typename Amp, int B, bool HALF>
 __global__ void __launch_bounds__(1 << (B - kRegDims))
 k_batch_ham2(const BatchArgs A, const PassArgs2 *__restrict__ pa, const BItem *__restrict__ items)
 {
     constexpr int NW = (1 << (B - kRegDims)) / 64;
-    constexpr int LB = B - 1;
+    constexpr int LB = HALF ? B - 1 : B;
     extern __shared__ unsigned char lds_raw[];
     Amp *ldp = reinterpret_cast<Amp *>(lds_raw);
     Amp *ldl = ldp + (1 << LB);
@@ -374,22 +389,37 @@ k_batch_ham2(const BatchArgs A, const PassArgs2 *__restrict__ pa, const BItem *_
             const uint32_t bt = deposit32(t, m.npiv);
             if (g > 0) {
                 const MGDesc2 &mp = args.mg[g - 1];
-                // bprev and bt have 0 at the anchor bit (it is a pivot)
-                const uint32_t lo = (1u << args.qbit) - 1;
-                const uint32_t bw = (bprev & lo) | ((bprev >> 1) & ~lo);
-                const uint32_t br = (bt & lo) | ((bt >> 1) & ~lo);
+                if constexpr (HALF) {
+                    // bprev and bt have 0 at the anchor bit (it is a pivot)
+                    const uint32_t lo = (1u << args.qbit) - 1;
+                    const uint32_t bw = (bprev & lo) | ((bprev >> 1) & ~lo);
+                    const uint32_t br = (bt & lo) | ((bt >> 1) & ~lo);
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
+                    for (int h = 0; h < 2; ++h) {
 #pragma unroll
-                    for (int j = h; j < kRegs; j += 2) {
-                        st(ldp[bw ^ mp.UC[j]], p[j]);
-                        st(ldl[bw ^ mp.UC[j]], l[j]);
+                        for (int j = h; j < kRegs; j += 2) {
+                            st(ldp[bw ^ mp.UC[j]], p[j]);
+                            st(ldl[bw ^ mp.UC[j]], l[j]);
+                        }
+                        __syncthreads();
+#pragma unroll
+                        for (int j = h; j < kRegs; j += 2) {
+                            p[j] = ld(ldp[br ^ m.UC[j]]);
+                            l[j] = ld(ldl[br ^ m.UC[j]]);
+                        }
+                        __syncthreads();
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < kRegs; ++j) {
+                        st(ldp[bprev ^ mp.U[j]], p[j]);
+                        st(ldl[bprev ^ mp.U[j]], l[j]);
                     }
                     __syncthreads();
 #pragma unroll
-                    for (int j = h; j < kRegs; j += 2) {
-                        p[j] = ld(ldp[br ^ m.UC[j]]);
-                        l[j] = ld(ldl[br ^ m.UC[j]]);
+                    for (int j = 0; j < kRegs; ++j) {
+                        p[j] = ld(ldp[bt ^ m.U[j]]);
+                        l[j] = ld(ldl[bt ^ m.U[j]]);
                     }
                     __syncthreads();
                 }
@@ -483,13 +513,15 @@ cfh_status launch_batch_ham2(unsigned grid, hipStream_t s, const BatchArgs &A, c
 {
     constexpr int B = kBatchRegTile;
     constexpr int T = 1 << (B - kRegDims);
-    constexpr size_t lds = 2 * ((size_t)1 << (B - 1)) * sizeof(Amp);  // half-tile buffers of psi and lam
+    constexpr bool HALF = batch_fwd_half((int)sizeof(Amp));
+    // psi and lam buffers: half tiles at complex128, whole tiles at complex64
+    constexpr size_t lds = 2 * ((size_t)1 << (HALF ? B - 1 : B)) * sizeof(Amp);
     static bool attr = false;
     if (!attr) {
-        if (cfh_status st = set_lds_limit(&k_batch_ham2<Amp, B>, "k_batch_ham2: LDS limit")) return st;
+        if (cfh_status st = set_lds_limit(&k_batch_ham2<Amp, B, HALF>, "k_batch_ham2: LDS limit")) return st;
         attr = true;
     }
-    hipLaunchKernelGGL((k_batch_ham2<Amp, B>), dim3(grid), dim3(T), lds, s, A, pa, items);
+    hipLaunchKernelGGL((k_batch_ham2<Amp, B, HALF>), dim3(grid), dim3(T), lds, s, A, pa, items);
     return last_launch("k_batch_ham2");
 }
 
@@ -499,13 +531,15 @@ cfh_status launch_batch_adj2(unsigned grid, hipStream_t s, const BatchArgs &A, c
 {
     constexpr int B = kBatchRegTile;
     constexpr int T = 1 << (B - kRegDims);
-    constexpr size_t lds = 2 * ((size_t)1 << (B - 1)) * sizeof(Amp);  // half-tile buffers of psi and lam
+    constexpr bool HALF = batch_fwd_half((int)sizeof(Amp));
+    // psi and lam buffers: half tiles at complex128, whole tiles at complex64
+    constexpr size_t lds = 2 * ((size_t)1 << (HALF ? B - 1 : B)) * sizeof(Amp);
     static bool attr = false;
     if (!attr) {
-        if (cfh_status st = set_lds_limit(&k_batch_adj2<Amp, B>, "k_batch_adj2: LDS limit")) return st;
+        if (cfh_status st = set_lds_limit(&k_batch_adj2<Amp, B, HALF>, "k_batch_adj2: LDS limit")) return st;
         attr = true;
     }
-    hipLaunchKernelGGL((k_batch_adj2<Amp, B>), dim3(grid), dim3(T), lds, s, A, pa, items);
+    hipLaunchKernelGGL((k_batch_adj2<Amp, B, HALF>), dim3(grid), dim3(T), lds, s, A, pa, items);
     return last_launch("k_batch_adj2");
 }
 
