@@ -739,6 +739,19 @@ def test_degenerate_inputs(dtype):
     h0.apply(psi, out)
     torch.cuda.synchronize()
     assert out.abs().max().item() == 0
+    # argument errors of the measurement and circuit entry points
+    for args, code in [((psi, n, 0, 1, 0, 1.0), cfh.CFH_E_INVAL),            # u outside [0, 1)
+                       ((psi, n, 0, 1, 1, 0.5), cfh.CFH_E_NOT_HERMITIAN),    # odd phase
+                       ((psi, n, 1 << n, 0, 0, 0.5), cfh.CFH_E_RANGE)]:      # mask bit >= n
+        with pytest.raises(cfh.CfhError) as e:
+            cfh.cfh_measure_pauli(*args)
+        assert e.value.code == code
+    import ctypes as C
+    g1 = np.array([[12, 0, -1]], np.int32)
+    with pytest.raises(cfh.CfhError) as e:   # a measurement row without an outcomes array
+        cfh._call("cfh_circuit_run", hybrid.Frame(n).h, g1.ctypes.data, np.array([0.5]).ctypes.data, 1,
+                  cfh._dev_ptr(psi, "psi"), cfh._dtype_code(psi), None, None, cfh._stream(None))
+    assert e.value.code == cfh.CFH_E_INVAL
     # one qubit: rotation, <Y>, measurement and flush against closed forms
     q = hybrid.new_state(1, dtype, index=0)
     fr = hybrid.Frame(1)
