@@ -63,8 +63,9 @@ def main():
     ap.add_argument("--trotter-steps", type=int, default=10)
     ap.add_argument("--no-extras", action="store_true", help="skip unfused/c64/adjoint/cpu legs")
     ap.add_argument("--cpu-rotations", type=int, default=20)
-    ap.add_argument("--mode", choices=["full", "passes", "copy"], default="full",
+    ap.add_argument("--mode", choices=["full", "passes", "expval", "copy"], default="full",
                     help="passes: apply the plan of the first --rotations rotations once (for counter runs); "
+                         "expval: those rotations, then <H> of the workload's observable --steps times; "
                          "copy: a plain device copy of the same state size (counter and bandwidth calibration)")
     ap.add_argument("--rotations", type=int, default=150)
     ap.add_argument("--chunk", type=int, default=2000, help="rotations planned per plan inside a step")
@@ -116,6 +117,27 @@ def main():
         plan.apply(psi, theta)
         torch.cuda.synchronize()
         print(json.dumps({"mode": "passes", "rotations": args.rotations, **plan.info()}), flush=True)
+        return
+    if args.mode == "expval":
+        sdt = torch.complex128 if args.dtype == "c128" else torch.complex64
+        frame = hybrid.Frame(w.n)
+        frame.apply_gates(w.prefix)
+        rot = frame.conjugate(cfh.cfh_pauli_encode(w.rot[:args.rotations]))
+        plan = hybrid.Plan(w.n, sdt, rot)
+        psi = hybrid.new_state(w.n, sdt, index=w.init)
+        plan.apply(psi, torch.tensor(w.theta[:args.rotations], device=dev))
+        ham = hybrid.Hamiltonian(w.n, sdt, frame.conjugate(cfh.cfh_pauli_encode(w.ham)), w.coeff)
+        out_dev = torch.zeros(2, dtype=torch.float64, device=dev)
+        ms = []
+        for _ in range(max(1, args.steps)):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            ham.expval_async(psi, out_dev)
+            b.record()
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        print(json.dumps({"mode": "expval", "rotations": args.rotations, "value": float(out_dev[0].item()),
+                          "ms": ms, **ham.info()}), flush=True)
         return
     n, K = w.n, w.n_rot
     dtype = torch.complex128

@@ -238,8 +238,13 @@ cfh_status cfh_apply_plan(cfh_plan p, void *psi, const double *theta_dev, int in
  * frame, e even) for expectation values and H*psi on n-qubit states.  Terms
  * are grouped by x mask.  For <H> the terms are packed into read-only passes
  * of the register-tiled kernel (at most 32 terms per pass on 2^b tiles,
- * b >= 10; tuning variant 1 or smaller tiles select LDS-staged passes); H*psi
- * always uses LDS-staged passes.  Allocates device memory.  Errors as
+ * b >= 10; tuning variant 1 or smaller tiles select LDS-staged passes;
+ * variant 5 moves the registers between micro-groups in two halves, as
+ * 2^14 tiles always do).
+ * H*psi runs on register-tiled passes that hold psi and H psi together
+ * (tiles of at most 2^13 complex128 / 2^14 complex64 amplitudes, at least
+ * 256 tiles per pass), or on LDS-staged passes where the register-tiled
+ * <H> passes are not selected.  Allocates device memory.  Errors as
  * cfh_plan_create. */
 cfh_status cfh_ham_create(int n, int dtype, const cfh_pauli *terms, const double *coeff, size_t m,
                           const cfh_tuning *tuning, cfh_ham *out);
@@ -259,7 +264,9 @@ cfh_status cfh_expval_async(cfh_ham h, const void *psi, double *out_dev, void *s
 cfh_status cfh_expval(const void *psi, int n, int dtype, const cfh_pauli *terms,
                       const double *coeff, size_t m, double *out_host, void *stream);
 
-/* out <- H psi (out-of-place; out must not alias psi). */
+/* out <- H psi (out-of-place; out must not alias psi).  Asynchronous on
+ * `stream`; allocates nothing.  Errors: CFH_E_INVAL (null or aliased
+ * pointers), CFH_E_HIP. */
 cfh_status cfh_ham_apply(cfh_ham h, const void *psi, void *out, void *stream);
 
 /* ------------------------------------------------- a9: adjoint gradient */

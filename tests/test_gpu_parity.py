@@ -256,11 +256,13 @@ def test_expval_config0_vs_oracle(dtype):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("n,tb,lb", [(14, 10, 3), (15, 12, 4), (16, 13, 3), (17, 14, 3), (15, 11, 5)])
-def test_expval_register_tiled_vs_oracle(dtype, n, tb, lb):
+@pytest.mark.parametrize("n,tb,lb,var", [(14, 10, 3, 0), (15, 12, 4, 0), (16, 13, 3, 0), (17, 14, 3, 0),
+                                         (15, 11, 5, 0), (15, 12, 4, 5), (16, 13, 3, 5)])
+def test_expval_register_tiled_vs_oracle(dtype, n, tb, lb, var):
     """<H> on the register-tiled read-only passes: JW terms, dense random terms,
     diagonal terms and 40 terms sharing one x mask (more than one pass holds),
-    against the oracle's physical state and against the LDS-staged passes."""
+    against the oracle's physical state and against the LDS-staged passes.
+    Variant 5 selects the half-tile transposes below 2^14 as well."""
     rng = np.random.default_rng(n + tb)
     w = W.make_workload("meas", n, seed=n, n_prefix=2 * n, n_rot=60, n_ham=150)
     dense = rng.integers(0, 4, size=(80, n)).astype(np.uint8)
@@ -274,7 +276,7 @@ def test_expval_register_tiled_vs_oracle(dtype, n, tb, lb):
     psi = hybrid.new_state(n, dtype, index=w.init)
     plan.apply(psi, torch.tensor(w.theta, device=DEV))
     terms = frame.conjugate(cfh.cfh_pauli_encode(rows))
-    h4 = hybrid.Hamiltonian(n, dtype, terms, coeff, {"tile_bits": tb, "low_bits": lb})
+    h4 = hybrid.Hamiltonian(n, dtype, terms, coeff, {"tile_bits": tb, "low_bits": lb, "variant": var})
     # LDS-staged passes hold a whole tile in LDS: at most 2^13 complex128 amplitudes
     h1 = hybrid.Hamiltonian(n, dtype, terms, coeff, {"tile_bits": min(tb, 13), "low_bits": lb, "variant": 1})
     e4, e1 = h4.expval(psi), h1.expval(psi)
