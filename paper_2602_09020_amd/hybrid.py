@@ -26,7 +26,7 @@ class Frame:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h:
+        if h and _c is not None:  # None once the interpreter tears modules down
             _c.cfh_frame_destroy(h)
             self.h = None
 
@@ -75,7 +75,7 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h:
+        if h and _c is not None:  # None once the interpreter tears modules down
             _c.cfh_plan_destroy(h)
             self.h = None
 
@@ -99,7 +99,7 @@ class Hamiltonian:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h:
+        if h and _c is not None:  # None once the interpreter tears modules down
             _c.cfh_ham_destroy(h)
             self.h = None
 
@@ -187,7 +187,7 @@ class Batch:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h:
+        if h and _c is not None:  # None once the interpreter tears modules down
             _c.cfh_batch_destroy(h)
             self.h = None
 
