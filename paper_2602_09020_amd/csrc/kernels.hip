@@ -1180,15 +1180,7 @@ cfh_status cfh_ham_create(int n, int dtype, const cfh_pauli *terms, const double
         h->args.push_back(a);
     }
     cfh_status st = CFH_OK;
-    if (!gdev.empty()) {
-        if (!hip_ok(hipMalloc(&h->groups, gdev.size() * sizeof(HamGroupDev)), "cfh_ham_create: hipMalloc", &st) ||
-            !hip_ok(hipMemcpy(h->groups, gdev.data(), gdev.size() * sizeof(HamGroupDev), hipMemcpyHostToDevice),
-                    "cfh_ham_create: hipMemcpy", &st) ||
-            !hip_ok(hipMalloc(&h->terms, tdev.size() * sizeof(HamTermDev)), "cfh_ham_create: hipMalloc", &st) ||
-            !hip_ok(hipMemcpy(h->terms, tdev.data(), tdev.size() * sizeof(HamTermDev), hipMemcpyHostToDevice),
-                    "cfh_ham_create: hipMemcpy", &st))
-            return st;
-    }
+    std::vector<double2> mw_host;  // weights of the register-tiled passes' terms
     // <H> on the register-tiled kernel: passes of at most kMaxRun terms on
     // 2^b tiles (half-tile transposes at 2^14), terms ordered so consecutive
     // ones share register micro-groups.  The LDS-staged passes above stay for
@@ -1212,19 +1204,32 @@ cfh_status cfh_ham_create(int n, int dtype, const cfh_pauli *terms, const double
             if (th.tile_bits < n) th.low_bits = std::min(th.low_bits, th.tile_bits - 1);
             st = term_passes(n, dtype, groups, tp, th, true, h->hargs, "cfh_ham_create");
             if (st) return st;
-            std::vector<double2> w(m);
+            mw_host.resize(m);
             for (size_t i = 0; i < m; ++i) {
                 const int wp = (terms[i].e - popc(terms[i].x & terms[i].z)) & 3;  // i^wp
-                w[i] = make_double2(wp == 0 ? coeff[i] : wp == 2 ? -coeff[i] : 0.0,
-                                    wp == 1 ? coeff[i] : wp == 3 ? -coeff[i] : 0.0);
+                mw_host[i] = make_double2(wp == 0 ? coeff[i] : wp == 2 ? -coeff[i] : 0.0,
+                                          wp == 1 ? coeff[i] : wp == 3 ? -coeff[i] : 0.0);
             }
-            if (!hip_ok(hipMalloc(&h->mw, m * sizeof(double2)), "cfh_ham_create: hipMalloc", &st) ||
-                !hip_ok(hipMemcpy(h->mw, w.data(), m * sizeof(double2), hipMemcpyHostToDevice),
-                        "cfh_ham_create: hipMemcpy", &st))
-                return st;
             h->mmode = anchor ? 14 : 10;
         }
     }
+    // Device calls come only after all host planning: hipMemcpy on the null
+    // stream waits for work already queued there, and planning done after it
+    // would leave the device idle.
+    if (!gdev.empty()) {
+        if (!hip_ok(hipMalloc(&h->groups, gdev.size() * sizeof(HamGroupDev)), "cfh_ham_create: hipMalloc", &st) ||
+            !hip_ok(hipMemcpy(h->groups, gdev.data(), gdev.size() * sizeof(HamGroupDev), hipMemcpyHostToDevice),
+                    "cfh_ham_create: hipMemcpy", &st) ||
+            !hip_ok(hipMalloc(&h->terms, tdev.size() * sizeof(HamTermDev)), "cfh_ham_create: hipMalloc", &st) ||
+            !hip_ok(hipMemcpy(h->terms, tdev.data(), tdev.size() * sizeof(HamTermDev), hipMemcpyHostToDevice),
+                    "cfh_ham_create: hipMemcpy", &st))
+            return st;
+    }
+    if (!mw_host.empty() &&
+        (!hip_ok(hipMalloc(&h->mw, m * sizeof(double2)), "cfh_ham_create: hipMalloc", &st) ||
+         !hip_ok(hipMemcpy(h->mw, mw_host.data(), m * sizeof(double2), hipMemcpyHostToDevice),
+                 "cfh_ham_create: hipMemcpy", &st)))
+        return st;
     h->grid = persistent_grid(1ull << (n - h->tu.tile_bits));
     const size_t np = std::max<size_t>(h->grid, cfh_ham_s::kMeasureGrid);
     if (!hip_ok(hipMalloc(&h->partial, np * sizeof(double2)), "cfh_ham_create: hipMalloc", &st)) return st;
