@@ -106,7 +106,9 @@ typedef struct cfh_tuning {
                               can keep a group resident across its levels); <= 0 = one group */
     int32_t tile_order;    /* register-tiled passes: 0 = cosets that share 128-byte lines (chunks
                               narrower than 128 B) run on the same XCD at the same time, so the line
-                              is fetched into one L2 once; 1 = cosets in index order */
+                              is fetched into one L2 once, and bit-reversed order otherwise;
+                              1 = cosets in index order; 2 = bit-reversed coset index (workgroups
+                              running together are spread over the whole state) */
 } cfh_tuning;
 
 typedef struct cfh_frame_s *cfh_frame;

@@ -112,7 +112,7 @@ struct PassArgs2 {
     int32_t nmg;
     int32_t inverse;                 // negate angles (order already reversed on the host)
     int32_t qbit;                    // anchor pivot bit (register dim 0 of every micro-group), -1 = none
-    int32_t xrot;                    // p: the 2^p cosets sharing a 128-byte line go to one XCD (0 = index order)
+    int32_t xrot;                    // p > 0: the 2^p cosets sharing a 128-byte line go to one XCD; 0 = index order; -1 = bit-reversed
     int32_t pad;
     MGDesc2 mg[kMaxMG];
     RotDesc2 rot[kMaxRun];
@@ -156,10 +156,11 @@ struct TuningResolved {
 enum { kTuneForward = 0, kTuneAdjoint = 1, kTuneHamiltonian = 2, kTuneMeasure = 3, kTuneAdjoint2 = 4 };
 TuningResolved resolve_tuning(const cfh_tuning *t, int n, int dtype, int kind);
 
-// Number p of low coset-index bits that address amplitudes inside one 128-byte
-// line (the outer bits below the line size), for the XCD-aware coset order; 0
-// when the tiles use whole lines, when tile_order asks for index order, or
-// when there are fewer than 8 * 2^p cosets.
+// Coset order of a register-tiled pass.  p > 0: the number of low coset-index
+// bits that address amplitudes inside one 128-byte line (the outer bits below
+// the line size), for the XCD-aware order.  -1 (bit-reversed coset index) when
+// the tiles use whole lines or there are fewer than 8 * 2^p cosets, or when
+// tile_order is 2.  0 (index order) when tile_order is 1.
 int line_share_bits(uint64_t outer_mask, int n, int b, int amp_bytes, int tile_order);
 
 // Builds the passes of a rotation sequence (the fusion planner).

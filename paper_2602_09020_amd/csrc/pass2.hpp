@@ -202,9 +202,15 @@ __device__ __forceinline__ void measure_dispatch(uint32_t cx, uint32_t msign, co
 // lines differ only in their low p index bits; they get loop indices 8 apart,
 // so each line is filled into that XCD's L2 once and written back whole.
 // Needs 8 * 2^p <= ntiles (both powers of two): then this is a permutation.
-__device__ __forceinline__ uint64_t coset_of(uint64_t t, int p)
+__device__ __forceinline__ uint64_t coset_of(uint64_t t, int p, uint64_t ntiles)
 {
     if (p == 0) return t;
+    if (p < 0) {
+        // bit-reversed order: workgroups running at the same time are spread
+        // over the whole state (ntiles is a power of two)
+        const int lg = 63 - __builtin_clzll(ntiles);
+        return lg == 0 ? t : (__brevll(t) >> (64 - lg));
+    }
     const uint64_t m = (8ull << p) - 1, lo = t & m;
     return (t & ~m) | ((lo & 7) << p) | (lo >> 3);
 }
@@ -286,7 +292,7 @@ k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2
     Amp pf[kRegs];
     uint64_t tile = blockIdx.x;
     if (PF && tile < ntiles) {
-        const uint64_t y0 = deposit(coset_of(tile, args.xrot), args.outer_mask) ^ Lb0;
+        const uint64_t y0 = deposit(coset_of(tile, args.xrot, ntiles), args.outer_mask) ^ Lb0;
 #pragma unroll
         for (int j = 0; j < kRegs; ++j) pf[j] = psi[y0 ^ args.LU_first[j]];
     }
@@ -295,14 +301,14 @@ k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2
         // keep the 2 x 16 per-register address terms from being hoisted out of
         // the loop as 64 live VGPRs: recomputing them is two scalar-operand XORs
         asm volatile("" : "+v"(Lb0), "+v"(LbL));
-        const uint64_t tb = deposit(coset_of(tile, args.xrot), args.outer_mask);
+        const uint64_t tb = deposit(coset_of(tile, args.xrot, ntiles), args.outer_mask);
         double2 r[kRegs];
         if (PF) {
 #pragma unroll
             for (int j = 0; j < kRegs; ++j) r[j] = ld(pf[j]);
             const uint64_t nt = tile + gridDim.x;
             if (nt < ntiles) {
-                const uint64_t y0 = deposit(coset_of(nt, args.xrot), args.outer_mask) ^ Lb0;
+                const uint64_t y0 = deposit(coset_of(nt, args.xrot, ntiles), args.outer_mask) ^ Lb0;
 #pragma unroll
                 for (int j = 0; j < kRegs; ++j) pf[j] = psi[y0 ^ args.LU_first[j]];
             }
@@ -506,7 +512,7 @@ k_adj2(Amp *__restrict__ psi, Amp *__restrict__ lam, const double2 *__restrict__
 #pragma unroll 1
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         asm volatile("" : "+v"(Lb0), "+v"(LbL));
-        const uint64_t tb = deposit(coset_of(tile, args.xrot), args.outer_mask);
+        const uint64_t tb = deposit(coset_of(tile, args.xrot, ntiles), args.outer_mask);
         double2 p[kRegs], l[kRegs];
         {
             const uint64_t y0 = tb ^ Lb0;
@@ -657,7 +663,7 @@ k_ham2(const Amp *__restrict__ psi, Amp *__restrict__ lam, const double2 *__rest
 #pragma unroll 1
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         asm volatile("" : "+v"(Lb0), "+v"(LbL));
-        const uint64_t tb = deposit(coset_of(tile, args.xrot), args.outer_mask);
+        const uint64_t tb = deposit(coset_of(tile, args.xrot, ntiles), args.outer_mask);
         double2 p[kRegs], l[kRegs];
         {
             const uint64_t y0 = tb ^ Lb0;

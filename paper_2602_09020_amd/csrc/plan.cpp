@@ -148,11 +148,14 @@ RotDesc make_rot_desc(const PassPlan &pp, const Pauli &p, int k)
 
 int line_share_bits(uint64_t outer_mask, int n, int b, int amp_bytes, int tile_order)
 {
-    if (tile_order != 0) return 0;
+    if (tile_order == 1) return 0;   // index order
+    if (tile_order == 2) return -1;  // bit-reversed order
     const int line_amps = 128 / amp_bytes;
     const int p = popc(outer_mask & (uint64_t)(line_amps - 1));
-    // the cosets of a line group and the 8 XCDs must tile the coset range
-    if (p == 0 || n - b < 3 + p) return 0;
+    // the cosets of a line group and the 8 XCDs must tile the coset range;
+    // otherwise bit-reversed (measured 1.3% faster per complex128 pass at
+    // 28 qubits than index order, equal at complex64)
+    if (p == 0 || n - b < 3 + p) return -1;
     return p;
 }
 

@@ -486,14 +486,16 @@ def test_config1_n24_prefix_vs_ladder_oracle():
 
 @pytest.mark.parametrize("dtype,n,tb,lb", [(torch.complex128, 16, 10, 1), (torch.complex128, 16, 10, 2),
                                            (torch.complex128, 17, 14, 2), (torch.complex64, 16, 10, 2),
-                                           (torch.complex64, 16, 11, 3)])
+                                           (torch.complex64, 16, 11, 3), (torch.complex128, 17, 12, 3),
+                                           (torch.complex64, 17, 13, 4)])
 def test_xcd_coset_order_vs_oracle_and_index_order(dtype, n, tb, lb):
-    """Chunks narrower than a 128-byte line: the default coset order (the cosets
-    sharing a line run on one XCD) gives the oracle's state, the same state bit
-    for bit as index order, and the same <H> and gradients within rounding."""
+    """The default coset order (cosets sharing a line on one XCD when chunks are
+    narrower than a 128-byte line, bit-reversed otherwise) gives the oracle's
+    state, the same state bit for bit as index order and as the bit-reversed
+    order, and the same <H> and gradients within rounding."""
     w = W.make_workload("xcd", n, seed=n + lb, n_prefix=2 * n, n_rot=160, n_ham=80)
     out = {}
-    for order in (0, 1):
+    for order in (0, 1, 2):
         tu = {"tile_bits": tb, "low_bits": lb, "tile_order": order}
         frame, rot, terms, plan, ham = hybrid.prepare(w, dtype, tu, tu)
         psi = hybrid.new_state(n, dtype, index=w.init)
@@ -508,12 +510,14 @@ def test_xcd_coset_order_vs_oracle_and_index_order(dtype, n, tb, lb):
         out[order] = (fwd, e, grad.cpu().numpy())
     _, phi_ref = sim.simulate(w)
     assert maxdiff(out[0][0], phi_ref) <= TOL[dtype]
-    assert torch.equal(out[0][0], out[1][0])
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][0], out[2][0])
     scale = np.abs(w.coeff).sum()
     tol = (1e-12 if dtype == torch.complex128 else 1e-4) * scale
     ref_psi, _ = sim.simulate(w)
     assert abs(out[0][1].real - sim.energy(ref_psi, n, w.ham, w.coeff)) <= tol
-    assert np.abs(out[0][2] - out[1][2]).max() <= (1e-11 if dtype == torch.complex128 else 2e-3) * max(1.0, scale)
+    for order in (1, 2):
+        assert abs(out[0][1] - out[order][1]) <= tol
+        assert np.abs(out[0][2] - out[order][2]).max() <= (1e-11 if dtype == torch.complex128 else 2e-3) * max(1.0, scale)
 
 
 # ------------------------------------------------------------- frame flush
