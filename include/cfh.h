@@ -379,8 +379,8 @@ typedef struct cfh_circuit_desc {
  * circuits, and every circuit under variant 2, use LDS-staged passes on tiles
  * of 2^min(n, tile_bits) amplitudes (default 2^10) only.  Passes are cut
  * into at most tuning->batch_items work items each and queued level by level
- * across circuits.  States, angles, gradients, partial sums and the queue
- * live in one library-owned device allocation.  tuning may be NULL.
+ * across circuits.  States, angles, gradients, partial sums and the
+ * work-item tables live in one library-owned device allocation.  tuning may be NULL.
  * Errors: CFH_E_INVAL, CFH_E_RANGE, CFH_E_NOT_HERMITIAN, CFH_E_UNSUPPORTED
  * (n outside 8..30, tile_bits outside 8..11 for c128 or 8..12 for c64,
  * variant other than 0 or 2), CFH_E_NOMEM, CFH_E_HIP. */
@@ -400,13 +400,20 @@ cfh_status cfh_batch_set_theta(cfh_batch b, const double *theta_host);
 
 /* Run every circuit: build its initial state, apply its rotations, reduce
  * its energy E_i = <psi_i|H_i|psi_i> (Eq. chfsexp) and, with with_grad = 1,
- * its adjoint gradient dE_i/dtheta, in ONE persistent kernel launch that
- * pops (circuit, pass, coset range) items from a device queue (plus two tiny
- * set-up kernels: counter reset and angle tables).  Asynchronous; allocates
- * nothing and calls no memset, so it can be captured in a hipGraph.  Runs on
- * one batch must not overlap in time.  A pass that waits too long for its
- * predecessor makes every workgroup stop; cfh_batch_results then reports
- * CFH_E_HIP. */
+ * its adjoint gradient dE_i/dtheta.  Every circuit is a chain of passes;
+ * level l holds pass l of every circuit whose chain is that long.  The call
+ * enqueues on `stream`, in order: a kernel that clears the per-circuit
+ * timestamps, a kernel that turns the angles into (cos, sin) tables, then
+ * for each level one launch per kernel kind that has items at that level
+ * (register-tiled forward, measurement, H psi and adjoint passes; LDS-staged
+ * passes), followed by one launch that reduces the level's per-item partial
+ * sums in a fixed order.  Kernel boundaries order the levels: no workgroup
+ * waits for another, and there is no device queue and no time-out.
+ * Asynchronous; allocates nothing and calls no memset, so it can be captured
+ * in a hipGraph (cfh_batch_graph_launch).  Runs on one batch must not overlap
+ * in time, since they share its device buffers.  Errors: CFH_E_INVAL (null
+ * batch), CFH_E_UNSUPPORTED (a tile size the kernels were not built for),
+ * CFH_E_HIP (a launch failed; the message is in cfh_last_error). */
 cfh_status cfh_batch_run(cfh_batch b, int with_grad, void *stream);
 
 /* Capture cfh_batch_run(b, with_grad) into a hipGraph on the first call for

@@ -1,5 +1,6 @@
-"""GPU tests of the batched persistent path (cfh_batch_*) against the oracle
-and against the single-circuit path, including hipGraph replays."""
+"""GPU tests of the batched path (cfh_batch_*: level-synchronous launches, one
+per kernel kind and level) against the oracle and against the single-circuit
+path, including hipGraph replays."""
 import numpy as np
 import pytest
 import torch

@@ -330,6 +330,50 @@ def test_expval_equals_dense():
         assert abs(sim.expval(psi, n, letters, ph) - np.vdot(psi, dense.pauli(letters, ph) @ psi)) < 1e-13
 
 
+@pytest.mark.parametrize("n", [1, 3, 5])
+def test_apply_pauli_sum_equals_dense_weighted_sum(n):
+    """Sec. 4.4, Eq. chfsexp with H = sum_j c_j i^{ph_j} P_j: the oracle's H psi
+    against the dense sum of explicit Kronecker products, several terms at once,
+    random real weights and every phase.  A dropped or mis-indexed weight, a
+    wrong power of i or a lost accumulation across terms changes the result."""
+    rng = np.random.default_rng(300 + n)
+    psi = rand_state(n, rng)
+    m = 7
+    letters = rng.integers(0, 4, size=(m, n)).astype(np.uint8)
+    coeff = rng.normal(size=m)
+    phases = np.array([j % 4 for j in range(m)], np.int32)
+    rng.shuffle(phases)
+    dense_h = sum(c * dense.pauli(l, int(p)) for l, c, p in zip(letters, coeff, phases))
+    out = sim.apply_pauli_sum(psi, n, letters, coeff, phases)
+    assert np.abs(out - dense_h @ psi).max() < 1e-13
+    # without phases every term is c_j P_j
+    dense_0 = sum(c * dense.pauli(l) for l, c in zip(letters, coeff))
+    assert np.abs(sim.apply_pauli_sum(psi, n, letters, coeff) - dense_0 @ psi).max() < 1e-13
+    # linear in the weights: doubling one term's weight adds exactly that term once more
+    c2 = coeff.copy()
+    c2[3] *= 2
+    extra = coeff[3] * dense.pauli(letters[3], int(phases[3])) @ psi
+    assert np.abs(sim.apply_pauli_sum(psi, n, letters, c2, phases) - (dense_h @ psi + extra)).max() < 1e-13
+
+
+def test_energy_with_phases_equals_dense():
+    """E = sum_j c_j Re <psi| i^{ph_j} P_j |psi> against the dense quadratic form,
+    with phases 1 and 3 (anti-Hermitian terms contribute Re of an imaginary
+    number only through their Y and sign content) and several weighted terms."""
+    n = 4
+    rng = np.random.default_rng(77)
+    psi = rand_state(n, rng)
+    m = 9
+    letters = rng.integers(0, 4, size=(m, n)).astype(np.uint8)
+    coeff = rng.normal(size=m)
+    phases = rng.integers(0, 4, size=m).astype(np.int32)
+    want = sum(c * np.vdot(psi, dense.pauli(l, int(p)) @ psi).real for l, c, p in zip(letters, coeff, phases))
+    assert abs(sim.energy(psi, n, letters, coeff, phases) - want) < 1e-13
+    # the energy of a sum is the real part of <psi|H psi> built from the weighted sum
+    hpsi = sim.apply_pauli_sum(psi, n, letters, coeff, phases)
+    assert abs(np.vdot(psi, hpsi).real - want) < 1e-13
+
+
 def test_expval_through_frame_equation():
     """Eq. chfsexp: <psi|P|psi> = <Phi|F(P)|Phi> with psi = C Phi and F(P) = C^dag P C."""
     w = W.config(0)
