@@ -55,6 +55,35 @@ def counter_traffic(name: str, kernel: str):
     return d.get("traffic_bytes_per_launch")
 
 
+def measure_ceilings(buf, n, reps=5):
+    """HBM rates of the library's calibration kernel on a state-sized buffer
+    (its contents are overwritten): in-place read-modify-write streamed in
+    index order, and in 128-byte runs scattered over the buffer (the access
+    pattern of a fused pass with 128-byte contiguous tile chunks); each with
+    ordinary and nontemporal accesses.  GB/s of algorithmic bytes
+    (read + write of every amplitude)."""
+    import torch
+    from paper_2602_09020_amd import cfh
+    amp_b = 16 if buf.dtype == torch.complex128 else 8
+    nbytes = 2.0 * (1 << n) * amp_b
+    line_bits = {16: 3, 8: 4}[amp_b]
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, cb, nt in (("stream_rmw", -1, False), ("stream_rmw_nontemporal", -1, True),
+                         ("scatter128_rmw", line_bits, False), ("scatter128_rmw_nontemporal", line_bits, True),
+                         ("scatter256_rmw", line_bits + 1, False), ("scatter512_rmw", line_bits + 2, False)):
+        cfh.cfh_calib_rmw(buf, n, cb, nt)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            cfh.cfh_calib_rmw(buf, n, cb, nt)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        out[name + "_gbs"] = nbytes / (ms * 1e-3) / 1e9
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,10 +93,11 @@ def main():
     ap.add_argument("--trotter-steps", type=int, default=10)
     ap.add_argument("--no-extras", action="store_true", help="skip unfused/c64/adjoint/cpu legs")
     ap.add_argument("--cpu-rotations", type=int, default=20)
-    ap.add_argument("--mode", choices=["full", "passes", "expval", "copy"], default="full",
+    ap.add_argument("--mode", choices=["full", "passes", "expval", "copy", "stream"], default="full",
                     help="passes: apply the plan of the first --rotations rotations once (for counter runs); "
                          "expval: those rotations, then <H> of the workload's observable --steps times; "
-                         "copy: a plain device copy of the same state size (counter and bandwidth calibration)")
+                         "copy: a plain device copy of the same state size (counter and bandwidth calibration); "
+                         "stream: the library's in-place calibration kernel, streamed and in scattered chunks")
     ap.add_argument("--rotations", type=int, default=150)
     ap.add_argument("--chunk", type=int, default=2000, help="rotations planned per plan inside a step")
     ap.add_argument("--dtype", choices=["c128", "c64"], default="c128", help="state storage for --mode passes")
@@ -88,6 +118,12 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.mode == "stream":
+        sdt = torch.complex128 if args.dtype == "c128" else torch.complex64
+        buf = torch.zeros(1 << args.n, dtype=sdt, device=dev)
+        print(json.dumps({"mode": "stream", "n": args.n, "dtype": args.dtype, "peak_gbs": HBM_PEAK_GBS,
+                          **measure_ceilings(buf, args.n)}), flush=True)
+        return
     if args.mode == "copy":
         # read 2^n * 16 bytes, write as many: the traffic of one fused pass
         src = torch.ones((1 << args.n) * 2, dtype=torch.float64, device=dev)
@@ -176,6 +212,7 @@ def main():
         d.record(stream)
         return plans, ham, (a, b, c, d)
 
+    ceilings = measure_ceilings(psi, n)  # psi is reset at the start of every step
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -230,7 +267,12 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kname,
-                     "bytes_per_launch": pass_bytes, "avg_launch_ms": pass_ms},
+                     "bytes_per_launch": pass_bytes, "avg_launch_ms": pass_ms,
+                     "ceilings_measured_gbs": ceilings,
+                     "frac_of_stream_ceiling": achieved_gbs / max(ceilings["stream_rmw_gbs"],
+                                                                  ceilings["stream_rmw_nontemporal_gbs"]),
+                     "frac_of_scatter128_ceiling": achieved_gbs / max(ceilings["scatter128_rmw_gbs"],
+                                                                      ceilings["scatter128_rmw_nontemporal_gbs"])},
         "passes": launches,
         "fusion_depth": K / launches,
         "rotation_phase_ms": float(np.mean(rot_ms)),

@@ -226,6 +226,17 @@ cfh_status cfh_plan_info(cfh_plan p, int64_t *n_passes, int64_t *n_rot, int32_t 
  * offsets into order), order has m rotation indices in application order. */
 cfh_status cfh_plan_schedule(cfh_plan p, int64_t *pass_start, int64_t *order);
 
+/* Coverage of the compile-time rotation bodies (for tests): counts[512]
+ * gets, for each body of the register-tiled pass kernel, how many rotations
+ * of the plan's passes (inverse = 0: forward order, 1: the inverse sweep)
+ * run it with the angles theta_host (host, m entries).  Body index =
+ * cx | zr << 4 | tangent << 8: the partner mask and the register sign mask
+ * in register coordinates (they also fix whether the pair coefficient is
+ * imaginary), and the tangent form (taken when |sin(theta/2)| <=
+ * |cos(theta/2)| and the plan's kernel has it).  Host only.  Errors:
+ * CFH_E_INVAL (null), CFH_E_UNSUPPORTED (an unfused or LDS-staged plan). */
+cfh_status cfh_plan_leaf_counts(cfh_plan p, const double *theta_host, int inverse, int64_t *counts);
+
 /* psi <- R_{m-1} ... R_0 psi with R_k = exp(-i theta_dev[k]/2 rot[k])
  * (inverse = 0), or the inverse product R_0^dag ... R_{m-1}^dag psi
  * (inverse = 1).  theta_dev: device array of m doubles.  Allocates nothing
@@ -352,6 +363,20 @@ cfh_status cfh_measure_pauli(void *psi, int n, int dtype, const cfh_pauli *p, do
  * cfh_measure_pauli, CFH_E_HIP. */
 cfh_status cfh_circuit_run(cfh_frame f, const int32_t *gates, const double *angles, size_t m, void *psi, int dtype,
                            const cfh_tuning *tuning, int32_t *outcomes, void *stream);
+
+/* ------------------------------------------------ roofline calibration */
+
+/* Calibration of the HBM roofline (not part of the method): every amplitude
+ * of buf (device memory, 2^n amplitudes of dtype, caller-owned scratch;
+ * 8 <= n <= 34) is read once, multiplied by a fixed unit phase and written
+ * back, one amplitude per thread.  chunk_bits = -1 streams the buffer in index
+ * order; chunk_bits = c >= 0 keeps runs of 2^c contiguous amplitudes and
+ * bit-reverses the index bits above them, so consecutive runs land far
+ * apart (the access pattern of a fused pass whose tile has c contiguous low
+ * bits).  nontemporal = 1 uses nontemporal loads and stores.  The HBM bytes
+ * are 2 * 2^n * (bytes per amplitude).  Asynchronous on `stream`.
+ * Errors: CFH_E_INVAL, CFH_E_UNSUPPORTED, CFH_E_HIP. */
+cfh_status cfh_calib_rmw(void *buf, int n, int dtype, int chunk_bits, int nontemporal, void *stream);
 
 /* ----------------------------------------------- a10: batched circuits */
 

@@ -99,13 +99,15 @@ def measure_pauli(psi: np.ndarray, n: int, letters: np.ndarray, u: float, phase:
     return s, p_plus
 
 
-def apply_circuit(psi: np.ndarray, n: int, gates: np.ndarray, angles: np.ndarray) -> np.ndarray:
+def apply_circuit(psi: np.ndarray, n: int, gates: np.ndarray, angles: np.ndarray,
+                  probs: Optional[list] = None) -> np.ndarray:
     """In place, gate by gate: Clifford rows as apply_gate, rows 9/10/11 as the
     one-qubit rotations exp(-i theta/2 X_q / Y_q / Z_q), row 12 a Z_q
     measurement and row 13 a reset to |0> (measure, then X_q on -1), both with
     the row's angle as their uniform number (the gate-level simulation a
     circuit simulator performs, with no frame).  Returns the outcomes (+1/-1
-    at measurement and reset rows, else 0)."""
+    at measurement and reset rows, else 0); ``probs``, if given, receives the
+    probability P(s) of each outcome drawn, in row order."""
     g = np.ascontiguousarray(gates, dtype=np.int32).reshape(-1, 3)
     out = np.zeros(g.shape[0], np.int32)
     for i, ((code, q0, q1), th) in enumerate(zip(g, np.asarray(angles, np.float64))):
@@ -114,7 +116,9 @@ def apply_circuit(psi: np.ndarray, n: int, gates: np.ndarray, angles: np.ndarray
             letters[q0] = {9: 1, 10: 2, 11: 3}[int(code)]
             rotation(psi, n, letters, float(th))
         elif code in (12, 13):
-            out[i], _ = measure_z(psi, n, int(q0), float(th))
+            out[i], p_plus = measure_z(psi, n, int(q0), float(th))
+            if probs is not None:
+                probs.append(p_plus if out[i] > 0 else 1.0 - p_plus)
             if code == 13 and out[i] < 0:
                 apply_gate(psi, n, 3, int(q0), -1)
         else:

@@ -7,7 +7,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libcfh.so")
-SOURCES = ["frame.cpp", "plan.cpp", "kernels.hip", "pass2_c128.hip", "pass2_c64.hip", "batch.hip", "batch2.hip"]
+SOURCES = ["frame.cpp", "plan.cpp", "kernels.hip", "pass2_c128.hip", "pass2_c64.hip", "batch.hip", "batch2.hip",
+           "calib.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -83,6 +83,7 @@ _SIGS = {
     "cfh_plan_info": (C.c_int32, [_vp, _P(C.c_int64), _P(C.c_int64), _P(C.c_int32), _P(C.c_double),
                                   _P(C.c_int32)]),
     "cfh_plan_schedule": (C.c_int32, [_vp, _vp, _vp]),
+    "cfh_plan_leaf_counts": (C.c_int32, [_vp, _vp, C.c_int, _vp]),
     "cfh_apply_plan": (C.c_int32, [_vp, _vp, _vp, C.c_int, _vp]),
     "cfh_ham_create": (C.c_int32, [C.c_int, C.c_int, _vp, _vp, C.c_size_t, _P(cfh_tuning), _P(_vp)]),
     "cfh_ham_destroy": (C.c_int32, [_vp]),
@@ -91,6 +92,7 @@ _SIGS = {
     "cfh_expval": (C.c_int32, [_vp, C.c_int, C.c_int, _vp, _vp, C.c_size_t, _vp, _vp]),
     "cfh_ham_apply": (C.c_int32, [_vp, _vp, _vp, _vp]),
     "cfh_adjoint_grad": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "cfh_calib_rmw": (C.c_int32, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, _vp]),
     "cfh_batch_create": (C.c_int32, [_vp, C.c_int, C.c_int, _P(cfh_tuning), _P(_vp)]),
     "cfh_batch_destroy": (C.c_int32, [_vp]),
     "cfh_batch_info": (C.c_int32, [_vp, _P(C.c_int64), _P(C.c_int64), _P(C.c_int64), _P(C.c_double),
@@ -348,6 +350,13 @@ def cfh_plan_schedule(p: int, m: int, n_passes: int):
     return ps, order
 
 
+def cfh_plan_leaf_counts(p: int, theta: np.ndarray, inverse: bool = False) -> np.ndarray:
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    out = np.zeros(512, np.int64)
+    _call("cfh_plan_leaf_counts", p, th.ctypes.data, int(bool(inverse)), out.ctypes.data)
+    return out
+
+
 def cfh_apply_plan(p: int, psi, theta_dev, inverse: bool = False, stream=None) -> None:
     _call("cfh_apply_plan", p, _dev_ptr(psi, "psi"), _dev_ptr(theta_dev, "theta"), int(bool(inverse)),
           _stream(stream))
@@ -388,6 +397,11 @@ def cfh_expval(psi, n: int, terms: np.ndarray, coeff: np.ndarray, stream=None) -
     _call("cfh_expval", _dev_ptr(psi, "psi"), n, _dtype_code(psi), a.ctypes.data, c.ctypes.data, a.shape[0],
           out.ctypes.data, _stream(stream))
     return complex(out[0], out[1])
+
+
+def cfh_calib_rmw(buf, n: int, chunk_bits: int = -1, nontemporal: bool = False, stream=None) -> None:
+    _call("cfh_calib_rmw", _dev_ptr(buf, "buf"), n, _dtype_code(buf), int(chunk_bits), int(bool(nontemporal)),
+          _stream(stream))
 
 
 def cfh_ham_apply(h: int, psi, out, stream=None) -> None:

@@ -100,7 +100,7 @@ k_batch_fwd2(const BatchArgs A, const PassArgs2 *__restrict__ pa, const BItem *_
                 const RotDesc2 &d = args.rot[ri];
                 const double2 cs = tab[ri];
                 const uint32_t sg = ((tsb >> ri) ^ (uint32_t)par64(tb & d.z)) & 1u;
-                kase_dispatch<8, 0>(d.kase, r, cs.x, flip_if(cs.y, sg));
+                kase_dispatch<7, 0>(d.kase & 255u, r, cs.x, flip_if(cs.y, sg));
             }
         }
         const uint64_t yL = tb ^ LbL;
@@ -309,7 +309,7 @@ k_batch_meas2(const BatchArgs A, const PassArgs2 *__restrict__ pa, const BItem *
                 const RotDesc2 &d = args.rot[ri];
                 const double2 w = tab[ri];
                 const uint32_t sg = ((tsb >> ri) ^ (uint32_t)par64(tb & d.z)) & 1u;
-                measure_dispatch<3, 0>(d.cx, d.msign, r, flip_if(w.x, sg), flip_if(w.y, sg), accr, acci);
+                meas_dispatch<7, 0>(d.kase & 255u, r, flip_if(w.x, sg), flip_if(w.y, sg), accr, acci);
             }
         }
     }

@@ -1066,6 +1066,27 @@ cfh_status cfh_plan_schedule(cfh_plan p, int64_t *pass_start, int64_t *order)
     return CFH_OK;
 }
 
+cfh_status cfh_plan_leaf_counts(cfh_plan p, const double *theta_host, int inverse, int64_t *counts)
+{
+    if (!p || !counts || (!theta_host && !p->rot.empty()))
+        return set_error(CFH_E_INVAL, "cfh_plan_leaf_counts: null argument");
+    if (p->tu.unfused || !(p->mode2 & 2) || p->args2.size() != p->passes.size())
+        return set_error(CFH_E_UNSUPPORTED, "cfh_plan_leaf_counts: the plan does not run the compile-time bodies");
+    std::fill(counts, counts + 512, (int64_t)0);
+    const bool tanf = (p->mode2 & 16) != 0;
+    for (const PassArgs2 &a : inverse ? p->args2_inv : p->args2) {
+        const int nrot = a.mg[a.nmg - 1].rot_begin + a.mg[a.nmg - 1].rot_count;
+        for (int ri = 0; ri < nrot; ++ri) {
+            const RotDesc2 &d = a.rot[ri];
+            const double th = theta_host[d.k];
+            // the kernel's test on (cos, sin) of theta/2, which sign flips do not change
+            const bool tan = tanf && std::fabs(std::sin(0.5 * th)) <= std::fabs(std::cos(0.5 * th));
+            ++counts[(d.kase & 255u) | (tan ? 256u : 0u)];
+        }
+    }
+    return CFH_OK;
+}
+
 cfh_status cfh_apply_plan(cfh_plan p, void *psi, const double *theta_dev, int inverse, void *stream)
 {
     if (!p || !psi || (!theta_dev && !p->rot.empty())) return set_error(CFH_E_INVAL, "cfh_apply_plan: null argument");

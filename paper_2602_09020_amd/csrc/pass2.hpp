@@ -89,10 +89,14 @@ __device__ __forceinline__ void mg_dispatch(int cx, double2 (&r)[kRegs], double 
     }
 }
 
-// Compile-time rotation bodies.  KASE = cx | zr << 4 | imag << 8 fixes the
-// partner mask and every register's sign (the sign of register j is
-// parity(j & zr), since the register offsets are spanned by four vectors), so
-// the signs become negations of FMA operands instead of sign arithmetic.
+// Compile-time rotation bodies.  KASE = cx | zr << 4 fixes the partner mask
+// and every register's sign (the sign of register j is parity(j & zr), since
+// the register offsets are spanned by four vectors), so the signs become
+// negations of FMA operands instead of sign arithmetic.  For a Hermitian
+// rotation the pair coefficient is imaginary exactly when |x & z| is even,
+// and |x & z| = parity(cx & zr) in register coordinates, so KASE also fixes
+// real/imaginary: 256 bodies cover every rotation the planner emits (the
+// planner checks the relation for each descriptor).
 constexpr bool cpar(int v) { return __builtin_popcount(v) & 1; }
 
 // TAN: the tangent form of the same update, c(u + t sigma beta v) with
@@ -104,21 +108,13 @@ __device__ __forceinline__ void kase_body(double2 (&r)[kRegs], double c_in, doub
 {
     const double c = TAN ? 1.0 : c_in;
     constexpr int CX = KASE & 15, ZR = (KASE >> 4) & 15;
-    constexpr bool IMAG = (KASE >> 8) & 1;
+    constexpr bool IMAG = CX == 0 || !cpar(CX & ZR);
     if constexpr (CX == 0) {
-        if constexpr (IMAG) {
+        // x = 0: exp(-i theta/2 P) is a phase on every amplitude
 #pragma unroll
-            for (int j = 0; j < kRegs; ++j) {
-                const double sj = cpar(j & ZR) ? -s : s;
-                r[j] = make_double2(c * r[j].x - sj * r[j].y, c * r[j].y + sj * r[j].x);
-            }
-        } else {
-            const double cp = c + s, cm = c - s;
-#pragma unroll
-            for (int j = 0; j < kRegs; ++j) {
-                const double f = cpar(j & ZR) ? cm : cp;
-                r[j] = make_double2(f * r[j].x, f * r[j].y);
-            }
+        for (int j = 0; j < kRegs; ++j) {
+            const double sj = cpar(j & ZR) ? -s : s;
+            r[j] = make_double2(c * r[j].x - sj * r[j].y, c * r[j].y + sj * r[j].x);
         }
     } else {
 #pragma unroll
@@ -131,7 +127,7 @@ __device__ __forceinline__ void kase_body(double2 (&r)[kRegs], double c_in, doub
     }
 }
 
-// Uniform branch tree over the nine bits of kase (one leaf per body).
+// Uniform branch tree over the eight bits of cx | zr << 4 (one leaf per body).
 template <int BIT, int ACC, bool TAN = false>
 __device__ __forceinline__ void kase_dispatch(uint32_t kase, double2 (&r)[kRegs], double c, double s)
 {
@@ -145,53 +141,78 @@ __device__ __forceinline__ void kase_dispatch(uint32_t kase, double2 (&r)[kRegs]
     }
 }
 
-// Read-only term bodies (expectation values).  For a term with partner mask CX
-// the thread's share of
+// Read-only term bodies (expectation values).  For a term with partner mask
+// CX and register sign mask ZR (the sign of register j is
+// sigma_j = (-1)^{parity(j & ZR)}, as for the rotation bodies) the thread's
+// share of
 //   sum_y (-1)^{|y & z|} conj(psi_y) psi_{y ^ x}
-// is (thread and coset sign) * S, S = sum_j sigma_j conj(r_j) r_{j^CX} with
-// sigma_j = (-1)^{msign_j}.  The members j and j^CX of a pair give conjugate
-// products, so S = 2 sum_{j<j^CX} sigma_j Re(conj(r_j) r_{j^CX}) when
-// sigma_CX = +1 (sigma_0 = +1, so sigma_{j^CX} = sigma_j sigma_CX) and
-// 2i sum sigma_j Im(...) when sigma_CX = -1.  Only CX selects a body (16); the
-// register signs are sign-bit flips taken from the uniform msign.
-template <int CX>
-__device__ __forceinline__ void measure_cx(uint32_t msign, const double2 (&r)[kRegs], double wre, double wim,
-                                           double &accr, double &acci)
+// is (thread and coset sign) * S, S = sum_j sigma_j conj(r_j) r_{j^CX}.  The
+// members j and j^CX of a pair give conjugate products, and
+// sigma_{j^CX} = sigma_j sigma_CX, so S = 2 sum_{j<j^CX} sigma_j Re(conj(r_j) r_{j^CX})
+// when sigma_CX = +1 and 2i sum sigma_j Im(...) when sigma_CX = -1; for
+// CX = 0, S = sum_j sigma_j |r_j|^2.  With ZR fixed at compile time every sign
+// is an FMA operand negation: a pair costs two FMAs, accumulated into two
+// independent partial sums.
+template <int KM>
+__device__ __forceinline__ void meas_body(const double2 (&r)[kRegs], double wre, double wim, double &accr,
+                                          double &acci)
 {
-    double sum = 0.0;
+    constexpr int CX = KM & 15, ZR = (KM >> 4) & 15;
+    // a side effect: keeps the leaf from being if-converted into selects with its siblings
+    asm volatile("");
+    double acc[2] = {0.0, 0.0};
     if constexpr (CX == 0) {
 #pragma unroll
-        for (int j = 0; j < kRegs; ++j) sum += flip_if(r[j].x * r[j].x + r[j].y * r[j].y, msign >> j);
-        accr += wre * sum;
-        acci += wim * sum;
-    } else if ((msign >> CX) & 1) {
-#pragma unroll
-        for (int j = 0; j < kRegs; ++j)
-            if ((j ^ CX) > j) sum += flip_if(r[j].x * r[j ^ CX].y - r[j].y * r[j ^ CX].x, msign >> j);
-        sum += sum;                 // value = w * (i * sum)
-        accr -= wim * sum;
-        acci += wre * sum;
+        for (int j = 0; j < kRegs; ++j) {
+            const double x = cpar(j & ZR) ? -r[j].x : r[j].x;
+            const double y = cpar(j & ZR) ? -r[j].y : r[j].y;
+            acc[j & 1] = fma(x, r[j].x, acc[j & 1]);
+            acc[j & 1] = fma(y, r[j].y, acc[j & 1]);
+        }
+        const double S = acc[0] + acc[1];
+        accr = fma(wre, S, accr);
+        acci = fma(wim, S, acci);
     } else {
+        constexpr bool IM = cpar(CX & ZR);
+        constexpr int LOW = CX & -CX;           // j runs over the pair members with this bit clear
+        constexpr int ALT = LOW == 1 ? 2 : 1;   // alternates over those members: two partial sums
 #pragma unroll
-        for (int j = 0; j < kRegs; ++j)
-            if ((j ^ CX) > j) sum += flip_if(r[j].x * r[j ^ CX].x + r[j].y * r[j ^ CX].y, msign >> j);
-        sum += sum;
-        accr += wre * sum;
-        acci += wim * sum;
+        for (int j = 0; j < kRegs; ++j) {
+            if (j & LOW) continue;
+            const double2 a = r[j], b = r[j ^ CX];
+            const bool neg = cpar(j & ZR);
+            double &t = acc[(j & ALT) ? 1 : 0];
+            if constexpr (IM) {
+                t = fma(neg ? -a.x : a.x, b.y, t);
+                t = fma(neg ? a.y : -a.y, b.x, t);
+            } else {
+                t = fma(neg ? -a.x : a.x, b.x, t);
+                t = fma(neg ? -a.y : a.y, b.y, t);
+            }
+        }
+        const double S = 2.0 * (acc[0] + acc[1]);
+        if constexpr (IM) {
+            accr = fma(-wim, S, accr);
+            acci = fma(wre, S, acci);
+        } else {
+            accr = fma(wre, S, accr);
+            acci = fma(wim, S, acci);
+        }
     }
 }
 
+// Uniform branch tree over the eight bits of cx | zr << 4 (one leaf per body).
 template <int BIT, int ACC>
-__device__ __forceinline__ void measure_dispatch(uint32_t cx, uint32_t msign, const double2 (&r)[kRegs], double wre,
-                                                 double wim, double &accr, double &acci)
+__device__ __forceinline__ void meas_dispatch(uint32_t km, const double2 (&r)[kRegs], double wre, double wim,
+                                              double &accr, double &acci)
 {
     if constexpr (BIT < 0) {
-        measure_cx<ACC>(msign, r, wre, wim, accr, acci);
+        meas_body<ACC>(r, wre, wim, accr, acci);
     } else {
-        if (cx & (1u << BIT))
-            measure_dispatch<BIT - 1, ACC | (1 << BIT)>(cx, msign, r, wre, wim, accr, acci);
+        if (km & (1u << BIT))
+            meas_dispatch<BIT - 1, ACC | (1 << BIT)>(km, r, wre, wim, accr, acci);
         else
-            measure_dispatch<BIT - 1, ACC>(cx, msign, r, wre, wim, accr, acci);
+            meas_dispatch<BIT - 1, ACC>(km, r, wre, wim, accr, acci);
     }
 }
 
@@ -358,7 +379,7 @@ k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2
                     const RotDesc2 &d = args.rot[ri];
                     const double2 w = tab[ri];
                     const uint32_t sg = ((tsb >> ri) ^ (uint32_t)par64(tb & d.z)) & 1u;
-                    measure_dispatch<3, 0>(d.cx, d.msign, r, flip_if(w.x, sg), flip_if(w.y, sg), accr, acci);
+                    meas_dispatch<7, 0>(d.kase & 255u, r, flip_if(w.x, sg), flip_if(w.y, sg), accr, acci);
                 }
             } else if constexpr (CT) {
 #pragma unroll 1
@@ -367,9 +388,9 @@ k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2
                     const double2 cs = tab[ri];
                     const uint32_t sg = ((tsb >> ri) ^ (uint32_t)par64(tb & d.z)) & 1u;
                     if (TANF && ((tanm >> ri) & 1))
-                        kase_dispatch<8, 0, true>(d.kase, r, 1.0, flip_if(cs.y, sg));
+                        kase_dispatch<7, 0, true>(d.kase & 255u, r, 1.0, flip_if(cs.y, sg));
                     else
-                        kase_dispatch<8, 0>(d.kase, r, cs.x, flip_if(cs.y, sg));
+                        kase_dispatch<7, 0>(d.kase & 255u, r, cs.x, flip_if(cs.y, sg));
                 }
             } else {
 #pragma unroll 1

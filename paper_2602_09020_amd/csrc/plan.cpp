@@ -299,6 +299,10 @@ bool build_pass_args2(const PassPlan &pp, const std::vector<Pauli> &rot, bool in
             for (int q = 0; q < kRegDims; ++q)
                 if (popc(s.v[q] & zl[i]) & 1) zr |= 1u << q;
             d.kase = cx | (zr << 4) | ((uint32_t)(w & 1) << 8);
+            // the compile-time bodies take the imaginary coefficient from
+            // (cx, zr): for a Hermitian string it is set exactly when
+            // parity(cx & zr) = |x & z| mod 2 is even
+            if ((w & 1) != ((cx == 0 || !(popc(cx & zr) & 1)) ? 1 : 0)) return false;
             uint32_t zt = 0;
             int tb = 0;
             for (int bit = 0; bit < b; ++bit)

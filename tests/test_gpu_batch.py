@@ -98,6 +98,25 @@ def test_batch_register_tiled_forward_vs_oracle(dtype, tol):
             assert np.abs(r["grad"][i] - sim.param_shift_grad(w)).max() <= 1e-10, i
 
 
+def test_batch_c64_gradients_vs_oracle_parameter_shift():
+    """complex64 storage, forward + adjoint in one batch: three circuits on the
+    register-tiled passes (12-14 qubits) and one on the LDS-staged passes
+    (9 qubits); every gradient against the oracle's complex128 parameter shift.
+    Tolerance: g_k = Im <lam_k|P_k|psi_k> with |lam_k| <= sum_j |c_j| and
+    |psi_k| = 1, so amplitude errors within the complex64 bound (1e-4) move a
+    gradient by at most about 1e-4 * sum_j |c_j|; the energy likewise."""
+    ws = [W.make_workload(f"c64g{i}", n, seed=500 + i, n_prefix=2 * n, n_rot=r, n_ham=20)
+          for i, (n, r) in enumerate(((12, 60), (13, 45), (14, 70), (9, 40)))]
+    B = hybrid.Batch(ws, torch.complex64)
+    B.run(with_grad=True)
+    r = B.results()
+    for i, w in enumerate(ws):
+        scale = np.abs(w.coeff).sum()
+        assert abs(r["energy"][i] - sim.energy_of(w, w.theta)) <= 1e-4 * scale, i
+        ps = sim.param_shift_grad(w)
+        assert np.abs(r["grad"][i] - ps).max() <= 1e-4 * scale, i
+
+
 def test_batch_matches_single_circuit_path():
     ws = W.batched_configs(seed=3, count=8, n_range=(12, 16), r_range=(100, 300), n_ham=40)
     B = hybrid.Batch(ws, torch.complex128)

@@ -45,6 +45,17 @@ def rand_state(n, seed):
     return v / np.linalg.norm(v)
 
 
+def phase_aligned(got, ref):
+    """Compare two states equal up to a global phase.  If got = ph ref + delta
+    with |ph| = 1 and |delta_i| <= eps, the phase read from the largest entry j
+    of ref is ph' = ph + delta_j / ref_j, so |got_i - ph' ref_i| <= 2 eps for
+    every i and ||ph'| - 1| <= eps / |ref_j|.  Returns
+    (max |got - ph' ref|, ||ph'| - 1|, |ref_j|)."""
+    j = int(np.argmax(np.abs(ref)))
+    ph = got[j] / ref[j]
+    return float(np.abs(got - ph * ref).max()), abs(abs(ph) - 1), float(abs(ref[j]))
+
+
 def run_workload(w, dtype, tuning=None, K=None):
     frame, rot, terms, plan, ham = hybrid.prepare(w, dtype, tuning)
     if K is not None:
@@ -173,6 +184,39 @@ def test_dense_random_strings_every_body_vs_oracle(dtype, tb, lb):
         psi, *_ = run_workload(w, dtype, {"tile_bits": tb, "low_bits": lb, "variant": variant})
         _, phi_ref = sim.simulate(w)
         assert maxdiff(psi, phi_ref) <= TOL[dtype], variant
+
+
+@pytest.mark.parametrize("dtype,tb,lb,variant", [(torch.complex128, 14, 3, 5), (torch.complex64, 13, 4, 4)])
+def test_every_body_production_shape_vs_oracle(dtype, tb, lb, variant):
+    """Uniformly random letters on 18 qubits in the kernel shape the benchmark
+    runs (complex128: 2^14 tiles, 3 contiguous bits, half-tile transposes;
+    complex64: 2^13 tiles, 4 contiguous bits), default coset order, many
+    cosets per workgroup.  Angles span [-pi, pi], so both the tangent and the
+    full form of every compile-time body run: the plan's own descriptors are
+    counted on the host, every one of the 512 (partner mask, register sign
+    mask, form) bodies is selected at least once, and the state matches the
+    oracle element by element."""
+    n = 18
+    rng = np.random.default_rng(7000 + tb)
+    rows = rng.integers(0, 4, size=(9000, n)).astype(np.uint8)
+    diag = rows[::37]                       # diagonal strings (partner mask 0)
+    diag[diag == 1] = 3
+    diag[diag == 2] = 0
+    rows[::37] = diag
+    theta = rng.uniform(-np.pi, np.pi, size=rows.shape[0])
+    w = W.Workload("dense18", n, 5, np.zeros((0, 3), np.int32), rows, theta, np.zeros((0, n), np.uint8), np.zeros(0))
+    tu = {"tile_bits": tb, "low_bits": lb, "variant": variant}
+    psi, frame, rot, terms, plan, ham, th = run_workload(w, dtype, tu)
+    counts = cfh.cfh_plan_leaf_counts(plan.h, w.theta)
+    assert plan.info()["tile_bits"] == tb and plan.info()["n_passes"] > 1
+    missing = np.flatnonzero(counts == 0)
+    assert missing.size == 0, f"bodies never selected: {missing[:20]}"
+    assert counts.sum() == rows.shape[0]
+    _, phi_ref = sim.simulate(w)
+    assert maxdiff(psi, phi_ref) <= TOL[dtype]
+    # the inverse sweep runs each rotation once more, with the same bodies
+    inv = cfh.cfh_plan_leaf_counts(plan.h, w.theta, inverse=True)
+    assert inv.sum() == counts.sum() and np.count_nonzero(inv) > 0
 
 
 def test_plan_rejects_unsupported_tuning():
@@ -439,6 +483,64 @@ def test_adjoint_config3_n20_all_gradients():
     assert abs(gpu_energy(p60, ham, psi0, th[:K].contiguous()) - sim.energy_of(w, w.theta, n_rot=K)) <= 1e-10
 
 
+def _golden_gradients(name):
+    """Oracle reference gradients written by tests/golden/make_oracle_gradients.py."""
+    import os
+    out = {"shift": {}, "fd": {}}
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            parts = line.split()
+            if parts[0] == "energy":
+                out["energy"] = float(parts[1])
+            else:
+                out[parts[0]][int(parts[1])] = float(parts[2])
+    return out
+
+
+def _adjoint_gradients(w):
+    frame, rot, terms, plan, ham = hybrid.prepare(w, torch.complex128)
+    psi0 = hybrid.new_state(w.n, torch.complex128, index=w.init)
+    theta = torch.tensor(w.theta, device=DEV, requires_grad=True)
+    e = hybrid.PauliEnergy.apply(theta, plan, ham, psi0)
+    e.backward()
+    return e.item(), theta.grad.cpu().numpy()
+
+
+def test_adjoint_config3_n20_gradient_subset_vs_oracle():
+    """n = 20, 1,000 rotations, 500-term H (the differentiation workload):
+    a seeded subset of 32 adjoint gradients against the CPU oracle's
+    parameter-shift rule (dense ladder simulations of every shifted circuit,
+    stored by the oracle-only script in tests/golden), within 1e-10; the
+    energy against the oracle's, within 1e-12 * sum |c_j|."""
+    w = W.config(3)
+    ref = _golden_gradients("config3_n20_grad_subset.txt")
+    e, g = _adjoint_gradients(w)
+    idx = np.array(sorted(ref["shift"]))
+    assert idx.size == 32
+    ps = np.array([ref["shift"][k] for k in idx])
+    assert np.abs(g[idx] - ps).max() <= 1e-10, np.abs(g[idx] - ps).max()
+    assert abs(e - ref["energy"]) <= 1e-12 * np.abs(w.coeff).sum()
+
+
+def test_adjoint_n24_gradient_subset_vs_oracle():
+    """n = 24 (HBM-resident states) with a 240-gate Clifford prefix, 60 JW
+    rotations and a 20-term observable: a seeded subset of 3 adjoint gradients
+    against the oracle's parameter shift (1e-10), one of them also against its
+    central finite difference (h = 1e-6, 1e-6), stored by the oracle-only
+    script in tests/golden."""
+    w = W.make_workload("adj24", 24, seed=24, n_prefix=240, n_rot=60, n_ham=20)
+    ref = _golden_gradients("adj24_grad_subset.txt")
+    e, g = _adjoint_gradients(w)
+    idx = np.array(sorted(ref["shift"]))
+    assert idx.size == 3
+    assert np.abs(g[idx] - np.array([ref["shift"][k] for k in idx])).max() <= 1e-10
+    for k, v in ref["fd"].items():
+        assert abs(g[k] - v) <= 1e-6
+    assert abs(e - ref["energy"]) <= 1e-12 * np.abs(w.coeff).sum()
+
+
 # -------------------------------------------------------- full-size checks
 
 @pytest.mark.parametrize("dtype", DTYPES)
@@ -456,6 +558,66 @@ def test_config2_n28_prefix_vs_sparse_oracle(dtype):
     norm = float((psi.abs() ** 2).sum().item())
     assert abs(norm - 1) <= (1e-12 if dtype == torch.complex128 else 1e-5)
     assert abs(norm - float(np.sum(np.abs(got) ** 2))) <= (1e-12 if dtype == torch.complex128 else 1e-5)
+
+
+class _N28Ladder:
+    """The oracle's dense ladder run of the 28-qubit Trotter workload (no
+    Clifford prefix, so Phi_ref = psi), advanced as tests ask for longer
+    prefixes and shared by the complex128 and complex64 checks."""
+
+    def __init__(self):
+        self.w = W.config(2)
+        self.k = 0
+        self.psi = sim.basis_state(self.w.n, self.w.init)
+
+    def advance(self, K):
+        if K > self.k:
+            sim.rotations(self.psi, self.w.n, self.w.rot[self.k:K], self.w.theta[self.k:K])
+            self.k = K
+        return self.psi
+
+
+@pytest.fixture(scope="module")
+def n28_ladder():
+    run = _N28Ladder()
+    yield run
+    run.psi = None
+
+
+@pytest.mark.parametrize("K", [100, 200])
+def test_config2_n28_c128_prefix_vs_ladder_oracle(n28_ladder, K):
+    """n = 28, complex128, in the benchmark's launch configuration: the state
+    after the first K rotations of the Trotter workload (the fused plan of those
+    K rotations) against the dense CNOT-ladder oracle, element by element over
+    all 2^28 amplitudes."""
+    psi, *_ = run_workload(n28_ladder.w, torch.complex128, K=K)
+    ref = n28_ladder.advance(K)
+    assert maxdiff(psi, ref) <= TOL[torch.complex128]
+
+
+def test_config2_n28_c64_prefix_vs_ladder_oracle(n28_ladder):
+    """n = 28, complex64 storage: the first 200 rotations against the same
+    complex128 ladder oracle run, element by element."""
+    K = 200
+    psi, *_ = run_workload(n28_ladder.w, torch.complex64, K=K)
+    ref = n28_ladder.advance(K)
+    assert maxdiff(psi, ref) <= TOL[torch.complex64]
+
+
+def test_config1_n24_500_rotations_and_500_terms_vs_ladder_oracle():
+    """n = 24 after the 500-gate Clifford prefix (rotations conjugated through
+    the frame): the first 500 rotations against the dense ladder oracle
+    (Phi = C^dag psi, element by element), and <H> over the first 500 terms of
+    the workload's observable, read from (frame, Phi), against the oracle's
+    <psi|H|psi> on its physical state."""
+    w = W.config(1)
+    K, M = 500, 500
+    psi, _, rot, terms, plan, ham, theta = run_workload(w, torch.complex128, K=K)
+    ref_psi, phi_ref = sim.simulate(w, n_rot=K)
+    assert maxdiff(psi, phi_ref) <= 1e-12
+    hm = hybrid.Hamiltonian(w.n, torch.complex128, terms[:M], w.coeff[:M])
+    e = hm.expval(psi)
+    assert abs(e.real - sim.energy(ref_psi, w.n, w.ham[:M], w.coeff[:M])) <= 1e-12 * np.abs(w.coeff[:M]).sum()
 
 
 def test_config2_n28_full_trotter_inverse_roundtrip():
@@ -536,16 +698,15 @@ def test_frame_flush_gives_the_physical_state(dtype, n, n_prefix):
     frame.flush(psi)
     phys, _ = sim.simulate(w)
     got = psi.cpu().to(torch.complex128).numpy()
-    k = int(np.argmax(np.abs(phys)))
-    ph = got[k] / phys[k]
-    tol = TOL[dtype] * (10 if dtype == torch.complex128 else 1)
-    assert abs(abs(ph) - 1) <= tol
-    assert np.abs(got - ph * phys).max() <= tol
+    err, dph, rmax = phase_aligned(got, phys)
+    assert dph <= TOL[dtype] / rmax
+    assert err <= 2 * TOL[dtype]
     for q in range(n):
         assert frame.row(q) == ((0, 1 << q, 0), (1 << q, 0, 0))
     # the identity frame: terms are their own images, and <H> is the same
     h_id = hybrid.Hamiltonian(n, dtype, cfh.cfh_pauli_encode(w.ham), w.coeff)
-    assert abs(h_id.expval(psi) - e_before) <= (1e-11 if dtype == torch.complex128 else 1e-4) * np.abs(w.coeff).sum()
+    # <H> is quadratic in the state: a state error eps moves it by at most 2 eps sum |c_j|
+    assert abs(h_id.expval(psi) - e_before) <= 2 * TOL[dtype] * np.abs(w.coeff).sum()
 
 
 # ------------------------------------------------------ gate-stream circuits
@@ -564,16 +725,15 @@ def test_circuit_run_vs_oracle_gate_by_gate(dtype, n, k, terms, steps):
     phys = sim.basis_state(n, init)
     sim.apply_circuit(phys, n, g, a)
     scale = np.abs(coeff).sum()
-    tol = TOL[dtype] * (10 if dtype == torch.complex128 else 1)
-    # <H> in the hybrid representation (Eq. chfsexp) against the oracle's physical state
+    # <H> in the hybrid representation (Eq. chfsexp) against the oracle's
+    # physical state: quadratic in the state, so within 2 eps sum |c_j|
     ham = hybrid.Hamiltonian(n, dtype, frame.conjugate(cfh.cfh_pauli_encode(letters)), coeff)
-    assert abs(ham.expval(psi).real - sim.energy(phys, n, letters, coeff)) <= tol * scale
+    assert abs(ham.expval(psi).real - sim.energy(phys, n, letters, coeff)) <= 2 * TOL[dtype] * scale
     frame.flush(psi)
     got = psi.cpu().to(torch.complex128).numpy()
-    j = int(np.argmax(np.abs(phys)))
-    ph = got[j] / phys[j]
-    assert abs(abs(ph) - 1) <= tol
-    assert np.abs(got - ph * phys).max() <= tol
+    err, dph, rmax = phase_aligned(got, phys)
+    assert dph <= TOL[dtype] / rmax
+    assert err <= 2 * TOL[dtype]
 
 
 # ------------------------------------------------------ measurement, reset
@@ -585,7 +745,6 @@ def test_measure_pauli_vs_oracle(dtype):
     projector definition, for u on both sides of P(+1)."""
     n = 12
     rng = np.random.default_rng(31)
-    tol = TOL[dtype] * (10 if dtype == torch.complex128 else 1)
     for trial in range(10):
         v = rand_state(n, 100 + trial)
         letters = rng.integers(0, 4, size=n).astype(np.uint8)
@@ -601,8 +760,11 @@ def test_measure_pauli_vs_oracle(dtype):
             if abs(u - pp_ref) < 1e-9:
                 continue                        # outcome decided by rounding: not comparable
             s, pp = cfh.cfh_measure_pauli(psi, n, int(p["x"]), int(p["z"]), int(p["e"]), u)
-            assert s == s_ref and abs(pp - pp_ref) <= tol
-            assert maxdiff(psi, w) <= tol
+            assert s == s_ref and abs(pp - pp_ref) <= TOL[dtype]
+            # the collapse scales by 1/(2 sqrt(P(s))): rounding in the pass and the
+            # error in P(s) grow by at most 1/P(s)
+            ps = pp_ref if s_ref > 0 else 1.0 - pp_ref
+            assert maxdiff(psi, w) <= TOL[dtype] * (1 + 1 / ps)
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
@@ -612,7 +774,6 @@ def test_circuit_with_measurements_and_resets_vs_oracle(dtype, n):
     the flushed final state (up to phase) against the oracle's gate-by-gate
     run with the same uniform numbers."""
     rng = np.random.default_rng(n)
-    tol = TOL[dtype] * (10 if dtype == torch.complex128 else 1)
     for trial in range(4):
         gates, angles = [], []
         for _ in range(30 * n):
@@ -632,16 +793,22 @@ def test_circuit_with_measurements_and_resets_vs_oracle(dtype, n):
                 angles.append(0.0)
         g, a = np.array(gates, np.int32), np.array(angles)
         phys = sim.basis_state(n, 0)
-        out_ref = sim.apply_circuit(phys, n, g, a)
+        probs = []
+        out_ref = sim.apply_circuit(phys, n, g, a, probs)
         frame = hybrid.Frame(n)
         psi = hybrid.new_state(n, dtype, index=0)
         out = frame.run_circuit(g, a, psi)
         assert np.array_equal(out, out_ref), trial
         frame.flush(psi)
         got = psi.cpu().to(torch.complex128).numpy()
-        j = int(np.argmax(np.abs(phys)))
-        ph = got[j] / phys[j]
-        assert abs(abs(ph) - 1) <= tol and np.abs(got - ph * phys).max() <= tol, trial
+        # each collapse renormalizes by 1/sqrt(P(s)), which scales the error
+        # carried so far, and adds at most eps (1 + 1/P(s)) of its own (see the
+        # single-measurement test); the flush and the phase alignment add 2 eps
+        eps = TOL[dtype]
+        for ps in probs:
+            eps = eps / np.sqrt(ps) + TOL[dtype] * (1 + 1 / ps)
+        err, dph, rmax = phase_aligned(got, phys)
+        assert dph <= eps / rmax and err <= 2 * eps, trial
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
