@@ -55,6 +55,21 @@ def counter_traffic(name: str, kernel: str):
     return d.get("traffic_bytes_per_launch")
 
 
+def host_info():
+    """The host CPU the oracle runs on: model name (as lscpu prints it), the
+    logical CPUs the machine has and those this process may use."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0))}
+
+
 def measure_ceilings(buf, n, reps=5):
     """HBM rates of the library's calibration kernel on a state-sized buffer
     (its contents are overwritten): in-place read-modify-write streamed in
@@ -451,6 +466,49 @@ def main():
                           "backward_over_forward": float(np.median(bw) / np.median(fw)),
                           "passes": plan_a.info()["n_passes"]}
 
+        # the 24-qubit Trotter workload after its 500-gate Clifford prefix: the
+        # whole path (frame tracking, conjugation of 5,000 rotations and 5,000
+        # terms, planning, fused passes, <H>) end to end; the 256 MiB state
+        # largely fits the 256 MiB Infinity Cache, so its GB/s is cache-assisted
+        w1 = W.config(1)
+        psi1 = torch.empty(1 << w1.n, dtype=dtype, device=dev)
+        th1 = torch.tensor(w1.theta, device=dev)
+        e1 = torch.zeros(2, dtype=torch.float64, device=dev)
+        runs1 = []
+        for it in range(3):
+            torch.cuda.synchronize()
+            t0w = time.perf_counter()
+            f1 = hybrid.Frame(w1.n)
+            f1.apply_gates(w1.prefix)
+            r1 = f1.conjugate(cfh.cfh_pauli_encode(w1.rot))
+            t1 = f1.conjugate(cfh.cfh_pauli_encode(w1.ham))
+            cfh.cfh_state_set_basis(psi1, w1.n, w1.init)
+            p1 = hybrid.Plan(w1.n, dtype, r1)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            ev[0].record(stream)
+            p1.apply(psi1, th1)
+            ev[1].record(stream)
+            h1 = hybrid.Hamiltonian(w1.n, dtype, t1, w1.coeff)
+            ev[2].record(stream)
+            h1.expval_async(psi1, e1)
+            ev[3].record(stream)
+            torch.cuda.synchronize()
+            if it:
+                runs1.append((time.perf_counter() - t0w, ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3])))
+        i1, hi1 = p1.info(), h1.info()
+        wall1, pass1_ms, ex1_ms = (float(np.median([r[k] for r in runs1])) for k in range(3))
+        out["config1_n24"] = {
+            "workload": w1.name, "n_qubits": w1.n, "clifford_prefix": int(w1.prefix.shape[0]),
+            "rotations": w1.n_rot, "hamiltonian_terms": int(w1.ham.shape[0]),
+            "rotations_per_s_end_to_end": w1.n_rot / wall1, "end_to_end_ms": wall1 * 1e3,
+            "passes": i1["n_passes"], "fusion_depth": w1.n_rot / i1["n_passes"],
+            "passes_ms": pass1_ms, "passes_gbs_cache_assisted": i1["hbm_bytes"] / (pass1_ms * 1e-3) / 1e9,
+            "expval_ms": ex1_ms, "expval_passes": hi1["n_passes"],
+            "expval_gbs_cache_assisted": hi1["hbm_bytes"] / (ex1_ms * 1e-3) / 1e9,
+            "energy": float(e1[0].item())}
+        del psi1, p1, h1
+        torch.cuda.empty_cache()
+
         # 256 independent circuits (n 12..20, 500..3,000 rotations, 200-term observables),
         # forward + adjoint in one captured hipGraph launch, tile shape from the autotuner
         from paper_2602_09020_amd import autotune
@@ -519,6 +577,32 @@ def main():
             sim.apply_circuit(v24, 24, g[:cut], a_[:cut])
             kgl.append({"L": L, "s_per_term": (time.perf_counter() - t0) / 4})
         out["cpu_baseline"]["klocal_gate_by_gate"] = kgl
+        out["cpu_baseline"]["host"] = host_info()
+        # one core: the first 2 rotations of the 28-qubit workload
+        nthr = sim.num_threads()
+        sim.set_num_threads(1)
+        v[:] = 0
+        v[w.init] = 1
+        t0 = time.perf_counter()
+        sim.rotations(v, n, w.rot[:2], w.theta[:2])
+        s1 = time.perf_counter() - t0
+        sim.set_num_threads(nthr)
+        out["cpu_baseline"]["single_core"] = {"value": 2 / s1, "unit": "rotations/s", "cores": 1,
+                                              "sample": f"first 2 rotations of the {n}-qubit workload ({s1:.1f} s)"}
+        del v
+        # full oracle runs of the 10-qubit forward workload and the 20-qubit
+        # differentiation workload (its energy at the given angles), all cores
+        full = []
+        for cfg in (0, 3):
+            wc = W.config(cfg)
+            t0 = time.perf_counter()
+            psi_c, _ = sim.simulate(wc)
+            e_c = sim.energy(psi_c, wc.n, wc.ham, wc.coeff)
+            sc = time.perf_counter() - t0
+            full.append({"workload": wc.name, "n_qubits": wc.n, "rotations": wc.n_rot,
+                         "hamiltonian_terms": int(wc.ham.shape[0]), "s": sc, "rotations_per_s": wc.n_rot / sc,
+                         "energy": e_c, "cores": nthr})
+        out["cpu_baseline"]["full_runs"] = full
     print(json.dumps(out), flush=True)
 
 

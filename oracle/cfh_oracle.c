@@ -471,6 +471,15 @@ int64_t orc_sparse_rotations(int n, const uint64_t *idx_in, const cplx *amp_in, 
     return o;
 }
 
+void orc_set_num_threads(int k)
+{
+#ifdef _OPENMP
+    if (k > 0) omp_set_num_threads(k);
+#else
+    (void)k;
+#endif
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

@@ -47,12 +47,18 @@ def lib():
                                            _f64p, C.c_int64, _u64p, _c128p, C.c_int64]
         L.orc_sparse_rotations.restype = C.c_int64
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
         _LIB = L
     return _LIB
 
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(k: int) -> None:
+    """Threads the oracle's parallel loops use from now on (k >= 1)."""
+    lib().orc_set_num_threads(int(k))
 
 
 def _check(rc, what):

@@ -19,6 +19,9 @@ FLAGS = [
     # structurizing them makes every body's outputs live through the whole
     # tree, which costs register copies and occupancy
     "-mllvm", "-structurizecfg-skip-uniform-regions=true",
+    # keep sibling leaves of the body switches apart: sinking their common
+    # instructions merges them into one leaf with selected operands
+    "-mllvm", "-sink-common-insts=false",
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
 ]

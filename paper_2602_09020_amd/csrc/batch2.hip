@@ -68,7 +68,7 @@ k_batch_fwd2(const BatchArgs A, const PassArgs2 *__restrict__ pa, const BItem *_
 #pragma unroll 1
         for (int g = 0; g <= last; ++g) {
             const MGDesc2 &m = args.mg[g];
-            const uint32_t bt = deposit32(t, m.npiv);
+            const uint32_t bt = deposit_tid(t, m.npiv);
             if (g > 0) {
                 const MGDesc2 &mp = args.mg[g - 1];
                 if constexpr (HALF) {
@@ -100,7 +100,7 @@ k_batch_fwd2(const BatchArgs A, const PassArgs2 *__restrict__ pa, const BItem *_
                 const RotDesc2 &d = args.rot[ri];
                 const double2 cs = tab[ri];
                 const uint32_t sg = ((tsb >> ri) ^ (uint32_t)par64(tb & d.z)) & 1u;
-                kase_dispatch<7, 0>(d.kase & 255u, r, cs.x, flip_if(cs.y, sg));
+                kase_switch(d.kase, r, cs.x, flip_if(cs.y, sg));
             }
         }
         const uint64_t yL = tb ^ LbL;
@@ -175,7 +175,7 @@ k_batch_adj2(const BatchArgs A, const PassArgs2 *__restrict__ pa, const BItem *_
 #pragma unroll 1
         for (int g = 0; g <= last; ++g) {
             const MGDesc2 &m = args.mg[g];
-            const uint32_t bt = deposit32(t, m.npiv);
+            const uint32_t bt = deposit_tid(t, m.npiv);
             if (g > 0) {
                 const MGDesc2 &mp = args.mg[g - 1];
                 if constexpr (HALF) {
@@ -289,7 +289,7 @@ k_batch_meas2(const BatchArgs A, const PassArgs2 *__restrict__ pa, const BItem *
 #pragma unroll 1
         for (int g = 0; g <= last; ++g) {
             const MGDesc2 &m = args.mg[g];
-            const uint32_t bt = deposit32(t, m.npiv);
+            const uint32_t bt = deposit_tid(t, m.npiv);
             if (g > 0) {
                 const MGDesc2 &mp = args.mg[g - 1];
 #pragma unroll
@@ -309,7 +309,7 @@ k_batch_meas2(const BatchArgs A, const PassArgs2 *__restrict__ pa, const BItem *
                 const RotDesc2 &d = args.rot[ri];
                 const double2 w = tab[ri];
                 const uint32_t sg = ((tsb >> ri) ^ (uint32_t)par64(tb & d.z)) & 1u;
-                meas_dispatch<7, 0>(d.kase & 255u, r, flip_if(w.x, sg), flip_if(w.y, sg), accr, acci);
+                meas_switch(d.kase, r, flip_if(w.x, sg), flip_if(w.y, sg), accr, acci);
             }
         }
     }
@@ -386,7 +386,7 @@ k_batch_ham2(const BatchArgs A, const PassArgs2 *__restrict__ pa, const BItem *_
 #pragma unroll 1
         for (int g = 0; g <= last; ++g) {
             const MGDesc2 &m = args.mg[g];
-            const uint32_t bt = deposit32(t, m.npiv);
+            const uint32_t bt = deposit_tid(t, m.npiv);
             if (g > 0) {
                 const MGDesc2 &mp = args.mg[g - 1];
                 if constexpr (HALF) {

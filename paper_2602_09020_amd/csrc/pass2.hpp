@@ -35,6 +35,22 @@ __device__ __forceinline__ uint32_t deposit32(uint32_t v, uint32_t mask)
     return r;
 }
 
+// deposit32(t, mask) for the thread index t of a workgroup of at least one
+// wave, where mask has one set bit per thread-index bit: the six lane bits go
+// to the six lowest set bits of mask (two VALU operations each), the wave
+// bits, uniform across the wave, to the others (scalar operations).
+__device__ __forceinline__ uint32_t deposit_tid(uint32_t t, uint32_t mask)
+{
+    uint32_t m = mask, r = 0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        const uint32_t low = m & (~m + 1);
+        r |= (0u - ((t >> i) & 1u)) & low;
+        m &= m - 1;
+    }
+    return r | deposit32(__builtin_amdgcn_readfirstlane(t >> 6), m);
+}
+
 // v with its sign flipped when the (wave-uniform) bit is set: one XOR of the
 // high word instead of a select between two registers.
 __device__ __forceinline__ double flip_if(double v, uint32_t bit)
@@ -127,19 +143,25 @@ __device__ __forceinline__ void kase_body(double2 (&r)[kRegs], double c_in, doub
     }
 }
 
-// Uniform branch tree over the eight bits of cx | zr << 4 (one leaf per body).
-template <int BIT, int ACC, bool TAN = false>
-__device__ __forceinline__ void kase_dispatch(uint32_t kase, double2 (&r)[kRegs], double c, double s)
+// One leaf per body, selected by a dense switch on cx | zr << 4 (a binary
+// search of scalar compares, two scalar instructions per level).
+#define CFH_KASE_CASE(K) \
+    case K: kase_body<K, TAN>(r, c, s); break;
+#define CFH_KASE_CASE4(K) CFH_KASE_CASE(K) CFH_KASE_CASE(K + 1) CFH_KASE_CASE(K + 2) CFH_KASE_CASE(K + 3)
+#define CFH_KASE_CASE16(K) CFH_KASE_CASE4(K) CFH_KASE_CASE4(K + 4) CFH_KASE_CASE4(K + 8) CFH_KASE_CASE4(K + 12)
+#define CFH_KASE_CASE64(K) CFH_KASE_CASE16(K) CFH_KASE_CASE16(K + 16) CFH_KASE_CASE16(K + 32) CFH_KASE_CASE16(K + 48)
+template <bool TAN = false>
+__device__ __forceinline__ void kase_switch(uint32_t kase, double2 (&r)[kRegs], double c, double s)
 {
-    if constexpr (BIT < 0) {
-        kase_body<ACC, TAN>(r, c, s);
-    } else {
-        if (kase & (1u << BIT))
-            kase_dispatch<BIT - 1, ACC | (1 << BIT), TAN>(kase, r, c, s);
-        else
-            kase_dispatch<BIT - 1, ACC, TAN>(kase, r, c, s);
+    switch (kase & 255u) {
+        CFH_KASE_CASE64(0) CFH_KASE_CASE64(64) CFH_KASE_CASE64(128) CFH_KASE_CASE64(192)
+    default: break;
     }
 }
+#undef CFH_KASE_CASE64
+#undef CFH_KASE_CASE16
+#undef CFH_KASE_CASE4
+#undef CFH_KASE_CASE
 
 // Read-only term bodies (expectation values).  For a term with partner mask
 // CX and register sign mask ZR (the sign of register j is
@@ -158,8 +180,6 @@ __device__ __forceinline__ void meas_body(const double2 (&r)[kRegs], double wre,
                                           double &acci)
 {
     constexpr int CX = KM & 15, ZR = (KM >> 4) & 15;
-    // a side effect: keeps the leaf from being if-converted into selects with its siblings
-    asm volatile("");
     double acc[2] = {0.0, 0.0};
     if constexpr (CX == 0) {
 #pragma unroll
@@ -201,20 +221,24 @@ __device__ __forceinline__ void meas_body(const double2 (&r)[kRegs], double wre,
     }
 }
 
-// Uniform branch tree over the eight bits of cx | zr << 4 (one leaf per body).
-template <int BIT, int ACC>
-__device__ __forceinline__ void meas_dispatch(uint32_t km, const double2 (&r)[kRegs], double wre, double wim,
-                                              double &accr, double &acci)
+// One leaf per body, selected by a dense switch on cx | zr << 4.
+#define CFH_MEAS_CASE(K) \
+    case K: meas_body<K>(r, wre, wim, accr, acci); break;
+#define CFH_MEAS_CASE4(K) CFH_MEAS_CASE(K) CFH_MEAS_CASE(K + 1) CFH_MEAS_CASE(K + 2) CFH_MEAS_CASE(K + 3)
+#define CFH_MEAS_CASE16(K) CFH_MEAS_CASE4(K) CFH_MEAS_CASE4(K + 4) CFH_MEAS_CASE4(K + 8) CFH_MEAS_CASE4(K + 12)
+#define CFH_MEAS_CASE64(K) CFH_MEAS_CASE16(K) CFH_MEAS_CASE16(K + 16) CFH_MEAS_CASE16(K + 32) CFH_MEAS_CASE16(K + 48)
+__device__ __forceinline__ void meas_switch(uint32_t km, const double2 (&r)[kRegs], double wre, double wim,
+                                            double &accr, double &acci)
 {
-    if constexpr (BIT < 0) {
-        meas_body<ACC>(r, wre, wim, accr, acci);
-    } else {
-        if (km & (1u << BIT))
-            meas_dispatch<BIT - 1, ACC | (1 << BIT)>(km, r, wre, wim, accr, acci);
-        else
-            meas_dispatch<BIT - 1, ACC>(km, r, wre, wim, accr, acci);
+    switch (km & 255u) {
+        CFH_MEAS_CASE64(0) CFH_MEAS_CASE64(64) CFH_MEAS_CASE64(128) CFH_MEAS_CASE64(192)
+    default: break;
     }
 }
+#undef CFH_MEAS_CASE64
+#undef CFH_MEAS_CASE16
+#undef CFH_MEAS_CASE4
+#undef CFH_MEAS_CASE
 
 // Coset handled at loop index t of the persistent loop.  Workgroups are
 // dealt to the 8 XCDs in turn (workgroup w runs on XCD w mod 8) and the grid
@@ -342,7 +366,7 @@ k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2
 #pragma unroll 1
         for (int g = 0; g <= last; ++g) {
             const MGDesc2 &m = args.mg[g];
-            const uint32_t bt = deposit32(t, m.npiv);
+            const uint32_t bt = deposit_tid(t, m.npiv);
             if (g > 0) {
                 const MGDesc2 &mp = args.mg[g - 1];
                 if constexpr (HALF) {
@@ -379,7 +403,7 @@ k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2
                     const RotDesc2 &d = args.rot[ri];
                     const double2 w = tab[ri];
                     const uint32_t sg = ((tsb >> ri) ^ (uint32_t)par64(tb & d.z)) & 1u;
-                    meas_dispatch<7, 0>(d.kase & 255u, r, flip_if(w.x, sg), flip_if(w.y, sg), accr, acci);
+                    meas_switch(d.kase, r, flip_if(w.x, sg), flip_if(w.y, sg), accr, acci);
                 }
             } else if constexpr (CT) {
 #pragma unroll 1
@@ -388,9 +412,9 @@ k_pass2(Amp *__restrict__ psi, const double2 *__restrict__ coef, const PassArgs2
                     const double2 cs = tab[ri];
                     const uint32_t sg = ((tsb >> ri) ^ (uint32_t)par64(tb & d.z)) & 1u;
                     if (TANF && ((tanm >> ri) & 1))
-                        kase_dispatch<7, 0, true>(d.kase & 255u, r, 1.0, flip_if(cs.y, sg));
+                        kase_switch<true>(d.kase, r, 1.0, flip_if(cs.y, sg));
                     else
-                        kase_dispatch<7, 0>(d.kase & 255u, r, cs.x, flip_if(cs.y, sg));
+                        kase_switch(d.kase, r, cs.x, flip_if(cs.y, sg));
                 }
             } else {
 #pragma unroll 1
@@ -547,7 +571,7 @@ k_adj2(Amp *__restrict__ psi, Amp *__restrict__ lam, const double2 *__restrict__
 #pragma unroll 1
         for (int g = 0; g <= last; ++g) {
             const MGDesc2 &m = args.mg[g];
-            const uint32_t bt = deposit32(t, m.npiv);
+            const uint32_t bt = deposit_tid(t, m.npiv);
             if (g > 0) {
                 const MGDesc2 &mp = args.mg[g - 1];
                 if constexpr (HALF) {
@@ -698,7 +722,7 @@ k_ham2(const Amp *__restrict__ psi, Amp *__restrict__ lam, const double2 *__rest
 #pragma unroll 1
         for (int g = 0; g <= last; ++g) {
             const MGDesc2 &m = args.mg[g];
-            const uint32_t bt = deposit32(t, m.npiv);
+            const uint32_t bt = deposit_tid(t, m.npiv);
             if (g > 0) {
                 const MGDesc2 &mp = args.mg[g - 1];
                 // bprev and bt have 0 at the anchor bit (it is a pivot)
