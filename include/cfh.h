@@ -277,6 +277,24 @@ cfh_status cfh_expval_async(cfh_ham h, const void *psi, double *out_dev, void *s
 cfh_status cfh_expval(const void *psi, int n, int dtype, const cfh_pauli *terms,
                       const double *coeff, size_t m, double *out_host, void *stream);
 
+/* For callers that cannot allocate device memory at call time (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * out_dev[0] + i out_dev[1] = sum_j coeff_j <psi|P_j|psi>, as cfh_expval
+ * computes it, with nothing allocated, freed or synchronized.  psi is device
+ * memory, 2^n amplitudes of dtype (1 <= n <= 34); terms (m Hermitian Paulis,
+ * host) and coeff (m doubles, host) are read before the call returns; out_dev
+ * is device memory for 2 doubles.  Each term is one read of the state (no
+ * fusion).  The per-workgroup partial sums live in a fixed 32 KiB device
+ * array of the library (at most 2048 workgroups per launch, so every n up
+ * to 34 fits), one copy per device, looked up on the first call on that
+ * device; each call overwrites it, so calls that overlap in time on one
+ * device race.  Asynchronous on `stream`; deterministic fixed-order
+ * reduction.  Errors: CFH_E_INVAL (null state, output, or terms/coeff with
+ * m > 0), CFH_E_RANGE, CFH_E_NOT_HERMITIAN, CFH_E_UNSUPPORTED (n, dtype),
+ * CFH_E_HIP. */
+cfh_status cfh_expval_noalloc(const void *psi, int n, int dtype, const cfh_pauli *terms, const double *coeff,
+                              size_t m, double *out_dev, void *stream);
+
 /* out <- H psi (out-of-place; out must not alias psi).  Asynchronous on
  * `stream`; allocates nothing.  Errors: CFH_E_INVAL (null or aliased
  * pointers), CFH_E_HIP. */

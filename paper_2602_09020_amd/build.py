@@ -8,7 +8,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libcfh.so")
 SOURCES = ["frame.cpp", "plan.cpp", "kernels.hip", "pass2_c128.hip", "pass2_c64.hip", "batch.hip", "batch2.hip",
-           "calib.hip"]
+           "calib.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -90,6 +90,7 @@ _SIGS = {
     "cfh_ham_info": (C.c_int32, [_vp, _P(C.c_int64), _P(C.c_int64), _P(C.c_double)]),
     "cfh_expval_async": (C.c_int32, [_vp, _vp, _vp, _vp]),
     "cfh_expval": (C.c_int32, [_vp, C.c_int, C.c_int, _vp, _vp, C.c_size_t, _vp, _vp]),
+    "cfh_expval_noalloc": (C.c_int32, [_vp, C.c_int, C.c_int, _vp, _vp, C.c_size_t, _vp, _vp]),
     "cfh_ham_apply": (C.c_int32, [_vp, _vp, _vp, _vp]),
     "cfh_adjoint_grad": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cfh_calib_rmw": (C.c_int32, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, _vp]),
@@ -397,6 +398,13 @@ def cfh_expval(psi, n: int, terms: np.ndarray, coeff: np.ndarray, stream=None) -
     _call("cfh_expval", _dev_ptr(psi, "psi"), n, _dtype_code(psi), a.ctypes.data, c.ctypes.data, a.shape[0],
           out.ctypes.data, _stream(stream))
     return complex(out[0], out[1])
+
+
+def cfh_expval_noalloc(psi, n: int, terms: np.ndarray, coeff: np.ndarray, out_dev, stream=None) -> None:
+    a = _paulis(terms)
+    c = np.ascontiguousarray(coeff, dtype=np.float64)
+    _call("cfh_expval_noalloc", _dev_ptr(psi, "psi"), n, _dtype_code(psi), a.ctypes.data, c.ctypes.data,
+          a.shape[0], _dev_ptr(out_dev, "out"), _stream(stream))
 
 
 def cfh_calib_rmw(buf, n: int, chunk_bits: int = -1, nontemporal: bool = False, stream=None) -> None:
