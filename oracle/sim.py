@@ -27,7 +27,8 @@ _u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
 def lib():
     global _LIB
     if _LIB is None:
-        path = os.path.join(_HERE, "liboracle.so")
+        # CFH_ORACLE_LIB selects another build of the oracle (the host sanitizer run uses one)
+        path = os.environ.get("CFH_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
         if not os.path.exists(path):
             from . import build as _b
             _b.build()

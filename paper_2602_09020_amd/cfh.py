@@ -15,7 +15,8 @@ from typing import Optional, Sequence, Tuple
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libcfh.so")
+# CFH_LIB_PATH selects another build of the library (the host sanitizer run uses one)
+LIB_PATH = os.environ.get("CFH_LIB_PATH") or os.path.join(_HERE, "libcfh.so")
 
 CFH_OK, CFH_E_INVAL, CFH_E_RANGE, CFH_E_NOT_HERMITIAN = 0, -1, -2, -3
 CFH_E_NOMEM, CFH_E_HIP, CFH_E_UNSUPPORTED = -4, -5, -6

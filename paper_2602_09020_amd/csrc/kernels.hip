@@ -1209,8 +1209,9 @@ cfh_status cfh_ham_create(int n, int dtype, const cfh_pauli *terms, const double
     {
         TuningResolved tm = resolve_tuning(tuning, n, dtype, kTuneMeasure);
         if (tm.variant != 1 && tm.tile_bits >= 10 && tm.tile_bits <= 14 && m > 0) {
-            // half-tile transposes: required at 2^14, selectable by variant 5 below
-            const bool anchor = tm.tile_bits == 14 || tm.variant == 5;
+            // half-tile transposes: required at 2^14, the default at complex128,
+            // selectable by variant 5
+            const bool anchor = tm.tile_bits == 14 || tm.variant == 5 || (tm.variant == 0 && dtype == CFH_C128);
             std::vector<Pauli> tp(m);
             for (size_t i = 0; i < m; ++i) tp[i] = Pauli{terms[i].x, terms[i].z, terms[i].e & 3};
             st = term_passes(n, dtype, groups, tp, tm, anchor, h->margs, "cfh_ham_create");

@@ -26,6 +26,11 @@ TuningResolved resolve_tuning(const cfh_tuning *t, int n, int dtype, int kind)
     if (kind == kTuneAdjoint) b = c64 ? 12 : 11;
     if (kind == kTuneHamiltonian) b = c64 ? 13 : 12;
     if (kind == kTuneAdjoint2) b = c64 ? 14 : 13;
+    // read-only <H> passes at complex128: 2^13 tiles with half-tile
+    // transposes leave LDS for two workgroups per CU, which overlap one
+    // workgroup's loads with the other's term sums (28 qubits, 2,000 terms:
+    // 2^13 126 ms, 2^14 139 ms, 2^12 129 ms)
+    if (kind == kTuneMeasure && !c64) b = 13;
     // the adjoint holds two vectors per workgroup (fewer workgroups per CU),
     // so it keeps at least 256 tiles
     b = std::max(std::min(b, n - (kind == kTuneAdjoint2 ? 8 : 7)), std::min(n, 10));
