@@ -109,6 +109,8 @@ typedef struct cfh_tuning {
                               is fetched into one L2 once, and bit-reversed order otherwise;
                               1 = cosets in index order; 2 = bit-reversed coset index (workgroups
                               running together are spread over the whole state) */
+    int32_t reg_tile_bits; /* batched runs: log2 amplitudes of the register tiles that circuits with
+                              at least that many qubits run on (11..13; 0 = 12) */
 } cfh_tuning;
 
 typedef struct cfh_frame_s *cfh_frame;

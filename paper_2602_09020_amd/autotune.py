@@ -109,16 +109,34 @@ def tune_plan(n: int, dtype, rot: np.ndarray, theta: np.ndarray, candidates: Opt
 
 
 def batch_candidates(dtype) -> List[dict]:
+    """Register tile (2^11..2^13 amplitudes, for circuits with at least that
+    many qubits) x fusion depth (the most rotations one pass may carry) x work
+    items per pass; the LDS tile of the smaller circuits stays at its default."""
     c128 = hybrid.state_dtype(dtype) == _c.CFH_C128
-    tbs = (9, 10, 11) if c128 else (10, 11, 12)
-    return [{"tile_bits": tb, "batch_items": it, "group_mib": gm} for tb in tbs for it in (16, 64)
-            for gm in (0, 128, 192)]
+    return [{"tile_bits": 10 if c128 else 11, "reg_tile_bits": rb, "max_run": mr, "batch_items": it, "group_mib": 0}
+            for rb in (11, 12, 13) for mr in (8, 32) for it in (64, 128)]
+
+
+def _time_batch(B, with_grad: bool, s, reps: int) -> float:
+    """Median over reps replays of the captured graph (one warm-up replay first)."""
+    B.graph_launch(with_grad, s)
+    B.results(stream=s)
+    ms = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        B.graph_launch(with_grad, s)
+        b.record(s)
+        B.results(stream=s)
+        ms.append(a.elapsed_time(b))
+    return float(np.median(ms))
 
 
 def tune_batch(workloads, dtype, candidates: Optional[Iterable[dict]] = None, with_grad: bool = True,
-               use_cache: bool = True, verbose: bool = False) -> Dict:
-    """Fastest (tile_bits, batch_items) for a batch of circuits, timed as one
-    captured-graph launch each."""
+               use_cache: bool = True, verbose: bool = False, reps: int = 3) -> Dict:
+    """Fastest batch tuning (register tile, fusion depth, items per pass, LDS
+    tile, cache groups) for a batch of circuits, each candidate timed as the
+    median of ``reps`` replays of its captured graph."""
     key = _key(f"batch{len(workloads)}", max(w.n for w in workloads), dtype)
     cache = _load() if use_cache else {}
     if use_cache and key in cache:
@@ -130,14 +148,7 @@ def tune_batch(workloads, dtype, candidates: Optional[Iterable[dict]] = None, wi
             B = hybrid.Batch(workloads, dtype, tu)
         except _c.CfhError:
             continue
-        B.graph_launch(with_grad, s)
-        B.results(stream=s)
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(s)
-        B.graph_launch(with_grad, s)
-        b.record(s)
-        B.results(stream=s)
-        ms = a.elapsed_time(b)
+        ms = _time_batch(B, with_grad, s, reps)
         del B
         if verbose:
             print(f"autotune batch {tu}: {ms:.2f} ms", flush=True)

@@ -36,7 +36,7 @@ class cfh_tuning(C.Structure):
     _fields_ = [("tile_bits", C.c_int32), ("low_bits", C.c_int32), ("max_run", C.c_int32),
                 ("lookahead", C.c_int32), ("unfused", C.c_int32), ("block_threads", C.c_int32),
                 ("variant", C.c_int32), ("batch_items", C.c_int32),
-                ("group_mib", C.c_int32), ("tile_order", C.c_int32)]
+                ("group_mib", C.c_int32), ("tile_order", C.c_int32), ("reg_tile_bits", C.c_int32)]
 
 
 class cfh_circuit_desc(C.Structure):

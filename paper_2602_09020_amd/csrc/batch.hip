@@ -342,7 +342,8 @@ struct cfh_batch_s {
     BItem *d_items[2][kKernCount] = {};
     PassArgs2 *d_pa = nullptr;
     double2 *d_mw = nullptr;
-    int reg_fwd = 0;                // circuits with n >= kBatchRegTile run forward on register tiles
+    int reg_fwd = 0;                // circuits with n >= reg_bits run on register tiles
+    int reg_bits = kBatchRegTile;   // log2 amplitudes of a register tile
     int *d_reduce[2] = {nullptr, nullptr};
     RotDesc *d_rot = nullptr;
     HamGroupDev *d_groups = nullptr;
@@ -406,6 +407,9 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
     B->count = count;
     B->dtype = dtype;
     B->reg_fwd = !(tuning && tuning->variant == 2);
+    B->reg_bits = (tuning && tuning->reg_tile_bits > 0) ? tuning->reg_tile_bits : kBatchRegTile;
+    if (B->reg_bits < 11 || B->reg_bits > 13)
+        return set_error(CFH_E_UNSUPPORTED, "cfh_batch_create: reg_tile_bits must be in 11..13");
     const int bcap = dtype == CFH_C128 ? 11 : 12;
     B->bmax = (tuning && tuning->tile_bits > 0) ? tuning->tile_bits : 10;
     if (B->bmax < 8 || B->bmax > bcap)
@@ -447,8 +451,8 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
         const uint64_t ntiles = 1ull << (d.n - b);
         const int tpi = (int)std::max<uint64_t>(1, (ntiles + max_items - 1) / max_items);
         const int nitems = (int)((ntiles + tpi - 1) / tpi);
-        const bool reg = B->reg_fwd && d.n >= kBatchRegTile && d.m > 0;
-        const uint64_t nt2 = reg ? 1ull << (d.n - kBatchRegTile) : 1;
+        const bool reg = B->reg_fwd && d.n >= B->reg_bits && d.m > 0;
+        const uint64_t nt2 = reg ? 1ull << (d.n - B->reg_bits) : 1;
         const int tpi2 = (int)std::max<uint64_t>(1, (nt2 + max_items - 1) / max_items);
         const int nitems2 = (int)((nt2 + tpi2 - 1) / tpi2);
         BCirc &C = circs[c];
@@ -502,10 +506,10 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
         }
         std::vector<int> fwd_ids, adj_reg;
         if (reg) {
-            // forward passes on 2^12-amplitude register tiles (128-byte chunks);
+            // forward passes on register tiles of 2^reg_bits amplitudes (128-byte chunks);
             // a run needing more micro-groups than a pass carries is split in two
             cfh_tuning t2{};
-            t2.tile_bits = kBatchRegTile;
+            t2.tile_bits = B->reg_bits;
             t2.max_run = tc.max_run;
             const TuningResolved tu2 = resolve_tuning(&t2, d.n, dtype, kTuneForward);
             std::vector<PassPlan> done;
@@ -528,8 +532,8 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
                     todo.push_back(std::move(pp));
                     continue;
                 }
-                if (a2.b != kBatchRegTile) return set_error(CFH_E_INVAL, "cfh_batch_create: register tile size");
-                const int id = new_pass(kPassFwd, kBatchRegTile, pp.outer_mask, pp.v, 0, (int)pp.rots.size(),
+                if (a2.b != B->reg_bits) return set_error(CFH_E_INVAL, "cfh_batch_create: register tile size");
+                const int id = new_pass(kPassFwd, B->reg_bits, pp.outer_mask, pp.v, 0, (int)pp.rots.size(),
                                         first_pass ? kFlagInit | kFlagStart : 0);
                 B->passes[id].p2 = (int)pa.size();
                 B->passes[id].nitems = nitems2;
@@ -565,7 +569,7 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
                     rd.k = a2.rot[t].k;
                     rots.push_back(rd);
                 }
-                const int id = new_pass(kPassAdj, kBatchRegTile, pp.outer_mask, pp.v, first, nr, 0);
+                const int id = new_pass(kPassAdj, B->reg_bits, pp.outer_mask, pp.v, first, nr, 0);
                 B->passes[id].p2 = (int)pa.size();
                 B->passes[id].nitems = nitems2;
                 B->passes[id].tiles_per_item = tpi2;
@@ -628,7 +632,7 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
             // forward runs, H psi passes (psi and lam in registers; anchored,
             // half-tile transposes at complex128) for gradient runs
             cfh_tuning t3{};
-            t3.tile_bits = kBatchRegTile;
+            t3.tile_bits = B->reg_bits;
             const TuningResolved tm = resolve_tuning(&t3, d.n, dtype, kTuneMeasure);
             std::vector<HamGroup> mgr;
             for (const HamGroup &g : groups)
@@ -670,8 +674,8 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
                         todo.push_back(std::move(pp));
                         continue;
                     }
-                    if (a3.b != kBatchRegTile) return set_error(CFH_E_INVAL, "cfh_batch_create: register tile size");
-                    const int id = new_pass(ham ? kPassHam : kPassMeas, kBatchRegTile, pp.outer_mask, pp.v, 0,
+                    if (a3.b != B->reg_bits) return set_error(CFH_E_INVAL, "cfh_batch_create: register tile size");
+                    const int id = new_pass(ham ? kPassHam : kPassMeas, B->reg_bits, pp.outer_mask, pp.v, 0,
                                             (int)pp.rots.size(), ids.empty() ? 0 : kFlagAccumulate);
                     B->passes[id].p2 = (int)pa.size();
                     B->passes[id].nitems = nitems2;
@@ -907,20 +911,20 @@ cfh_status cfh_batch_run(cfh_batch b, int with_grad, void *stream)
                 st = c128 ? launch_level<double2>(b->bmax, n, s, A, it) : launch_level<float2>(b->bmax, n, s, A, it);
                 break;
             case kKernFwd2:
-                st = c128 ? launch_batch_fwd2<double2>(n, s, A, b->d_pa, it)
-                          : launch_batch_fwd2<float2>(n, s, A, b->d_pa, it);
+                st = c128 ? launch_batch_fwd2<double2>(b->reg_bits, n, s, A, b->d_pa, it)
+                          : launch_batch_fwd2<float2>(b->reg_bits, n, s, A, b->d_pa, it);
                 break;
             case kKernAdj2:
-                st = c128 ? launch_batch_adj2<double2>(n, s, A, b->d_pa, it)
-                          : launch_batch_adj2<float2>(n, s, A, b->d_pa, it);
+                st = c128 ? launch_batch_adj2<double2>(b->reg_bits, n, s, A, b->d_pa, it)
+                          : launch_batch_adj2<float2>(b->reg_bits, n, s, A, b->d_pa, it);
                 break;
             case kKernMeas2:
-                st = c128 ? launch_batch_meas2<double2>(n, s, A, b->d_pa, it)
-                          : launch_batch_meas2<float2>(n, s, A, b->d_pa, it);
+                st = c128 ? launch_batch_meas2<double2>(b->reg_bits, n, s, A, b->d_pa, it)
+                          : launch_batch_meas2<float2>(b->reg_bits, n, s, A, b->d_pa, it);
                 break;
             default:
-                st = c128 ? launch_batch_ham2<double2>(n, s, A, b->d_pa, it)
-                          : launch_batch_ham2<float2>(n, s, A, b->d_pa, it);
+                st = c128 ? launch_batch_ham2<double2>(b->reg_bits, n, s, A, b->d_pa, it)
+                          : launch_batch_ham2<float2>(b->reg_bits, n, s, A, b->d_pa, it);
                 break;
             }
             if (st) return st;

@@ -70,49 +70,49 @@ struct BatchArgs {
 // 2^(b-4) threads per item, every item a range of cosets of one pass whose
 // PassArgs2 is pa[passes[item.pass].p2].  The first pass of a circuit builds
 // its basis state instead of reading psi.
-constexpr int kBatchRegTile = 12;
+constexpr int kBatchRegTile = 12;  // default register tile (tuning reg_tile_bits)
 // Complex128 items transpose in two halves through half the LDS (anchored
 // micro-groups), so as many workgroups fit on a CU as complex64 ones do with
 // whole-tile transposes.
 constexpr bool batch_fwd_half(int amp_bytes) { return amp_bytes == 16; }
 template <typename Amp>
-cfh_status launch_batch_fwd2(unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,
+cfh_status launch_batch_fwd2(int reg_bits, unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,
                              const BItem *items);
-extern template cfh_status launch_batch_fwd2<double2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
+extern template cfh_status launch_batch_fwd2<double2>(int, unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
                                                       const BItem *);
-extern template cfh_status launch_batch_fwd2<float2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
+extern template cfh_status launch_batch_fwd2<float2>(int, unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
                                                      const BItem *);
 
 // Register-tiled read-only measurement items (forward runs): each adds its
 // share of sum_k w_k <psi|P_k|psi> over its cosets to its energy partial
 // (assigned by the first measurement pass of the circuit, added by the rest).
 template <typename Amp>
-cfh_status launch_batch_meas2(unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,
+cfh_status launch_batch_meas2(int reg_bits, unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,
                               const BItem *items);
-extern template cfh_status launch_batch_meas2<double2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
+extern template cfh_status launch_batch_meas2<double2>(int, unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
                                                        const BItem *);
-extern template cfh_status launch_batch_meas2<float2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
+extern template cfh_status launch_batch_meas2<float2>(int, unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
                                                       const BItem *);
 
 // Register-tiled H psi items (gradient runs): lam (+)= sum_k w_k P_k psi on
 // the pass's terms; the circuit's last such pass also writes the energy
 // partials Re <psi|lam> of its items.
 template <typename Amp>
-cfh_status launch_batch_ham2(unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,
+cfh_status launch_batch_ham2(int reg_bits, unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,
                              const BItem *items);
-extern template cfh_status launch_batch_ham2<double2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
+extern template cfh_status launch_batch_ham2<double2>(int, unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
                                                       const BItem *);
-extern template cfh_status launch_batch_ham2<float2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
+extern template cfh_status launch_batch_ham2<float2>(int, unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
                                                      const BItem *);
 
 // Register-tiled adjoint items of one level (half-tile transposes of psi and
 // lam): gradient partials per item as the LDS-staged adjoint items write them.
 template <typename Amp>
-cfh_status launch_batch_adj2(unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,
+cfh_status launch_batch_adj2(int reg_bits, unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,
                              const BItem *items);
-extern template cfh_status launch_batch_adj2<double2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
+extern template cfh_status launch_batch_adj2<double2>(int, unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
                                                       const BItem *);
-extern template cfh_status launch_batch_adj2<float2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
+extern template cfh_status launch_batch_adj2<float2>(int, unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
                                                      const BItem *);
 
 } // namespace cfh

@@ -474,11 +474,10 @@ cfh_status set_lds_limit(KernelFn fn, const char *what)
 
 namespace cfh {
 
-template <typename Amp>
-cfh_status launch_batch_fwd2(unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,
+template <typename Amp, int B>
+cfh_status launch_batch_fwd2_b(unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,
                              const BItem *items)
 {
-    constexpr int B = kBatchRegTile;
     constexpr int T = 1 << (B - kRegDims);
     constexpr bool HALF = batch_fwd_half((int)sizeof(Amp));
     constexpr size_t lds = ((size_t)1 << (HALF ? B - 1 : B)) * sizeof(Amp);
@@ -491,11 +490,10 @@ cfh_status launch_batch_fwd2(unsigned grid, hipStream_t s, const BatchArgs &A, c
     return last_launch("k_batch_fwd2");
 }
 
-template <typename Amp>
-cfh_status launch_batch_meas2(unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,
+template <typename Amp, int B>
+cfh_status launch_batch_meas2_b(unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,
                               const BItem *items)
 {
-    constexpr int B = kBatchRegTile;
     constexpr int T = 1 << (B - kRegDims);
     constexpr size_t lds = ((size_t)1 << B) * sizeof(Amp);
     static bool attr = false;
@@ -507,11 +505,10 @@ cfh_status launch_batch_meas2(unsigned grid, hipStream_t s, const BatchArgs &A, 
     return last_launch("k_batch_meas2");
 }
 
-template <typename Amp>
-cfh_status launch_batch_ham2(unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,
+template <typename Amp, int B>
+cfh_status launch_batch_ham2_b(unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,
                              const BItem *items)
 {
-    constexpr int B = kBatchRegTile;
     constexpr int T = 1 << (B - kRegDims);
     constexpr bool HALF = batch_fwd_half((int)sizeof(Amp));
     // psi and lam buffers: half tiles at complex128, whole tiles at complex64
@@ -525,11 +522,10 @@ cfh_status launch_batch_ham2(unsigned grid, hipStream_t s, const BatchArgs &A, c
     return last_launch("k_batch_ham2");
 }
 
-template <typename Amp>
-cfh_status launch_batch_adj2(unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,
+template <typename Amp, int B>
+cfh_status launch_batch_adj2_b(unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,
                              const BItem *items)
 {
-    constexpr int B = kBatchRegTile;
     constexpr int T = 1 << (B - kRegDims);
     constexpr bool HALF = batch_fwd_half((int)sizeof(Amp));
     // psi and lam buffers: half tiles at complex128, whole tiles at complex64
@@ -543,21 +539,69 @@ cfh_status launch_batch_adj2(unsigned grid, hipStream_t s, const BatchArgs &A, c
     return last_launch("k_batch_adj2");
 }
 
-template cfh_status launch_batch_fwd2<double2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
-                                               const BItem *);
-template cfh_status launch_batch_fwd2<float2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
-                                              const BItem *);
-template cfh_status launch_batch_meas2<double2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
-                                                const BItem *);
-template cfh_status launch_batch_meas2<float2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
-                                               const BItem *);
-template cfh_status launch_batch_ham2<double2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
-                                               const BItem *);
-template cfh_status launch_batch_ham2<float2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
-                                              const BItem *);
-template cfh_status launch_batch_adj2<double2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
-                                               const BItem *);
-template cfh_status launch_batch_adj2<float2>(unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
-                                              const BItem *);
+template <typename Amp>
+cfh_status launch_batch_fwd2(int reg_bits, unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,
+                             const BItem *items)
+{
+    switch (reg_bits) {
+    case 11: return launch_batch_fwd2_b<Amp, 11>(grid, s, A, pa, items);
+    case 12: return launch_batch_fwd2_b<Amp, 12>(grid, s, A, pa, items);
+    case 13: return launch_batch_fwd2_b<Amp, 13>(grid, s, A, pa, items);
+    default: return set_error(CFH_E_UNSUPPORTED, "batched register tile must be 2^11..2^13");
+    }
+}
+
+template <typename Amp>
+cfh_status launch_batch_meas2(int reg_bits, unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,
+                             const BItem *items)
+{
+    switch (reg_bits) {
+    case 11: return launch_batch_meas2_b<Amp, 11>(grid, s, A, pa, items);
+    case 12: return launch_batch_meas2_b<Amp, 12>(grid, s, A, pa, items);
+    case 13: return launch_batch_meas2_b<Amp, 13>(grid, s, A, pa, items);
+    default: return set_error(CFH_E_UNSUPPORTED, "batched register tile must be 2^11..2^13");
+    }
+}
+
+template <typename Amp>
+cfh_status launch_batch_ham2(int reg_bits, unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,
+                             const BItem *items)
+{
+    switch (reg_bits) {
+    case 11: return launch_batch_ham2_b<Amp, 11>(grid, s, A, pa, items);
+    case 12: return launch_batch_ham2_b<Amp, 12>(grid, s, A, pa, items);
+    case 13: return launch_batch_ham2_b<Amp, 13>(grid, s, A, pa, items);
+    default: return set_error(CFH_E_UNSUPPORTED, "batched register tile must be 2^11..2^13");
+    }
+}
+
+template <typename Amp>
+cfh_status launch_batch_adj2(int reg_bits, unsigned grid, hipStream_t s, const BatchArgs &A, const PassArgs2 *pa,
+                             const BItem *items)
+{
+    switch (reg_bits) {
+    case 11: return launch_batch_adj2_b<Amp, 11>(grid, s, A, pa, items);
+    case 12: return launch_batch_adj2_b<Amp, 12>(grid, s, A, pa, items);
+    case 13: return launch_batch_adj2_b<Amp, 13>(grid, s, A, pa, items);
+    default: return set_error(CFH_E_UNSUPPORTED, "batched register tile must be 2^11..2^13");
+    }
+}
+
+template cfh_status launch_batch_fwd2<double2>(int, unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
+                                             const BItem *);
+template cfh_status launch_batch_fwd2<float2>(int, unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
+                                             const BItem *);
+template cfh_status launch_batch_meas2<double2>(int, unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
+                                             const BItem *);
+template cfh_status launch_batch_meas2<float2>(int, unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
+                                             const BItem *);
+template cfh_status launch_batch_ham2<double2>(int, unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
+                                             const BItem *);
+template cfh_status launch_batch_ham2<float2>(int, unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
+                                             const BItem *);
+template cfh_status launch_batch_adj2<double2>(int, unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
+                                             const BItem *);
+template cfh_status launch_batch_adj2<float2>(int, unsigned, hipStream_t, const BatchArgs &, const PassArgs2 *,
+                                             const BItem *);
 
 } // namespace cfh

@@ -33,3 +33,23 @@ def test_tune_batch_returns_accepted_tuning(tmp_path, monkeypatch):
     cands = [{"tile_bits": 9, "batch_items": 8}, {"tile_bits": 10, "batch_items": 32}]
     best = autotune.tune_batch(ws, torch.complex128, candidates=cands)
     assert best in cands
+
+
+def test_batch_candidates_change_the_schedule():
+    """The batch autotuner's axes are live: the register tile changes how many
+    cosets (work items) a pass has and how far rotations fuse, and the fusion
+    depth cap changes the pass count."""
+    ws = W.batched_configs(seed=2, count=4, n_range=(13, 15), r_range=(200, 300), n_ham=20)
+    info = {}
+    for rb in (11, 12, 13):
+        for mr in (8, 32):
+            B = hybrid.Batch(ws, torch.complex128, {"reg_tile_bits": rb, "max_run": mr})
+            info[rb, mr] = B.info()
+    for rb in (11, 12, 13):
+        assert info[rb, 8]["n_passes"] > info[rb, 32]["n_passes"]
+    assert len({info[rb, 32]["n_passes"] for rb in (11, 12, 13)}) == 3
+    assert len({info[rb, 32]["bytes_fwd"] for rb in (11, 12, 13)}) == 3
+    cands = autotune.batch_candidates(torch.complex128)
+    assert {c["reg_tile_bits"] for c in cands} == {11, 12, 13} and {c["max_run"] for c in cands} == {8, 32}
+    with pytest.raises(cfh.CfhError):
+        hybrid.Batch(ws, torch.complex128, {"reg_tile_bits": 14})

@@ -117,6 +117,30 @@ def test_batch_c64_gradients_vs_oracle_parameter_shift():
         assert np.abs(r["grad"][i] - ps).max() <= 1e-4 * scale, i
 
 
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 1e-4)])
+@pytest.mark.parametrize("reg_bits,max_run", [(11, 32), (13, 32), (12, 6)])
+def test_batch_register_tile_and_fusion_depth_vs_oracle(dtype, tol, reg_bits, max_run):
+    """The tunable register tile (2^11 / 2^13 amplitudes) and fusion depth cap:
+    states and energies against the oracle, and (complex128) gradients against
+    the oracle's parameter shift; circuits from 11 to 15 qubits straddle the
+    tile size, so both the register-tiled and the LDS-staged passes run."""
+    ws = [W.make_workload(f"rt{i}", n, seed=600 + i, n_prefix=2 * n, n_rot=r, n_ham=18)
+          for i, (n, r) in enumerate(((11, 50), (12, 70), (13, 60), (15, 90)))]
+    B = hybrid.Batch(ws, dtype, {"reg_tile_bits": reg_bits, "max_run": max_run, "batch_items": 4})
+    B.run(with_grad=False)
+    r = B.results()
+    for i, w in enumerate(ws):
+        psi, phi = sim.simulate(w)
+        got = B.state(i).cpu().to(torch.complex128).numpy()
+        assert np.abs(got - phi).max() <= tol, i
+        assert abs(r["energy"][i] - sim.energy(psi, w.n, w.ham, w.coeff)) <= tol * np.abs(w.coeff).sum(), i
+    if dtype == torch.complex128:
+        B.run(with_grad=True)
+        r = B.results()
+        for i, w in enumerate(ws[:3]):
+            assert np.abs(r["grad"][i] - sim.param_shift_grad(w)).max() <= 1e-10, i
+
+
 def test_batch_matches_single_circuit_path():
     ws = W.batched_configs(seed=3, count=8, n_range=(12, 16), r_range=(100, 300), n_ham=40)
     B = hybrid.Batch(ws, torch.complex128)
