@@ -629,7 +629,7 @@ cfh_status launch_ham(int b, uint64_t ntiles, unsigned grid, hipStream_t s, cons
     switch (b) {
 #define CFH_HAM_CASE(BB)                                                                                   \
     case BB:                                                                                               \
-        if constexpr (fits_lds<Amp, BB>(1)) {                                                              \
+        if constexpr (fits_lds<Amp, BB>(1) && BB <= 13) {                                                  \
             if (out)                                                                                       \
                 hipLaunchKernelGGL((k_ham_apply<Amp, BB>), dim3((unsigned)ntiles), dim3(threads_for(BB)), 0, s, \
                                    psi, out, a, gr, tm, accumulate);                                       \
@@ -992,8 +992,9 @@ cfh_status cfh_plan_create(int n, int dtype, const cfh_pauli *rot, size_t m, con
     // keeps the LDS-staged adjoint.
     if (p->tu.variant != 1 && !p->rot.empty()) {
         TuningResolved t2 = resolve_tuning(tuning, n, dtype, kTuneAdjoint2);
-        // two half-tile LDS buffers (psi and lam): at most 2^13 complex128 / 2^14 complex64
-        t2.tile_bits = std::min(t2.tile_bits, dtype == CFH_C128 ? 13 : 14);
+        // psi and lam of 16 amplitudes each per thread: at 2^14 the 1,024-thread
+        // workgroups cannot hold them without spilling, so 2^13 at most
+        t2.tile_bits = std::min(t2.tile_bits, 13);
         if (t2.tile_bits < n) t2.low_bits = std::min(t2.low_bits, t2.tile_bits - 1);
         if (t2.tile_bits >= 10 && t2.tile_bits <= 14) {
             t2.unfused = 0;
@@ -1148,8 +1149,9 @@ cfh_status cfh_ham_create(int n, int dtype, const cfh_pauli *terms, const double
     h->tu = resolve_tuning(tuning, n, dtype, kTuneHamiltonian);
     {
         // the LDS-staged passes (H psi, and <H> below 2^10) hold a whole tile
-        // in LDS: 2^13 complex128 / 2^14 complex64 amplitudes at most
-        const int lcap = dtype == CFH_C128 ? 13 : 14;
+        // in LDS: 2^13 amplitudes at most (2^14 complex64 would fit LDS, but
+        // its 1,024-thread workgroups cannot hold the kernel's registers)
+        const int lcap = 13;
         if (h->tu.tile_bits > lcap) h->tu.tile_bits = lcap;
         if (h->tu.tile_bits < n) h->tu.low_bits = std::min(h->tu.low_bits, h->tu.tile_bits - 1);
     }
@@ -1220,7 +1222,9 @@ cfh_status cfh_ham_create(int n, int dtype, const cfh_pauli *terms, const double
             // registers, both moved through half-tile LDS buffers, so the tile is
             // at most 2^13 complex128 / 2^14 complex64
             TuningResolved th = tm;
-            th.tile_bits = std::min(tm.tile_bits, dtype == CFH_C128 ? 13 : 14);
+            // (2^13 at both storage types: at 2^14 the 1,024-thread workgroups
+            // cannot hold psi and lam of 16 amplitudes each without spilling)
+            th.tile_bits = std::min(tm.tile_bits, 13);
             // two vectors per workgroup, as in the adjoint: at least 256 tiles
             th.tile_bits = std::min(th.tile_bits, std::max(n - 8, std::min(n, 10)));
             if (th.tile_bits < n) th.low_bits = std::min(th.low_bits, th.tile_bits - 1);

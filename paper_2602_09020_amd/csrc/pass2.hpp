@@ -902,8 +902,7 @@ cfh_status launch_ham2(uint64_t ntiles, hipStream_t s, const Amp *psi, Amp *lam,
     case 11: return launch_ham2_b<Amp, 11>(ntiles, s, psi, lam, mw, a, accumulate);
     case 12: return launch_ham2_b<Amp, 12>(ntiles, s, psi, lam, mw, a, accumulate);
     case 13: return launch_ham2_b<Amp, 13>(ntiles, s, psi, lam, mw, a, accumulate);
-    case 14: return launch_ham2_b<Amp, 14>(ntiles, s, psi, lam, mw, a, accumulate);
-    default: return set_error(CFH_E_UNSUPPORTED, "register-tiled H psi needs tile_bits in 10..14");
+    default: return set_error(CFH_E_UNSUPPORTED, "register-tiled H psi needs tile_bits in 10..13");
     }
 }
 
@@ -918,11 +917,8 @@ cfh_status launch_adj2(uint64_t ntiles, hipStream_t s, Amp *psi, Amp *lam, const
                     : launch_adj2_b<Amp, BB, false>(ntiles, s, psi, lam, coef, a, gpart, max_grid, grad);
         CFH_ADJ2_CASE(10) CFH_ADJ2_CASE(11) CFH_ADJ2_CASE(12) CFH_ADJ2_CASE(13)
 #undef CFH_ADJ2_CASE
-    case 14:
-        if (half) return launch_adj2_b<Amp, 14, true>(ntiles, s, psi, lam, coef, a, gpart, max_grid, grad);
-        return set_error(CFH_E_UNSUPPORTED, "register-tiled adjoint: tile_bits 14 needs half-tile transposes");
     default:
-        return set_error(CFH_E_UNSUPPORTED, "register-tiled adjoint needs tile_bits in 10..14");
+        return set_error(CFH_E_UNSUPPORTED, "register-tiled adjoint needs tile_bits in 10..13");
     }
 }
 

@@ -25,7 +25,7 @@ TuningResolved resolve_tuning(const cfh_tuning *t, int n, int dtype, int kind)
     int b = c64 ? 13 : 14;
     if (kind == kTuneAdjoint) b = c64 ? 12 : 11;
     if (kind == kTuneHamiltonian) b = c64 ? 13 : 12;
-    if (kind == kTuneAdjoint2) b = c64 ? 14 : 13;
+    if (kind == kTuneAdjoint2) b = 13;
     // read-only <H> passes at complex128: 2^13 tiles with half-tile
     // transposes leave LDS for two workgroups per CU, which overlap one
     // workgroup's loads with the other's term sums (28 qubits, 2,000 terms:
