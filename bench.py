@@ -543,6 +543,29 @@ def main():
             res["cache_groups"] = B.info()["n_groups"]
             res["tune_s"] = tune_s
             res["state_gb"] = B.info()["state_bytes"] / 1e9
+            del B
+            torch.cuda.empty_cache()
+            # the same batch as one persistent kernel per run (reset kernel +
+            # persistent kernel in the captured graph), whichever schedule won
+            tp = dict(tu, variant=1, reg_tile_bits=12, batch_items=32)
+            B = hybrid.Batch(ws, dt, tp)
+            pres = {"tuning": tp}
+            for wg in (False, True):
+                B.graph_launch(wg, s2)
+                B.results(stream=s2)
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(s2)
+                B.graph_launch(wg, s2)
+                b.record(s2)
+                r = B.results(stream=s2)
+                ms = a.elapsed_time(b)
+                lat = (r["t_end"].astype(np.float64) - r["t_start"].astype(np.float64)) / r["tick_hz"] * 1e3
+                rots = out["batched"]["rotations"] * (2 if wg else 1)
+                pres["forward_and_adjoint" if wg else "forward"] = {
+                    "ms": ms, "rotations_per_s": rots / (ms * 1e-3),
+                    "p50_circuit_ms": float(np.percentile(lat, 50)), "p99_circuit_ms": float(np.percentile(lat, 99))}
+            pres["grid"] = cfh.cfh_batch_persist_info(B.h)["grid"]
+            res["persistent"] = pres
             out["batched"][tag] = res
             del B
             torch.cuda.empty_cache()

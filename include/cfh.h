@@ -54,7 +54,8 @@ enum {
     CFH_E_NOT_HERMITIAN = -3, /* odd phase exponent where a Hermitian operator is required */
     CFH_E_NOMEM = -4,         /* host or device allocation failed */
     CFH_E_HIP = -5,           /* a HIP runtime call failed; message in cfh_last_error() */
-    CFH_E_UNSUPPORTED = -6    /* n or dtype outside what the library supports */
+    CFH_E_UNSUPPORTED = -6,   /* n or dtype outside what the library supports */
+    CFH_E_TIMEOUT = -7        /* a persistent batched run gave up waiting (cfh_batch_results) */
 };
 
 typedef enum { CFH_C64 = 0, CFH_C128 = 1 } cfh_dtype;
@@ -424,11 +425,15 @@ typedef struct cfh_circuit_desc {
  * circuits, and every circuit under variant 2, use LDS-staged passes on tiles
  * of 2^min(n, tile_bits) amplitudes (default 2^10) only.  Passes are cut
  * into at most tuning->batch_items work items each and queued level by level
- * across circuits.  States, angles, gradients, partial sums and the
- * work-item tables live in one library-owned device allocation.  tuning may be NULL.
+ * across circuits.  Variant 1 plans the same register-tiled passes and runs
+ * each run as one persistent kernel (see cfh_batch_run); it needs every
+ * circuit to have n >= the register tile and at least one rotation.  States,
+ * angles, gradients, partial sums and the work-item tables live in one
+ * library-owned device allocation.  tuning may be NULL.
  * Errors: CFH_E_INVAL, CFH_E_RANGE, CFH_E_NOT_HERMITIAN, CFH_E_UNSUPPORTED
  * (n outside 8..30, tile_bits outside 8..11 for c128 or 8..12 for c64,
- * variant other than 0 or 2), CFH_E_NOMEM, CFH_E_HIP. */
+ * reg_tile_bits outside 11..13, variant outside 0..2, a variant-1 circuit
+ * below the register tile), CFH_E_NOMEM, CFH_E_HIP. */
 cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, const cfh_tuning *tuning,
                             cfh_batch *out);
 cfh_status cfh_batch_destroy(cfh_batch b);
@@ -456,10 +461,56 @@ cfh_status cfh_batch_set_theta(cfh_batch b, const double *theta_host);
  * waits for another, and there is no device queue and no time-out.
  * Asynchronous; allocates nothing and calls no memset, so it can be captured
  * in a hipGraph (cfh_batch_graph_launch).  Runs on one batch must not overlap
- * in time, since they share its device buffers.  Errors: CFH_E_INVAL (null
- * batch), CFH_E_UNSUPPORTED (a tile size the kernels were not built for),
- * CFH_E_HIP (a launch failed; the message is in cfh_last_error). */
+ * in time, since they share its device buffers.
+ *
+ * A variant-1 batch enqueues two kernels instead: one that clears the run's
+ * per-pass counters, control words and timestamps and computes the
+ * (cos, sin) table, then one persistent kernel on the workgroups the device
+ * keeps resident.  Its workgroups take work items from one device counter in
+ * a fixed claim order in which every item follows all items of the pass
+ * before it in its circuit's chain; a workgroup waits (agent-scope acquire)
+ * until that pass is marked ready, runs the item, publishes its stores
+ * (agent-scope release) and counts it; the workgroup that finishes a pass
+ * reduces its partial sums in the same fixed order as the level launches
+ * and marks it ready.  Energies and gradients are therefore bitwise equal to
+ * those of variant 0 with the same tuning.  Since items are claimed in that
+ * order and only by running workgroups, the run completes whatever number
+ * of workgroups is resident.  Each wait is bounded (2 s of device wall clock
+ * by default, cfh_batch_persist_config); a workgroup whose wait runs out
+ * raises an abort word that makes every workgroup leave, so the kernel always
+ * ends, and cfh_batch_results then reports CFH_E_TIMEOUT.
+ *
+ * Errors: CFH_E_INVAL (null batch), CFH_E_UNSUPPORTED (a tile size the
+ * kernels were not built for), CFH_E_HIP (a launch failed; the message is in
+ * cfh_last_error). */
 cfh_status cfh_batch_run(cfh_batch b, int with_grad, void *stream);
+
+/* Variant-1 batches: a dependency wait gives up after max_wait_s seconds
+ * (0 < max_wait_s <= 600) of device wall clock; hold = 1 makes every wait
+ * need a ready value that is never written, so every run gives up (the
+ * give-up path, for tests); max_grid > 0 runs the persistent kernel on that
+ * many workgroups, which completes whether or not they fit on the device at
+ * once (0: as many as the occupancy calculation says fit).  Drops captured graphs,
+ * which hold the old kernel arguments.  Applies from the next run.
+ * Errors: CFH_E_INVAL, CFH_E_UNSUPPORTED (not a variant-1 batch). */
+cfh_status cfh_batch_persist_config(cfh_batch b, double max_wait_s, int hold, int max_grid);
+
+/* Variant-1 batches: the grid of the last persistent launch (0 before the
+ * first) and the tickets (work items) of a forward and of a gradient run.
+ * Any pointer may be NULL.  Errors: CFH_E_INVAL, CFH_E_UNSUPPORTED. */
+cfh_status cfh_batch_persist_info(cfh_batch b, int32_t *grid, int64_t *tickets_fwd, int64_t *tickets_grad);
+
+/* The claim order that variant-1 runs use, on the host only (no device):
+ * `count` chains of chain_len[c] passes, numbered consecutively chain after
+ * chain; pass p has pass_items[p] >= 1 work items; circ_amps[c] weights a
+ * circuit's passes (2^n).  Writes ticket_pass / ticket_item (sum of
+ * pass_items entries each) and prev (one per pass: the pass before it in its
+ * chain, -1 for a chain's first pass).  Level by level; within a level the
+ * circuits with the most work left (amps x passes left) come first.
+ * Errors: CFH_E_INVAL (null or negative sizes, a pass without items). */
+cfh_status cfh_batch_order(int count, const int32_t *chain_len, const int32_t *pass_items,
+                           const double *circ_amps, int32_t *ticket_pass, int32_t *ticket_item,
+                           int32_t *prev);
 
 /* Capture cfh_batch_run(b, with_grad) into a hipGraph on the first call for
  * that with_grad value, then launch the instantiated graph.  `stream` must
@@ -470,7 +521,8 @@ cfh_status cfh_batch_graph_launch(cfh_batch b, int with_grad, void *stream);
 /* Synchronize `stream`, then copy results to host: energies[count], grads
  * (concatenated per circuit, sum of m), per-circuit device wall-clock stamps
  * t_start[count] / t_end[count] and the clock rate in Hz.  Any output
- * pointer may be NULL. */
+ * pointer may be NULL.  Errors: CFH_E_INVAL, CFH_E_HIP, CFH_E_TIMEOUT (a
+ * variant-1 run gave up waiting; the copied results are incomplete). */
 cfh_status cfh_batch_results(cfh_batch b, double *energies, double *grads, uint64_t *t_start,
                              uint64_t *t_end, double *tick_hz, void *stream);
 

@@ -109,12 +109,21 @@ def tune_plan(n: int, dtype, rot: np.ndarray, theta: np.ndarray, candidates: Opt
 
 
 def batch_candidates(dtype) -> List[dict]:
-    """Register tile (2^11..2^13 amplitudes, for circuits with at least that
-    many qubits) x fusion depth (the most rotations one pass may carry) x work
-    items per pass; the LDS tile of the smaller circuits stays at its default."""
+    """Schedule x register tile x fusion depth x work items per pass.  Level
+    launches (variant 0): register tile 2^11..2^13 amplitudes (for circuits
+    with at least that many qubits) x fusion depth (the most rotations one
+    pass may carry) x work items per pass, the LDS tile of the smaller
+    circuits at its default.  One persistent kernel per run (variant 1, only
+    where every circuit fits the register tile): 2^12 tiles, both depths, 32
+    items per pass (fewer, larger items: each one costs a claim and a
+    device-scope release)."""
     c128 = hybrid.state_dtype(dtype) == _c.CFH_C128
-    return [{"tile_bits": 10 if c128 else 11, "reg_tile_bits": rb, "max_run": mr, "batch_items": it, "group_mib": 0}
-            for rb in (11, 12, 13) for mr in (8, 32) for it in (64, 128)]
+    lb = 10 if c128 else 11
+    levels = [{"variant": 0, "tile_bits": lb, "reg_tile_bits": rb, "max_run": mr, "batch_items": it, "group_mib": 0}
+              for rb in (11, 12, 13) for mr in (8, 32) for it in (64, 128)]
+    persistent = [{"variant": 1, "tile_bits": lb, "reg_tile_bits": 12, "max_run": mr, "batch_items": 32,
+                   "group_mib": 0} for mr in (8, 32)]
+    return levels + persistent
 
 
 def _time_batch(B, with_grad: bool, s, reps: int) -> float:
@@ -134,9 +143,11 @@ def _time_batch(B, with_grad: bool, s, reps: int) -> float:
 
 def tune_batch(workloads, dtype, candidates: Optional[Iterable[dict]] = None, with_grad: bool = True,
                use_cache: bool = True, verbose: bool = False, reps: int = 3) -> Dict:
-    """Fastest batch tuning (register tile, fusion depth, items per pass, LDS
-    tile, cache groups) for a batch of circuits, each candidate timed as the
-    median of ``reps`` replays of its captured graph."""
+    """Fastest batch tuning (schedule, register tile, fusion depth, items per
+    pass, LDS tile, cache groups) for a batch of circuits, each candidate
+    timed as the median of ``reps`` replays of its captured graph; candidates
+    the batch cannot take (a persistent schedule with circuits below the
+    register tile) are skipped."""
     key = _key(f"batch{len(workloads)}", max(w.n for w in workloads), dtype)
     cache = _load() if use_cache else {}
     if use_cache and key in cache:

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("CFH_LIB_PATH") or os.path.join(_HERE, "libcfh.so")
 
 CFH_OK, CFH_E_INVAL, CFH_E_RANGE, CFH_E_NOT_HERMITIAN = 0, -1, -2, -3
-CFH_E_NOMEM, CFH_E_HIP, CFH_E_UNSUPPORTED = -4, -5, -6
+CFH_E_NOMEM, CFH_E_HIP, CFH_E_UNSUPPORTED, CFH_E_TIMEOUT = -4, -5, -6, -7
 CFH_C64, CFH_C128 = 0, 1
 (CFH_GATE_H, CFH_GATE_S, CFH_GATE_SDG, CFH_GATE_X, CFH_GATE_Y, CFH_GATE_Z,
  CFH_GATE_CNOT, CFH_GATE_CZ, CFH_GATE_SWAP, CFH_GATE_RX, CFH_GATE_RY, CFH_GATE_RZ,
@@ -104,6 +104,9 @@ _SIGS = {
     "cfh_batch_graph_launch": (C.c_int32, [_vp, C.c_int, _vp]),
     "cfh_batch_results": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, _P(C.c_double), _vp]),
     "cfh_batch_state": (C.c_int32, [_vp, C.c_int, _vp, _vp]),
+    "cfh_batch_persist_config": (C.c_int32, [_vp, C.c_double, C.c_int, C.c_int]),
+    "cfh_batch_persist_info": (C.c_int32, [_vp, _P(C.c_int32), _P(C.c_int64), _P(C.c_int64)]),
+    "cfh_batch_order": (C.c_int32, [C.c_int, _vp, _vp, _vp, _vp, _vp, _vp]),
 }
 
 
@@ -484,3 +487,27 @@ def cfh_batch_results(b: int, count: int, total_rot: int, stream=None):
 
 def cfh_batch_state(b: int, i: int, dst_dev, stream=None) -> None:
     _call("cfh_batch_state", b, i, _dev_ptr(dst_dev, "dst"), _stream(stream))
+
+
+def cfh_batch_persist_config(b: int, max_wait_s: float = 2.0, hold: bool = False, max_grid: int = 0) -> None:
+    _call("cfh_batch_persist_config", b, float(max_wait_s), int(bool(hold)), int(max_grid))
+
+
+def cfh_batch_persist_info(b: int) -> dict:
+    g, tf, tg = C.c_int32(), C.c_int64(), C.c_int64()
+    _call("cfh_batch_persist_info", b, C.byref(g), C.byref(tf), C.byref(tg))
+    return {"grid": g.value, "tickets_fwd": tf.value, "tickets_grad": tg.value}
+
+
+def cfh_batch_order(chain_len, pass_items, circ_amps):
+    """Claim order of a persistent run on the host: (ticket_pass, ticket_item, prev)."""
+    cl = np.ascontiguousarray(chain_len, dtype=np.int32)
+    pi = np.ascontiguousarray(pass_items, dtype=np.int32)
+    ca = np.ascontiguousarray(circ_amps, dtype=np.float64)
+    nt = int(pi.sum())
+    tp = np.zeros(max(nt, 1), dtype=np.int32)
+    ti = np.zeros(max(nt, 1), dtype=np.int32)
+    pv = np.zeros(max(len(pi), 1), dtype=np.int32)
+    _call("cfh_batch_order", len(cl), cl.ctypes.data, pi.ctypes.data, ca.ctypes.data, tp.ctypes.data,
+          ti.ctypes.data, pv.ctypes.data)
+    return tp[:nt], ti[:nt], pv[:len(pi)]

@@ -15,6 +15,11 @@
 // Kernel boundaries order the levels, so no workgroup ever waits for another.
 // The whole sequence is enqueued by cfh_batch_run and captured once into a
 // hipGraph by cfh_batch_graph_launch.
+//
+// Tuning variant 1 runs the same work items, in one persistent kernel per run
+// instead of one launch per level and kind: resident workgroups claim items in
+// a dependency-respecting order and wait, with bounded waits, only for the
+// pass before an item in its own circuit (k_batch_persist).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -252,45 +257,10 @@ __global__ void __launch_bounds__(kBThreads) k_batch_level(const BatchArgs A, co
 }
 
 // Fixed-order reduction of the per-item partial sums of one pass per workgroup.
-// The items' partials are split over the workgroup (kBThreads / kMaxRun
-// lanes per gradient slot, every lane a strided share of the items) and the
-// lane sums added in a fixed order, so results are bitwise reproducible.
 __global__ void __launch_bounds__(kBThreads) k_batch_reduce(const BatchArgs A, const int *__restrict__ passes)
 {
-    constexpr int LANES = kBThreads / kMaxRun;  // item lanes per gradient slot
     __shared__ double sh[kBThreads];
-    const int t = threadIdx.x;
-    const int p = passes[blockIdx.x];
-    const BPass &P = A.passes[p];
-    const BCirc &C = A.circs[P.circ];
-    if (P.type == kPassAdj) {
-        const int r = t % kMaxRun, lane = t / kMaxRun;
-        double s = 0.0;
-        if (r < P.count)
-            for (int i = lane; i < P.nitems; i += LANES) s += A.gpart[C.gpart_off + (int64_t)i * kMaxRun + r];
-        sh[t] = s;
-        __syncthreads();
-        if (t < P.count) {
-            double g = 0.0;
-            for (int l = 0; l < LANES; ++l) g += sh[l * kMaxRun + t];
-            A.grad[C.theta_off + A.rot[P.first + t].k] = g;
-        }
-        __syncthreads();
-    }
-    if (P.flags & kFlagEnergy) {
-        double s = 0.0;
-        if (t < kMaxRun)
-            for (int i = t; i < P.nitems; i += kMaxRun) s += A.epart[C.epart_off + i];
-        sh[t] = s;
-        __syncthreads();
-        if (t == 0) {
-            double e = 0.0;
-            for (int l = 0; l < kMaxRun; ++l) e += sh[l];
-            A.energy[P.circ] = e;
-        }
-    }
-    const bool ends = A.with_grad ? P.end_flag_grad : (P.flags & kFlagEnd);
-    if (ends && t == 0) A.t_end[P.circ] = wall_clock64();
+    reduce_pass(A, passes[blockIdx.x], sh);
 }
 
 __global__ void k_batch_reset(uint64_t *t_start, uint64_t *t_end, int ncirc)
@@ -299,6 +269,29 @@ __global__ void k_batch_reset(uint64_t *t_start, uint64_t *t_end, int ncirc)
     if (i < ncirc) {
         t_start[i] = 0;
         t_end[i] = 0;
+    }
+}
+
+// Before a persistent run: clear its pass counters, control words and
+// timestamps, and turn the angles into (cos, sin) pairs.
+__global__ void __launch_bounds__(256)
+k_batch_persist_reset(uint32_t *done, uint32_t *ready, int npass, uint32_t *ctl, uint64_t *t_start, uint64_t *t_end,
+                      int ncirc, const double *__restrict__ theta, double2 *__restrict__ coef, int64_t m)
+{
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = i0; i < npass; i += step) {
+        done[i] = 0;
+        ready[i] = 0;
+    }
+    if (i0 < kCtlWords) ctl[i0] = 0;
+    for (int64_t i = i0; i < ncirc; i += step) {
+        t_start[i] = 0;
+        t_end[i] = 0;
+    }
+    for (int64_t k = i0; k < m; k += step) {
+        double sn, cs;
+        sincos(0.5 * theta[k], &sn, &cs);
+        coef[k] = make_double2(cs, sn);
     }
 }
 
@@ -352,6 +345,17 @@ struct cfh_batch_s {
     double2 *d_coef = nullptr;
     void *d_psi = nullptr, *d_lam = nullptr;
     uint64_t *d_tstart = nullptr, *d_tend = nullptr;
+    // persistent runs (tuning variant 1)
+    bool persist = false;
+    BItem *d_tickets[2] = {nullptr, nullptr};  // claim order of the forward / gradient run
+    int32_t *d_prev[2] = {nullptr, nullptr};   // per pass: the pass before it in that run's chain
+    int64_t n_tickets[2] = {0, 0};
+    uint32_t *d_done = nullptr, *d_ready = nullptr, *d_ctl = nullptr;
+    uint64_t max_wait_ticks = 0;  // a dependency wait gives up after this many wall-clock ticks
+    double tick_hz = 1e8;
+    uint32_t need = 1;            // 2: every wait gives up (the give-up path, for tests)
+    int max_grid = 0;             // 0: every resident workgroup
+    int grid_used = 0;
     std::vector<int64_t> psi_off;
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t exec[2] = {nullptr, nullptr};
@@ -398,15 +402,17 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
 {
     if (!out || !circ || count < 1) return set_error(CFH_E_INVAL, "cfh_batch_create: bad arguments");
     if (dtype != CFH_C64 && dtype != CFH_C128) return set_error(CFH_E_UNSUPPORTED, "cfh_batch_create: dtype");
-    if (tuning && tuning->variant != 0 && tuning->variant != 2)
+    if (tuning && (tuning->variant < 0 || tuning->variant > 2))
         return set_error(CFH_E_UNSUPPORTED,
-                         "cfh_batch_create: variant 0 (register-tiled forward passes where n >= 12) or 2 "
-                         "(LDS-staged passes only); the persistent work-queue kernel (1) is disabled");
+                         "cfh_batch_create: variant 0 (level launches, register-tiled passes where n >= the "
+                         "register tile), 1 (one persistent kernel per run, every circuit register-tiled) or 2 "
+                         "(level launches, LDS-staged passes only)");
     std::unique_ptr<cfh_batch_s> B(new (std::nothrow) cfh_batch_s);
     if (!B) return set_error(CFH_E_NOMEM, "cfh_batch_create: host memory");
     B->count = count;
     B->dtype = dtype;
     B->reg_fwd = !(tuning && tuning->variant == 2);
+    B->persist = tuning && tuning->variant == 1;
     B->reg_bits = (tuning && tuning->reg_tile_bits > 0) ? tuning->reg_tile_bits : kBatchRegTile;
     if (B->reg_bits < 11 || B->reg_bits > 13)
         return set_error(CFH_E_UNSUPPORTED, "cfh_batch_create: reg_tile_bits must be in 11..13");
@@ -452,6 +458,9 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
         const int tpi = (int)std::max<uint64_t>(1, (ntiles + max_items - 1) / max_items);
         const int nitems = (int)((ntiles + tpi - 1) / tpi);
         const bool reg = B->reg_fwd && d.n >= B->reg_bits && d.m > 0;
+        if (B->persist && !reg)
+            return set_error(CFH_E_UNSUPPORTED, "cfh_batch_create: a persistent batch needs every circuit on register "
+                                                "tiles (n >= reg_tile_bits and at least one rotation)");
         const uint64_t nt2 = reg ? 1ull << (d.n - B->reg_bits) : 1;
         const int tpi2 = (int)std::max<uint64_t>(1, (nt2 + max_items - 1) / max_items);
         const int nitems2 = (int)((nt2 + tpi2 - 1) / tpi2);
@@ -644,8 +653,8 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
             for (int64_t i = 0; i < d.mh; ++i) tp[i] = Pauli{d.terms[i].x, d.terms[i].z, d.terms[i].e & 3};
             const std::vector<HamPass> mps = plan_hamiltonian(d.n, mgr, tm, kMaxGroupsPerPass, kMaxRun);
             for (const bool ham : {false, true}) {
-                // H psi items use half-tile transposes where the forward items do
-                const bool anchored = ham && batch_fwd_half((int)ab);
+                // measurement and H psi items use half-tile transposes where the forward items do
+                const bool anchored = batch_fwd_half((int)ab);
                 std::vector<int> &ids = ham ? ham2_ids : meas_ids;
                 std::vector<PassPlan> todo;
                 for (const HamPass &mp : mps) {
@@ -772,6 +781,20 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
         for (int k = 0; k < kKernCount; ++k) B->n_items[g] += (int64_t)items[g][k].size();
     }
     B->n_groups = (int)cgroups.size();
+    std::vector<std::pair<int, int>> tickets[2];
+    std::vector<int> prev[2];
+    if (B->persist) {
+        std::vector<int> pitems(B->passes.size());
+        for (size_t p = 0; p < B->passes.size(); ++p) pitems[p] = B->passes[p].nitems;
+        std::vector<double> camps(count);
+        for (int c = 0; c < count; ++c) camps[c] = std::ldexp(1.0, circs[c].n);
+        for (int g = 0; g < 2; ++g) {
+            batch_ticket_order(g ? chain_grad : chain_fwd, pitems, camps, cgroups, tickets[g], prev[g]);
+            B->n_tickets[g] = (int64_t)tickets[g].size();
+            if (B->n_tickets[g] >= (int64_t)INT32_MAX / 2)
+                return set_error(CFH_E_UNSUPPORTED, "cfh_batch_create: too many work items for a persistent run");
+        }
+    }
     // algorithmic bytes: a rotation pass reads and writes psi (the first one
     // only writes), a Hamiltonian pass reads psi and writes lam (and reads it
     // when accumulating), an adjoint pass reads and writes psi and lam
@@ -812,6 +835,15 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
     for (int g = 0; g < 2; ++g)
         for (int k = 0; k < kKernCount; ++k)
             parts.push_back({(void **)&B->d_items[g][k], std::max<size_t>(1, items[g][k].size()) * sizeof(BItem)});
+    if (B->persist) {
+        for (int g = 0; g < 2; ++g) {
+            parts.push_back({(void **)&B->d_tickets[g], std::max<size_t>(1, tickets[g].size()) * sizeof(BItem)});
+            parts.push_back({(void **)&B->d_prev[g], (size_t)npass * sizeof(int32_t)});
+        }
+        parts.push_back({(void **)&B->d_done, (size_t)npass * sizeof(uint32_t)});
+        parts.push_back({(void **)&B->d_ready, (size_t)npass * sizeof(uint32_t)});
+        parts.push_back({(void **)&B->d_ctl, kCtlWords * sizeof(uint32_t)});
+    }
     size_t total = 0;
     for (auto &p : parts) total += (p.second + 255) & ~(size_t)255;
     cfh_status st = CFH_OK;
@@ -838,6 +870,21 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
     for (int g = 0; g < 2; ++g)
         for (int k = 0; k < kKernCount; ++k)
             if (!up(B->d_items[g][k], items[g][k].data(), items[g][k].size() * sizeof(BItem))) return st;
+    if (B->persist) {
+        for (int g = 0; g < 2; ++g) {
+            std::vector<BItem> tk(tickets[g].size());
+            for (size_t k = 0; k < tk.size(); ++k) tk[k] = BItem{tickets[g][k].first, tickets[g][k].second};
+            std::vector<int32_t> pv(prev[g].begin(), prev[g].end());
+            if (!up(B->d_tickets[g], tk.data(), tk.size() * sizeof(BItem)) ||
+                !up(B->d_prev[g], pv.data(), pv.size() * sizeof(int32_t)))
+                return st;
+        }
+        int khz = 0, dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+            B->tick_hz = khz * 1000.0;
+        B->max_wait_ticks = (uint64_t)(kPersistWaitSeconds * B->tick_hz);
+    }
     *out = B.release();
     return CFH_OK;
 }
@@ -871,16 +918,12 @@ cfh_status cfh_batch_set_theta(cfh_batch b, const double *theta_host)
     return st;
 }
 
-cfh_status cfh_batch_run(cfh_batch b, int with_grad, void *stream)
+} // extern "C"
+
+namespace {
+
+BatchArgs batch_args(const cfh_batch_s *b, int g)
 {
-    if (!b) return set_error(CFH_E_INVAL, "cfh_batch_run: null batch");
-    hipStream_t s = (hipStream_t)stream;
-    const int g = with_grad ? 1 : 0;
-    hipLaunchKernelGGL(k_batch_reset, dim3((b->count + 255) / 256), dim3(256), 0, s, b->d_tstart, b->d_tend,
-                       b->count);
-    if (b->total_rot)
-        hipLaunchKernelGGL(k_batch_coef, dim3((unsigned)((b->total_rot + 255) / 256)), dim3(256), 0, s, b->d_theta,
-                           b->d_coef, b->total_rot);
     BatchArgs A;
     std::memset(&A, 0, sizeof(A));
     A.passes = b->d_passes;
@@ -899,6 +942,52 @@ cfh_status cfh_batch_run(cfh_batch b, int with_grad, void *stream)
     A.t_start = b->d_tstart;
     A.t_end = b->d_tend;
     A.with_grad = g;
+    return A;
+}
+
+// One persistent run: a kernel that clears the pass counters, control words
+// and timestamps and computes the (cos, sin) table, then the persistent
+// kernel over every ticket of the run.
+cfh_status run_persistent(cfh_batch_s *b, int g, hipStream_t s)
+{
+    const int npass = (int)b->passes.size();
+    const int64_t span = std::max<int64_t>({(int64_t)npass, (int64_t)b->count, b->total_rot, (int64_t)kCtlWords});
+    const unsigned rgrid = (unsigned)std::min<int64_t>(1024, (span + 255) / 256);
+    hipLaunchKernelGGL(k_batch_persist_reset, dim3(rgrid), dim3(256), 0, s, b->d_done, b->d_ready, npass, b->d_ctl,
+                       b->d_tstart, b->d_tend, b->count, b->d_theta, b->d_coef, b->total_rot);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(CFH_E_HIP, std::string("k_batch_persist_reset: ") + hipGetErrorString(e));
+    PersistArgs Q;
+    Q.tickets = b->d_tickets[g];
+    Q.prev = b->d_prev[g];
+    Q.done = b->d_done;
+    Q.ready = b->d_ready;
+    Q.ctl = b->d_ctl;
+    Q.max_wait = b->max_wait_ticks;
+    Q.nt = (int32_t)b->n_tickets[g];
+    Q.need = b->need;
+    const BatchArgs A = batch_args(b, g);
+    return b->dtype == CFH_C128
+               ? launch_batch_persist<double2>(b->reg_bits, g != 0, b->max_grid, s, A, b->d_pa, Q, &b->grid_used)
+               : launch_batch_persist<float2>(b->reg_bits, g != 0, b->max_grid, s, A, b->d_pa, Q, &b->grid_used);
+}
+
+} // namespace
+
+extern "C" {
+
+cfh_status cfh_batch_run(cfh_batch b, int with_grad, void *stream)
+{
+    if (!b) return set_error(CFH_E_INVAL, "cfh_batch_run: null batch");
+    hipStream_t s = (hipStream_t)stream;
+    const int g = with_grad ? 1 : 0;
+    if (b->persist) return run_persistent(b, g, s);
+    hipLaunchKernelGGL(k_batch_reset, dim3((b->count + 255) / 256), dim3(256), 0, s, b->d_tstart, b->d_tend,
+                       b->count);
+    if (b->total_rot)
+        hipLaunchKernelGGL(k_batch_coef, dim3((unsigned)((b->total_rot + 255) / 256)), dim3(256), 0, s, b->d_theta,
+                           b->d_coef, b->total_rot);
+    const BatchArgs A = batch_args(b, g);
     const bool c128 = b->dtype == CFH_C128;
     for (const auto &L : b->levels[g]) {
         for (int k = 0; k < kKernCount; ++k) {
@@ -983,6 +1072,44 @@ cfh_status cfh_batch_results(cfh_batch b, double *energies, double *grads, uint6
         if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
         *tick_hz = khz * 1000.0;
     }
+    if (b->persist) {
+        uint32_t status = 0;
+        if (!hip_ok(hipMemcpy(&status, b->d_ctl + kCtlStatus, sizeof(status), hipMemcpyDeviceToHost), "copy", &st))
+            return st;
+        if (status)
+            return set_error(CFH_E_TIMEOUT, "cfh_batch_results: the persistent run gave up waiting for a pass; "
+                                            "its results are incomplete");
+    }
+    return CFH_OK;
+}
+
+cfh_status cfh_batch_persist_config(cfh_batch b, double max_wait_s, int hold, int max_grid)
+{
+    if (!b) return set_error(CFH_E_INVAL, "cfh_batch_persist_config: null batch");
+    if (!b->persist) return set_error(CFH_E_UNSUPPORTED, "cfh_batch_persist_config: not a persistent batch");
+    if (!(max_wait_s > 0.0) || max_wait_s > 600.0 || (hold != 0 && hold != 1) || max_grid < 0)
+        return set_error(CFH_E_INVAL, "cfh_batch_persist_config: max_wait_s in (0, 600], hold 0 or 1, max_grid >= 0");
+    b->max_wait_ticks = std::max<uint64_t>(1, (uint64_t)(max_wait_s * b->tick_hz));
+    b->need = hold ? 2u : 1u;
+    b->max_grid = max_grid;
+    // captured graphs hold the old kernel arguments
+    cfh_status st = CFH_OK;
+    for (int i = 0; i < 2; ++i) {
+        if (b->exec[i] && !hip_ok(hipGraphExecDestroy(b->exec[i]), "hipGraphExecDestroy", &st)) return st;
+        if (b->graph[i] && !hip_ok(hipGraphDestroy(b->graph[i]), "hipGraphDestroy", &st)) return st;
+        b->exec[i] = nullptr;
+        b->graph[i] = nullptr;
+    }
+    return CFH_OK;
+}
+
+cfh_status cfh_batch_persist_info(cfh_batch b, int32_t *grid, int64_t *tickets_fwd, int64_t *tickets_grad)
+{
+    if (!b) return set_error(CFH_E_INVAL, "cfh_batch_persist_info: null batch");
+    if (!b->persist) return set_error(CFH_E_UNSUPPORTED, "cfh_batch_persist_info: not a persistent batch");
+    if (grid) *grid = b->grid_used;
+    if (tickets_fwd) *tickets_fwd = b->n_tickets[0];
+    if (tickets_grad) *tickets_grad = b->n_tickets[1];
     return CFH_OK;
 }
 

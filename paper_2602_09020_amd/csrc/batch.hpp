@@ -66,6 +66,83 @@ struct BatchArgs {
     int pad;
 };
 
+// Fixed-order reduction of one finished pass's per-item partial sums, run by
+// one workgroup (any size): gradient slot r of an adjoint pass is split over
+// kBThreads / kMaxRun item lanes, each lane a strided share of the items,
+// and the lane sums are added in a fixed order; an energy pass's item
+// partials likewise.  The circuit's end stamp is taken when its last pass is
+// reduced.  Every schedule reduces this way, so results are bitwise
+// reproducible and equal across schedules.  sh holds kBThreads doubles.
+__device__ inline void reduce_pass(const BatchArgs &A, int p, double *sh)
+{
+    constexpr int LANES = kBThreads / kMaxRun;  // item lanes per gradient slot
+    const int t = threadIdx.x, T = blockDim.x;
+    const BPass &P = A.passes[p];
+    const BCirc &C = A.circs[P.circ];
+    if (P.type == kPassAdj) {
+        for (int v = t; v < kBThreads; v += T) {
+            const int r = v % kMaxRun, lane = v / kMaxRun;
+            double s = 0.0;
+            if (r < P.count)
+                for (int i = lane; i < P.nitems; i += LANES) s += A.gpart[C.gpart_off + (int64_t)i * kMaxRun + r];
+            sh[v] = s;
+        }
+        __syncthreads();
+        if (t < P.count) {
+            double g = 0.0;
+            for (int l = 0; l < LANES; ++l) g += sh[l * kMaxRun + t];
+            A.grad[C.theta_off + A.rot[P.first + t].k] = g;
+        }
+        __syncthreads();
+    }
+    if (P.flags & kFlagEnergy) {
+        for (int v = t; v < kBThreads; v += T) {
+            double s = 0.0;
+            if (v < kMaxRun)
+                for (int i = v; i < P.nitems; i += kMaxRun) s += A.epart[C.epart_off + i];
+            sh[v] = s;
+        }
+        __syncthreads();
+        if (t == 0) {
+            double e = 0.0;
+            for (int l = 0; l < kMaxRun; ++l) e += sh[l];
+            A.energy[P.circ] = e;
+        }
+        __syncthreads();
+    }
+    const bool ends = A.with_grad ? P.end_flag_grad : (P.flags & kFlagEnd);
+    if (ends && t == 0) A.t_end[P.circ] = wall_clock64();
+}
+
+// Persistent runs (tuning variant 1): control words, cleared before each run.
+// A dependency wait gives up after this long by default; a correct run's
+// longest wait is about one pass of its largest circuit (milliseconds).
+constexpr double kPersistWaitSeconds = 2.0;
+enum { kCtlTicket = 0, kCtlAbort = 1, kCtlStatus = 2, kCtlWords = 4 };
+
+struct PersistArgs {
+    const BItem *tickets;   // work items in claim order
+    const int32_t *prev;    // per pass: the pass before it in its circuit's chain, -1 for none
+    uint32_t *done;         // per pass: items finished
+    uint32_t *ready;        // per pass: 1 once its items are finished and its partial sums reduced
+    uint32_t *ctl;          // kCtl* words
+    uint64_t max_wait;      // a dependency wait gives up after this many wall-clock ticks
+    int32_t nt;             // tickets
+    uint32_t need;          // ready value a wait needs: 1 (2 is never written: every wait gives up)
+};
+
+// One launch runs every work item of a forward (grad = false: rotation and
+// measurement passes) or gradient run (rotation, H psi and adjoint passes)
+// on max_grid workgroups (0: as many as fit on the device at once); the grid
+// used is returned in *grid_out.
+template <typename Amp>
+cfh_status launch_batch_persist(int reg_bits, bool grad, int max_grid, hipStream_t s, const BatchArgs &A,
+                                const PassArgs2 *pa, const PersistArgs &Q, int *grid_out);
+extern template cfh_status launch_batch_persist<double2>(int, bool, int, hipStream_t, const BatchArgs &,
+                                                         const PassArgs2 *, const PersistArgs &, int *);
+extern template cfh_status launch_batch_persist<float2>(int, bool, int, hipStream_t, const BatchArgs &,
+                                                        const PassArgs2 *, const PersistArgs &, int *);
+
 // Register-tiled forward rotation items of one level: one workgroup of
 // 2^(b-4) threads per item, every item a range of cosets of one pass whose
 // PassArgs2 is pa[passes[item.pass].p2].  The first pass of a circuit builds

@@ -193,6 +193,15 @@ RotDesc make_rot_desc(const PassPlan &pp, const Pauli &p, int k);
 // anchor: seed every micro-group with the same vector (register dimension 0),
 // so transposes can move the tile through LDS in two halves.
 bool build_pass_args2(const PassPlan &pp, const std::vector<Pauli> &rot, bool inverse, bool anchor, PassArgs2 &a);
+// Claim order of a persistent batched run: cache group by cache group,
+// level by level (pass lv of every circuit of the group whose chain is that
+// long), circuits with the most work left (amplitudes x passes left) first,
+// each pass's work items in index order.  Every item comes after all items of
+// the pass before it in its chain (prev[p], -1 for a chain's first pass), so
+// a schedule that claims tickets in this order never waits on a later one.
+void batch_ticket_order(const std::vector<std::vector<int>> &chains, const std::vector<int> &pass_items,
+                        const std::vector<double> &circ_amps, const std::vector<std::pair<int, int>> &groups,
+                        std::vector<std::pair<int, int>> &tickets, std::vector<int> &prev);
 uint32_t local_coords(const std::vector<uint64_t> &v, uint64_t x, bool *in_span);
 uint32_t local_zmask(const std::vector<uint64_t> &v, uint64_t z);
 

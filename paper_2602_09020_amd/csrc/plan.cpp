@@ -452,9 +452,67 @@ std::vector<int> order_for_microgroups(const std::vector<uint64_t> &basis, const
     return out;
 }
 
+void batch_ticket_order(const std::vector<std::vector<int>> &chains, const std::vector<int> &pass_items,
+                        const std::vector<double> &circ_amps, const std::vector<std::pair<int, int>> &groups,
+                        std::vector<std::pair<int, int>> &tickets, std::vector<int> &prev)
+{
+    tickets.clear();
+    prev.assign(pass_items.size(), -1);
+    for (const auto &cg : groups) {
+        size_t maxlen = 0;
+        for (int c = cg.first; c < cg.second; ++c) maxlen = std::max(maxlen, chains[c].size());
+        std::vector<int> at;
+        for (size_t lv = 0; lv < maxlen; ++lv) {
+            at.clear();
+            for (int c = cg.first; c < cg.second; ++c)
+                if (lv < chains[c].size()) at.push_back(c);
+            // the circuits with the most work left in their chains first
+            std::stable_sort(at.begin(), at.end(), [&](int a, int b) {
+                return circ_amps[a] * (double)(chains[a].size() - lv) > circ_amps[b] * (double)(chains[b].size() - lv);
+            });
+            for (int c : at) {
+                const int p = chains[c][lv];
+                prev[p] = lv ? chains[c][lv - 1] : -1;
+                for (int i = 0; i < pass_items[p]; ++i) tickets.push_back({p, i});
+            }
+        }
+    }
+}
+
 } // namespace cfh
 
 using namespace cfh;
+
+extern "C" cfh_status cfh_batch_order(int count, const int32_t *chain_len, const int32_t *pass_items,
+                                      const double *circ_amps, int32_t *ticket_pass, int32_t *ticket_item,
+                                      int32_t *prev)
+{
+    if (count < 0 || (count && (!chain_len || !circ_amps)))
+        return set_error(CFH_E_INVAL, "cfh_batch_order: null argument");
+    std::vector<std::vector<int>> chains(count);
+    int np = 0;
+    for (int c = 0; c < count; ++c) {
+        if (chain_len[c] < 0) return set_error(CFH_E_INVAL, "cfh_batch_order: negative chain length");
+        for (int i = 0; i < chain_len[c]; ++i) chains[c].push_back(np++);
+    }
+    if (np && (!pass_items || !prev)) return set_error(CFH_E_INVAL, "cfh_batch_order: null argument");
+    std::vector<int> items(pass_items, pass_items + np);
+    int64_t nt = 0;
+    for (int p = 0; p < np; ++p) {
+        if (items[p] < 1) return set_error(CFH_E_INVAL, "cfh_batch_order: a pass without work items");
+        nt += items[p];
+    }
+    if (nt && (!ticket_pass || !ticket_item)) return set_error(CFH_E_INVAL, "cfh_batch_order: null argument");
+    std::vector<std::pair<int, int>> tickets;
+    std::vector<int> pv;
+    batch_ticket_order(chains, items, std::vector<double>(circ_amps, circ_amps + count), {{0, count}}, tickets, pv);
+    for (size_t k = 0; k < tickets.size(); ++k) {
+        ticket_pass[k] = tickets[k].first;
+        ticket_item[k] = tickets[k].second;
+    }
+    for (int p = 0; p < np; ++p) prev[p] = pv[p];
+    return CFH_OK;
+}
 
 extern "C" cfh_status cfh_plan_dry_run(int n, int dtype, const cfh_pauli *rot, size_t m, const cfh_tuning *tuning,
                                        int64_t *n_passes, int64_t *pass_start, int64_t *order)

@@ -51,5 +51,16 @@ def test_batch_candidates_change_the_schedule():
     assert len({info[rb, 32]["bytes_fwd"] for rb in (11, 12, 13)}) == 3
     cands = autotune.batch_candidates(torch.complex128)
     assert {c["reg_tile_bits"] for c in cands} == {11, 12, 13} and {c["max_run"] for c in cands} == {8, 32}
+    assert {c["variant"] for c in cands} == {0, 1}
     with pytest.raises(cfh.CfhError):
         hybrid.Batch(ws, torch.complex128, {"reg_tile_bits": 14})
+
+
+def test_tune_batch_skips_schedules_the_batch_cannot_take(tmp_path, monkeypatch):
+    """A persistent candidate needs every circuit on the register tile: with
+    an 11-qubit circuit in the batch it is skipped, and the level launches win."""
+    monkeypatch.setenv("CFH_TUNING_CACHE", str(tmp_path / "tune.json"))
+    ws = W.batched_configs(seed=3, count=3, n_range=(12, 13), r_range=(40, 60), n_ham=10)
+    ws.append(W.make_workload("n11", 11, seed=4, n_rot=30, n_ham=8))
+    cands = [{"variant": 1, "reg_tile_bits": 12, "batch_items": 32}, {"variant": 0, "reg_tile_bits": 12}]
+    assert autotune.tune_batch(ws, torch.complex128, candidates=cands, use_cache=False) == cands[1]

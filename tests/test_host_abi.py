@@ -219,9 +219,10 @@ def test_planner_rejects_bad_input():
     assert e.value.code == cfh.CFH_E_UNSUPPORTED
 
 
-def test_batch_rejects_disabled_persistent_variant_without_device_work():
-    """The persistent work-queue batch schedule is switched off: asking for it
-    fails in argument checking, before any device allocation."""
+def test_batch_rejects_persistent_variant_below_register_tile_without_device_work():
+    """A persistent batch (variant 1) runs register-tiled passes only: a
+    circuit below the register tile fails in argument checking, before any
+    device allocation."""
     import ctypes as C
     rot = cfh.cfh_pauli_encode(np.array([[1, 3, 1, 0, 0, 0, 0, 0]], np.uint8))
     circ = [{"n": 8, "init_index": 0, "rot": rot, "theta": np.array([0.3]), "terms": rot, "coeff": np.array([1.0])}]
