@@ -108,12 +108,14 @@ def main():
     ap.add_argument("--trotter-steps", type=int, default=10)
     ap.add_argument("--no-extras", action="store_true", help="skip unfused/c64/adjoint/cpu legs")
     ap.add_argument("--cpu-rotations", type=int, default=20)
-    ap.add_argument("--mode", choices=["full", "passes", "expval", "copy", "stream"], default="full",
+    ap.add_argument("--mode", choices=["full", "passes", "expval", "copy", "stream", "batch"], default="full",
                     help="passes: apply the plan of the first --rotations rotations once (for counter runs); "
                          "expval: those rotations, then <H> of the workload's observable --steps times; "
                          "copy: a plain device copy of the same state size (counter and bandwidth calibration); "
-                         "stream: the library's in-place calibration kernel, streamed and in scattered chunks")
+                         "stream: the library's in-place calibration kernel, streamed and in scattered chunks; "
+                         "batch: the 256-circuit batch once per schedule (level launches, persistent kernel)")
     ap.add_argument("--rotations", type=int, default=150)
+    ap.add_argument("--batch-grad", action="store_true", help="--mode batch: gradient runs instead of forward runs")
     ap.add_argument("--chunk", type=int, default=2000, help="rotations planned per plan inside a step")
     ap.add_argument("--dtype", choices=["c128", "c64"], default="c128", help="state storage for --mode passes")
     ap.add_argument("--variant", type=int, default=0, help="fused kernel variant for --mode passes (0 = default)")
@@ -169,6 +171,24 @@ def main():
         plan.apply(psi, theta)
         torch.cuda.synchronize()
         print(json.dumps({"mode": "passes", "rotations": args.rotations, **plan.info()}), flush=True)
+        return
+    if args.mode == "batch":
+        # the 256-circuit batch, one forward (or, with --batch-grad, gradient)
+        # run per schedule: level launches, then one persistent kernel (for
+        # counter collection)
+        bdt = torch.complex128 if args.dtype == "c128" else torch.complex64
+        ws = W.batched_configs()
+        for variant in (0, 1):
+            B = hybrid.Batch(ws, bdt, {"variant": variant, "reg_tile_bits": 12, "max_run": 32, "batch_items": 32})
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            B.run(with_grad=args.batch_grad)
+            b.record()
+            B.results()
+            print(json.dumps({"mode": "batch", "variant": variant, "with_grad": args.batch_grad,
+                              "ms": a.elapsed_time(b)}), flush=True)
+            del B
+            torch.cuda.empty_cache()
         return
     if args.mode == "expval":
         sdt = torch.complex128 if args.dtype == "c128" else torch.complex64
