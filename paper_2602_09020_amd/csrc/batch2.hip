@@ -754,20 +754,20 @@ cfh_status launch_batch_persist_b(int max_grid, hipStream_t s, const BatchArgs &
     constexpr int T = 1 << (B - kRegDims);
     constexpr size_t lds = persist_lds<Amp, B, GRAD>();
     auto kern = &k_batch_persist<Amp, B, GRAD>;
-    static int per_cu = 0, cus = 0;
-    if (!per_cu) {
+    static bool attr = false;
+    if (!attr) {
         if (cfh_status st = set_lds_limit(kern, "k_batch_persist: LDS limit")) return st;
-        cfh_status st = CFH_OK;
-        int dev = 0;
-        if (!hip_ok(hipGetDevice(&dev), "k_batch_persist: hipGetDevice", &st) ||
-            !hip_ok(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "k_batch_persist: CUs",
-                    &st) ||
-            !hip_ok(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kern), T,
-                                                                 lds),
-                    "k_batch_persist: occupancy", &st))
-            return st;
-        if (per_cu < 1 || cus < 1) return set_error(CFH_E_HIP, "k_batch_persist: no resident workgroup fits a CU");
+        attr = true;
     }
+    // the current device's CUs and the workgroups of this kernel that fit on one
+    int per_cu = 0, cus = 0, dev = 0;
+    cfh_status st = CFH_OK;
+    if (!hip_ok(hipGetDevice(&dev), "k_batch_persist: hipGetDevice", &st) ||
+        !hip_ok(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "k_batch_persist: CUs", &st) ||
+        !hip_ok(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kern), T, lds),
+                "k_batch_persist: occupancy", &st))
+        return st;
+    if (per_cu < 1 || cus < 1) return set_error(CFH_E_HIP, "k_batch_persist: no resident workgroup fits a CU");
     // by default the workgroups the occupancy calculation says fit at once;
     // any other grid also completes (items go only to running workgroups)
     int grid = max_grid > 0 ? max_grid : per_cu * cus;
