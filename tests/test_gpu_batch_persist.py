@@ -141,3 +141,57 @@ def test_persistent_rejects_circuits_below_the_register_tile():
     with pytest.raises(cfh.CfhError) as e:
         cfh.cfh_batch_persist_config(B.h, 1.0, False, 0)
     assert e.value.code == cfh.CFH_E_UNSUPPORTED
+
+
+@pytest.fixture(scope="module")
+def full_batch():
+    """The 256-circuit workload the bench times, with three sampled circuits
+    (the 12-qubit one with the fewest rotations, a 16-qubit one, the 20-qubit
+    one with the fewest rotations), their oracle energies, and the oracle's
+    parameter-shift gradient of the 12-qubit one at four seeded indices."""
+    ws = W.batched_configs()
+    ns = np.array([w.n for w in ws])
+    rs = np.array([w.n_rot for w in ws])
+    sample = [int(np.where(ns == 12)[0][np.argmin(rs[ns == 12])]), int(np.where(ns == 16)[0][0]),
+              int(np.where(ns == 20)[0][np.argmin(rs[ns == 20])])]
+    energies = {i: sim.energy_of(ws[i], ws[i].theta) for i in sample}
+    g_idx = np.sort(np.random.default_rng(21).choice(ws[sample[0]].n_rot, size=4, replace=False))
+    grads = sim.param_shift_grad(ws[sample[0]], g_idx)
+    return ws, sample, energies, g_idx, grads
+
+
+@pytest.mark.parametrize("dtype,tol,max_run", [(torch.complex128, 1e-12, 32), (torch.complex64, 1e-4, 8)])
+def test_full_batch_both_schedules_vs_oracle(full_batch, dtype, tol, max_run):
+    """The bench's 256-circuit batch on 2^12 register tiles: the level
+    launches at the bench's 128 items per pass, and both schedules at 32
+    items per pass, which give bitwise the same energies and gradients (the
+    same items and reductions).  For every run: sampled circuits' energies
+    against the oracle (tol times the coefficient sum) and four gradients of
+    the 12-qubit circuit against the oracle's parameter shift (1e-10 at
+    complex128; 1e-4 times the coefficient sum at complex64)."""
+    ws, sample, energies, g_idx, grads = full_batch
+    out = {}
+    for variant, items in ((0, 128), (0, 32), (1, 32)):
+        print(f"full batch variant {variant} {dtype}", flush=True)
+        B = hybrid.Batch(ws, dtype, {"variant": variant, "reg_tile_bits": 12, "max_run": max_run,
+                                     "batch_items": items})
+        B.run(with_grad=False)
+        rf = B.results()
+        B.run(with_grad=True)
+        out[variant, items] = (rf, B.results())
+        del B
+        torch.cuda.empty_cache()
+    for k in (0, 1):
+        r0, r1 = out[0, 32][k], out[1, 32][k]
+        assert np.array_equal(r0["energy"], r1["energy"]), k
+        assert np.all(r1["t_end"] >= r1["t_start"]) and np.all(r1["t_start"] > 0)
+    for a, b in zip(out[0, 32][1]["grad"], out[1, 32][1]["grad"]):
+        assert np.array_equal(a, b)
+    i0 = sample[0]
+    bound = 1e-10 if dtype == torch.complex128 else 1e-4 * np.abs(ws[i0].coeff).sum()
+    for key, (rf, rg) in out.items():
+        for i in sample:
+            scale = np.abs(ws[i].coeff).sum()
+            assert abs(rf["energy"][i] - energies[i]) <= tol * scale, (key, i)
+            assert abs(rg["energy"][i] - energies[i]) <= tol * scale, (key, i)
+        assert np.abs(rg["grad"][i0][g_idx] - grads).max() <= bound, key
