@@ -165,8 +165,9 @@ def prepare(w, dtype=torch.complex128, tuning: Optional[dict] = None, ham_tuning
 
 
 class Batch:
-    """Many independent circuits run together: one kernel launch per pass
-    level, all items of a level in one grid (cfh_batch_*)."""
+    """Many independent circuits run together (cfh_batch_*): by default one
+    kernel launch per pass level and kernel kind, all items of a level in one
+    grid; with tuning {"variant": 1}, one persistent kernel per run."""
 
     def __init__(self, workloads, dtype=torch.complex128, tuning: Optional[dict] = None):
         self.dtype = state_dtype(dtype)
