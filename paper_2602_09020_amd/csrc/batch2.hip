@@ -517,16 +517,19 @@ k_batch_ham2(const BatchArgs A, const PassArgs2 *__restrict__ pa, const BItem *_
 // Wait until *flag >= need.  Thread 0 of a workgroup polls with agent-scope
 // loads (they bypass the XCD's own L2, so a store from any XCD is seen),
 // sleeping between polls.  It gives up after max_ticks of the constant-rate
-// wall clock, or after max_ticks polls (each poll sleeps longer than one
-// tick), whichever comes first, or as soon as another workgroup has given up;
-// a workgroup that gives up raises the abort word and the status word.
+// wall clock (100 MHz), or as soon as another workgroup has given up; as a
+// backstop that does not rely on the clock, also after max_ticks / 8 polls
+// (a poll's sleep alone, 256 shader clocks, outlasts 8 ticks, so this bound
+// lies beyond the clock's).  A workgroup that gives up raises the abort word
+// and the status word.
 __device__ bool wait_ready(const uint32_t *flag, uint32_t need, uint32_t *ctl, uint64_t max_ticks)
 {
     const uint64_t t0 = wall_clock64();
+    const uint64_t max_polls = max_ticks / 8 + 1;
     for (uint64_t polls = 0;; ++polls) {
         if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) return true;
         if (__hip_atomic_load(&ctl[kCtlAbort], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
-        if (polls >= max_ticks || wall_clock64() - t0 >= max_ticks) {
+        if (polls >= max_polls || wall_clock64() - t0 >= max_ticks) {
             __hip_atomic_store(&ctl[kCtlStatus], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&ctl[kCtlAbort], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return false;
