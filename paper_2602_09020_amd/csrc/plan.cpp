@@ -340,9 +340,14 @@ std::vector<HamPass> plan_hamiltonian(int n, const std::vector<HamGroup> &groups
     const int b = tu.tile_bits, c = tu.low_bits;
     const int G = (int)groups.size();
     std::vector<char> done(G, 0);
-    int left = G;
+    // groups not yet placed, ascending: the scans below visit only these
+    std::vector<int> rem(G);
+    std::iota(rem.begin(), rem.end(), 0);
+    // red[g]: groups[g].x reduced against the current span (zero at every
+    // pivot; unique), kept up to date as vectors join the span
+    std::vector<uint64_t> red(G);
     std::vector<HamPass> out;
-    while (left > 0) {
+    while (!rem.empty()) {
         int nterms = 0;
         // Grow a b-dimensional subspace greedily.  Sparse x masks (JW strings)
         // are covered best by whole qubits (unit vectors: one tile then holds
@@ -351,52 +356,78 @@ std::vector<HamPass> plan_hamiltonian(int n, const std::vector<HamGroup> &groups
         // single x adds at most one dimension.
         Span s;
         for (int j = 0; j < c; ++j) s.add(1ull << j);
+        for (const int g : rem) red[g] = s.reduce(groups[g].x);
+        // e: reduced and nonzero; the basis stays reduced, and so does every
+        // red[g].  Groups whose red[g] becomes zero are collected in rem order.
+        std::vector<int> newly;
+        auto add = [&](uint64_t e) {
+            const int p = 63 - __builtin_clzll(e);
+            s.add(e);
+            for (const int g : rem)
+                if ((red[g] >> p) & 1) {
+                    red[g] ^= e;
+                    if (!red[g]) newly.push_back(g);
+                }
+        };
         std::vector<int> chosen;
         std::vector<char> in(G, 0);
         auto fits = [&](int g) { return nterms + (int)groups[g].terms.size() <= max_terms; };
-        auto sweep = [&]() {
-            for (int g = 0; g < G && (int)chosen.size() < max_groups; ++g)
-                if (!done[g] && !in[g] && fits(g) && s.reduce(groups[g].x) == 0) {
-                    in[g] = 1;
-                    chosen.push_back(g);
-                    nterms += (int)groups[g].terms.size();
-                }
+        auto take = [&](int g) {
+            if ((int)chosen.size() < max_groups && !in[g] && fits(g) && red[g] == 0) {
+                in[g] = 1;
+                chosen.push_back(g);
+                nterms += (int)groups[g].terms.size();
+            }
         };
-        sweep();
+        // the groups inside the span, ascending; later sweeps need only the
+        // groups that entered it since, because a group that did not fit
+        // never fits again (nterms only grows)
+        for (const int g : rem) take(g);
+        auto sweep = [&]() {
+            std::sort(newly.begin(), newly.end());
+            for (const int g : newly) take(g);
+            newly.clear();
+        };
         while ((int)chosen.size() < max_groups && nterms < max_terms && s.dim() < b) {
+            // the first group that costs the fewest new dimensions; a group
+            // that fits and costs none was taken by the sweep, so the first
+            // one costing one dimension ends the scan
             int best = -1, best_cost = 1 << 30;
             uint64_t best_r = 0;
-            for (int g = 0; g < G; ++g) {
-                if (done[g] || in[g] || !fits(g)) continue;
-                const uint64_t r = s.reduce(groups[g].x);
+            for (const int g : rem) {
+                if (in[g] || !fits(g)) continue;
+                const uint64_t r = red[g];
                 const int cost = popc(r);
-                if (cost < best_cost) { best_cost = cost; best = g; best_r = r; }
+                if (cost < best_cost) {
+                    best_cost = cost;
+                    best = g;
+                    best_r = r;
+                    if (cost <= 1) break;
+                }
             }
             if (best < 0) break;
             if (best_cost <= b - s.dim()) {
                 for (uint64_t r = best_r; r; r &= r - 1) {
                     const uint64_t e = s.reduce(r & (~r + 1));
-                    if (e) s.add(e);
+                    if (e) add(e);
                 }
             } else {
-                s.add(best_r);
+                add(best_r);
             }
             sweep();
         }
         if (chosen.empty()) {
             // every remaining group is larger than max_terms on its own (the
             // caller splits such groups); take one so the loop always ends
-            for (int g = 0; g < G && chosen.empty(); ++g)
-                if (!done[g]) {
-                    const uint64_t r = s.reduce(groups[g].x);
-                    if (r) s.add(r);
-                    chosen.push_back(g);
-                }
+            const int g = rem.front();
+            if (red[g]) add(red[g]);
+            chosen.push_back(g);
         }
         HamPass hp;
         hp.b = b;
         finish_basis(s, n, b, hp.v, hp.outer_mask);
-        for (int g : chosen) { done[g] = 1; --left; }
+        for (int g : chosen) done[g] = 1;
+        rem.erase(std::remove_if(rem.begin(), rem.end(), [&](int g) { return done[g] != 0; }), rem.end());
         hp.groups = std::move(chosen);
         out.push_back(std::move(hp));
     }
