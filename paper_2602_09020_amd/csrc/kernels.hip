@@ -10,7 +10,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
+#include <string>
+#include <thread>
 #include <tuple>
 #include <memory>
 #include <new>
@@ -804,6 +807,44 @@ cfh_status term_passes(int n, int dtype, const std::vector<HamGroup> &groups, co
     return CFH_OK;
 }
 
+// A planning task run on its own thread, or on the caller's if no thread can
+// be started.  finish() joins it and returns its status, with its error
+// message set again on the calling thread.  The destructor joins a task that
+// was started and not finished (an early return), so no thread outlives the
+// data it reads.
+class PlanJob {
+public:
+    explicit PlanJob(std::function<cfh_status()> f) : f_(std::move(f)) {}
+    ~PlanJob()
+    {
+        if (t_.joinable()) t_.join();
+    }
+    void start()
+    {
+        try {
+            t_ = std::thread([this] { run(); });
+        } catch (...) {
+            run();
+        }
+    }
+    cfh_status finish()
+    {
+        if (t_.joinable()) t_.join();
+        return st_ ? set_error(st_, msg_) : CFH_OK;
+    }
+
+private:
+    void run()
+    {
+        st_ = f_();
+        if (st_) msg_ = cfh_last_error();
+    }
+    std::function<cfh_status()> f_;
+    std::thread t_;
+    cfh_status st_ = CFH_OK;
+    std::string msg_;
+};
+
 unsigned persistent_grid(uint64_t ntiles)
 {
     return (unsigned)std::min<uint64_t>(ntiles, 2048);
@@ -1168,6 +1209,37 @@ cfh_status cfh_ham_create(int n, int dtype, const cfh_pauli *terms, const double
         }
     }
     h->n_groups = (int64_t)groups.size();
+    // The register-tiled term passes (<H>, and H psi for the adjoint) are
+    // planned on two worker threads while this thread plans the LDS-staged
+    // passes: the planners only read the groups and terms, and each writes
+    // its own pass list.  A worker's error message is carried back to this
+    // thread (the message store is per thread).
+    //
+    // <H> on the register-tiled kernel: passes of at most kMaxRun terms on
+    // 2^b tiles (half-tile transposes at 2^14), terms ordered so consecutive
+    // ones share register micro-groups.  The LDS-staged passes stay for H psi
+    // and for tiles below 2^10.
+    const TuningResolved tm = resolve_tuning(tuning, n, dtype, kTuneMeasure);
+    const bool reg = tm.variant != 1 && tm.tile_bits >= 10 && tm.tile_bits <= 14 && m > 0;
+    // half-tile transposes: required at 2^14, the default at complex128,
+    // selectable by variant 5
+    const bool anchor = tm.tile_bits == 14 || tm.variant == 5 || (tm.variant == 0 && dtype == CFH_C128);
+    // H psi (the adjoint's lam) on the same kernel family: psi and lam in
+    // registers, both moved through half-tile LDS buffers, so the tile is at
+    // most 2^13 (at 2^14 the 1,024-thread workgroups cannot hold psi and lam
+    // of 16 amplitudes each without spilling), with at least 256 tiles
+    TuningResolved th = tm;
+    th.tile_bits = std::min(tm.tile_bits, 13);
+    th.tile_bits = std::min(th.tile_bits, std::max(n - 8, std::min(n, 10)));
+    if (th.tile_bits < n) th.low_bits = std::min(th.low_bits, th.tile_bits - 1);
+    std::vector<Pauli> tp(reg ? m : 0);
+    for (size_t i = 0; i < tp.size(); ++i) tp[i] = Pauli{terms[i].x, terms[i].z, terms[i].e & 3};
+    PlanJob jm([&] { return term_passes(n, dtype, groups, tp, tm, anchor, h->margs, "cfh_ham_create"); });
+    PlanJob jh([&] { return term_passes(n, dtype, groups, tp, th, true, h->hargs, "cfh_ham_create"); });
+    if (reg) {
+        jm.start();
+        jh.start();
+    }
     h->passes = plan_hamiltonian(n, groups, h->tu);
     std::vector<HamGroupDev> gdev;
     std::vector<HamTermDev> tdev;
@@ -1204,40 +1276,15 @@ cfh_status cfh_ham_create(int n, int dtype, const cfh_pauli *terms, const double
     }
     cfh_status st = CFH_OK;
     std::vector<double2> mw_host;  // weights of the register-tiled passes' terms
-    // <H> on the register-tiled kernel: passes of at most kMaxRun terms on
-    // 2^b tiles (half-tile transposes at 2^14), terms ordered so consecutive
-    // ones share register micro-groups.  The LDS-staged passes above stay for
-    // H psi and for tiles below 2^10.
-    {
-        TuningResolved tm = resolve_tuning(tuning, n, dtype, kTuneMeasure);
-        if (tm.variant != 1 && tm.tile_bits >= 10 && tm.tile_bits <= 14 && m > 0) {
-            // half-tile transposes: required at 2^14, the default at complex128,
-            // selectable by variant 5
-            const bool anchor = tm.tile_bits == 14 || tm.variant == 5 || (tm.variant == 0 && dtype == CFH_C128);
-            std::vector<Pauli> tp(m);
-            for (size_t i = 0; i < m; ++i) tp[i] = Pauli{terms[i].x, terms[i].z, terms[i].e & 3};
-            st = term_passes(n, dtype, groups, tp, tm, anchor, h->margs, "cfh_ham_create");
-            if (st) return st;
-            // H psi (the adjoint's lam) on the same kernel family: psi and lam in
-            // registers, both moved through half-tile LDS buffers, so the tile is
-            // at most 2^13 complex128 / 2^14 complex64
-            TuningResolved th = tm;
-            // (2^13 at both storage types: at 2^14 the 1,024-thread workgroups
-            // cannot hold psi and lam of 16 amplitudes each without spilling)
-            th.tile_bits = std::min(tm.tile_bits, 13);
-            // two vectors per workgroup, as in the adjoint: at least 256 tiles
-            th.tile_bits = std::min(th.tile_bits, std::max(n - 8, std::min(n, 10)));
-            if (th.tile_bits < n) th.low_bits = std::min(th.low_bits, th.tile_bits - 1);
-            st = term_passes(n, dtype, groups, tp, th, true, h->hargs, "cfh_ham_create");
-            if (st) return st;
-            mw_host.resize(m);
-            for (size_t i = 0; i < m; ++i) {
-                const int wp = (terms[i].e - popc(terms[i].x & terms[i].z)) & 3;  // i^wp
-                mw_host[i] = make_double2(wp == 0 ? coeff[i] : wp == 2 ? -coeff[i] : 0.0,
-                                          wp == 1 ? coeff[i] : wp == 3 ? -coeff[i] : 0.0);
-            }
-            h->mmode = anchor ? 14 : 10;
+    if (reg) {
+        if ((st = jm.finish()) || (st = jh.finish())) return st;
+        mw_host.resize(m);
+        for (size_t i = 0; i < m; ++i) {
+            const int wp = (terms[i].e - popc(terms[i].x & terms[i].z)) & 3;  // i^wp
+            mw_host[i] = make_double2(wp == 0 ? coeff[i] : wp == 2 ? -coeff[i] : 0.0,
+                                      wp == 1 ? coeff[i] : wp == 3 ? -coeff[i] : 0.0);
         }
+        h->mmode = anchor ? 14 : 10;
     }
     // Device calls come only after all host planning: hipMemcpy on the null
     // stream waits for work already queued there, and planning done after it
