@@ -23,11 +23,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <map>
 #include <memory>
 #include <new>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "batch.hpp"
@@ -393,6 +396,220 @@ cfh_status launch_level(int bmax, unsigned grid, hipStream_t s, const BatchArgs 
     return CFH_OK;
 }
 
+// The planning of one circuit of a batch: argument checks, its rotation
+// passes (LDS-staged, or register-tiled with their forward and adjoint kernel
+// descriptors, a run that needs more micro-groups than a pass carries split
+// in two) and its observable's passes.  It depends on nothing but the circuit
+// and the batch settings, so circuits are planned on worker threads; the
+// batch tables are then assembled from these plans in circuit order.
+struct CircPlan {
+    cfh_status st = CFH_OK;
+    std::string msg;
+    std::vector<Pauli> r;                     // rotations
+    TuningResolved tu;                        // LDS-staged tuning
+    int b = 0, tpi = 1, nitems = 1, tpi2 = 1, nitems2 = 1;
+    bool reg = false;                         // register-tiled passes
+    std::vector<PassPlan> fw;                 // LDS-staged forward passes
+    std::vector<std::pair<PassPlan, PassArgs2>> fwd2, adj2, meas2, ham2;  // register-tiled passes, in order
+    std::vector<HamGroup> groups;             // the terms grouped by x mask (first-appearance order)
+    std::vector<HamPass> hp;                  // LDS-staged Hamiltonian passes
+};
+
+struct BatchSettings {
+    int dtype, bmax, reg_bits, max_items;
+    bool reg_fwd, persist;
+    const cfh_tuning *tuning;
+};
+
+void plan_circuit(const cfh_circuit_desc &d, const BatchSettings &S, CircPlan &out)
+{
+    auto fail = [&](cfh_status st) {
+        out.st = st;
+        out.msg = cfh_last_error();
+    };
+    const size_t ab = S.dtype == CFH_C64 ? 8 : 16;
+    const cfh_tuning *tuning = S.tuning;
+    if (d.n < 8 || d.n > 30) return fail(set_error(CFH_E_UNSUPPORTED, "cfh_batch_create: circuit n must be in 8..30"));
+    if ((d.m && (!d.rot || !d.theta)) || (d.mh && (!d.terms || !d.coeff)) || d.m < 0 || d.mh < 0)
+        return fail(set_error(CFH_E_INVAL, "cfh_batch_create: null rotation or term arrays"));
+    if (d.init_index >> d.n) return fail(set_error(CFH_E_RANGE, "cfh_batch_create: init_index >= 2^n"));
+    std::vector<Pauli> &r = out.r;
+    r.resize(d.m);
+    for (int64_t i = 0; i < d.m; ++i) {
+        cfh_status st = check_pauli(d.rot[i], d.n, true, "cfh_batch_create");
+        if (st) return fail(st);
+        r[i] = Pauli{d.rot[i].x, d.rot[i].z, d.rot[i].e & 3};
+    }
+    for (int64_t i = 0; i < d.mh; ++i) {
+        cfh_status st = check_pauli(d.terms[i], d.n, true, "cfh_batch_create");
+        if (st) return fail(st);
+    }
+    cfh_tuning tc{};
+    tc.tile_bits = std::min(S.bmax, d.n);
+    tc.low_bits = tuning && tuning->low_bits > 0 ? tuning->low_bits : 4;
+    tc.max_run = tuning && tuning->max_run > 0 ? tuning->max_run : kMaxRun;
+    out.tu = resolve_tuning(&tc, d.n, S.dtype, kTuneForward);
+    const TuningResolved &tu = out.tu;
+    out.b = tu.tile_bits;
+    const uint64_t ntiles = 1ull << (d.n - out.b);
+    out.tpi = (int)std::max<uint64_t>(1, (ntiles + S.max_items - 1) / S.max_items);
+    out.nitems = (int)((ntiles + out.tpi - 1) / out.tpi);
+    const bool reg = S.reg_fwd && d.n >= S.reg_bits && d.m > 0;
+    out.reg = reg;
+    if (S.persist && !reg)
+        return fail(set_error(CFH_E_UNSUPPORTED, "cfh_batch_create: a persistent batch needs every circuit on "
+                                                 "register tiles (n >= reg_tile_bits and at least one rotation)"));
+    const uint64_t nt2 = reg ? 1ull << (d.n - S.reg_bits) : 1;
+    out.tpi2 = (int)std::max<uint64_t>(1, (nt2 + S.max_items - 1) / S.max_items);
+    out.nitems2 = (int)((nt2 + out.tpi2 - 1) / out.tpi2);
+    // LDS-staged plan of circuits below the register tile (or under tuning
+    // variant 2): forward passes and, walked backwards, adjoint passes
+    if (!reg) out.fw = plan_rotations(d.n, r, tu);
+    if (reg) {
+        // forward passes on register tiles of 2^reg_bits amplitudes (128-byte chunks);
+        // a run needing more micro-groups than a pass carries is split in two
+        cfh_tuning t2{};
+        t2.tile_bits = S.reg_bits;
+        t2.max_run = tc.max_run;
+        const TuningResolved tu2 = resolve_tuning(&t2, d.n, S.dtype, kTuneForward);
+        std::vector<PassPlan> todo;
+        for (PassPlan &pp : plan_rotations(d.n, r, tu2)) todo.push_back(std::move(pp));
+        std::reverse(todo.begin(), todo.end());
+        PassArgs2 a2;
+        while (!todo.empty()) {
+            PassPlan pp = std::move(todo.back());
+            todo.pop_back();
+            if (!build_pass_args2(pp, r, false, batch_fwd_half((int)ab), a2)) {
+                if (pp.rots.size() < 2)
+                    return fail(set_error(CFH_E_INVAL, "cfh_batch_create: a rotation does not fit the register tile"));
+                PassPlan hi = pp;
+                const size_t half = pp.rots.size() / 2;
+                hi.rots.assign(pp.rots.begin() + (std::ptrdiff_t)half, pp.rots.end());
+                pp.rots.resize(half);
+                todo.push_back(std::move(hi));
+                todo.push_back(std::move(pp));
+                continue;
+            }
+            if (a2.b != S.reg_bits) return fail(set_error(CFH_E_INVAL, "cfh_batch_create: register tile size"));
+            out.fwd2.emplace_back(std::move(pp), a2);
+        }
+        // adjoint passes: the same runs walked backwards (anchored
+        // micro-groups and half-tile transposes at complex128); a run that
+        // needs more micro-groups so is split, its later half walked first
+        std::vector<PassPlan> rtodo;
+        for (const auto &f : out.fwd2) rtodo.push_back(f.first);
+        while (!rtodo.empty()) {
+            PassPlan pp = std::move(rtodo.back());
+            rtodo.pop_back();
+            if (!build_pass_args2(pp, r, true, batch_fwd_half((int)ab), a2)) {
+                if (pp.rots.size() < 2)
+                    return fail(set_error(CFH_E_INVAL, "cfh_batch_create: a rotation does not fit the register tile"));
+                PassPlan hi = pp;
+                const size_t half = pp.rots.size() / 2;
+                hi.rots.assign(pp.rots.begin() + (std::ptrdiff_t)half, pp.rots.end());
+                pp.rots.resize(half);
+                rtodo.push_back(std::move(pp));
+                rtodo.push_back(std::move(hi));
+                continue;
+            }
+            out.adj2.emplace_back(std::move(pp), a2);
+        }
+    }
+    // Hamiltonian passes (lam = H psi, energy on the last)
+    std::map<uint64_t, int> gid;
+    std::vector<HamGroup> &groups = out.groups;
+    for (int64_t i = 0; i < d.mh; ++i) {
+        auto itg = gid.find(d.terms[i].x);
+        if (itg == gid.end()) {
+            gid[d.terms[i].x] = (int)groups.size();
+            groups.push_back(HamGroup{d.terms[i].x, {(int)i}});
+        } else {
+            groups[itg->second].terms.push_back((int)i);
+        }
+    }
+    if (!reg) out.hp = plan_hamiltonian(d.n, groups, tu);
+    if (reg) {
+        // terms planned on register tiles: read-only measurement passes for
+        // forward runs, H psi passes (psi and lam in registers; anchored,
+        // half-tile transposes at complex128) for gradient runs
+        cfh_tuning t3{};
+        t3.tile_bits = S.reg_bits;
+        const TuningResolved tm = resolve_tuning(&t3, d.n, S.dtype, kTuneMeasure);
+        std::vector<HamGroup> mgr;
+        for (const HamGroup &g : groups)
+            for (size_t i = 0; i < g.terms.size(); i += kMaxRun)
+                mgr.push_back(HamGroup{g.x, std::vector<int>(g.terms.begin() + (std::ptrdiff_t)i,
+                                                             g.terms.begin() + (std::ptrdiff_t)std::min(
+                                                                                   g.terms.size(), i + kMaxRun))});
+        std::vector<Pauli> tp(d.mh);
+        for (int64_t i = 0; i < d.mh; ++i) tp[i] = Pauli{d.terms[i].x, d.terms[i].z, d.terms[i].e & 3};
+        const std::vector<HamPass> mps = plan_hamiltonian(d.n, mgr, tm, kMaxGroupsPerPass, kMaxRun);
+        for (const bool ham : {false, true}) {
+            // measurement and H psi items use half-tile transposes where the forward items do
+            const bool anchored = batch_fwd_half((int)ab);
+            std::vector<PassPlan> todo;
+            for (const HamPass &mp : mps) {
+                std::vector<int> idx;
+                for (int g : mp.groups) idx.insert(idx.end(), mgr[g].terms.begin(), mgr[g].terms.end());
+                PassPlan pp;
+                pp.b = mp.b;
+                pp.outer_mask = mp.outer_mask;
+                pp.v = mp.v;
+                pp.rots = order_for_microgroups(mp.v, tp, idx, anchored);
+                todo.push_back(std::move(pp));
+            }
+            std::reverse(todo.begin(), todo.end());
+            PassArgs2 a3;
+            while (!todo.empty()) {
+                PassPlan pp = std::move(todo.back());
+                todo.pop_back();
+                if (!build_pass_args2(pp, tp, false, anchored, a3)) {
+                    if (pp.rots.size() < 2)
+                        return fail(set_error(CFH_E_INVAL, "cfh_batch_create: a term does not fit the register tile"));
+                    PassPlan hi = pp;
+                    const size_t half = pp.rots.size() / 2;
+                    hi.rots.assign(pp.rots.begin() + (std::ptrdiff_t)half, pp.rots.end());
+                    pp.rots.resize(half);
+                    todo.push_back(std::move(hi));
+                    todo.push_back(std::move(pp));
+                    continue;
+                }
+                if (a3.b != S.reg_bits) return fail(set_error(CFH_E_INVAL, "cfh_batch_create: register tile size"));
+                (ham ? out.ham2 : out.meas2).emplace_back(std::move(pp), a3);
+            }
+        }
+    }
+}
+
+// Plans every circuit, on up to 16 threads (this one included); a thread
+// that cannot be started leaves its share to the others.
+void plan_circuits(const cfh_circuit_desc *circ, int count, const BatchSettings &S, std::vector<CircPlan> &plans)
+{
+    std::atomic<int> next{0};
+    auto work = [&] {
+        for (int c; (c = next.fetch_add(1)) < count;) {
+            try {
+                plan_circuit(circ[c], S, plans[c]);
+            } catch (...) {
+                plans[c].st = CFH_E_NOMEM;
+                plans[c].msg = "cfh_batch_create: host memory";
+            }
+        }
+    };
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const unsigned nthreads = std::min<unsigned>({hw, 16u, (unsigned)count});
+    std::vector<std::thread> pool;
+    for (unsigned i = 1; i < nthreads; ++i) {
+        try {
+            pool.emplace_back(work);
+        } catch (...) {
+            break;
+        }
+    }
+    work();
+    for (auto &t : pool) t.join();
+}
+
 } // namespace
 
 extern "C" {
@@ -432,38 +649,33 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
     std::vector<double> theta_all;
     std::vector<std::vector<int>> chain_fwd(count), chain_grad(count);
     int64_t amp = 0, gpart = 0, epart = 0;
+    std::vector<CircPlan> plans(count);
+    plan_circuits(circ, count, BatchSettings{dtype, B->bmax, B->reg_bits, max_items, B->reg_fwd != 0, B->persist, tuning},
+                  plans);
+    {
+        // the tables' final sizes (kernel descriptors are 3 KiB each): no regrowth copies
+        size_t npa = 0, npass = 0, nrot = 0, nmw = 0;
+        for (int c = 0; c < count; ++c) {
+            const CircPlan &CP = plans[c];
+            const size_t n2 = CP.fwd2.size() + CP.adj2.size() + CP.meas2.size() + CP.ham2.size();
+            npa += n2;
+            npass += n2 + 2 * CP.fw.size() + CP.hp.size();
+            for (const auto &f : CP.fwd2) nrot += f.first.rots.size();
+            for (const auto &f : CP.fw) nrot += f.rots.size();
+            nmw += (size_t)std::max<int64_t>(0, circ[c].mh);
+        }
+        pa.reserve(npa);
+        B->passes.reserve(npass);
+        rots.reserve(nrot);
+        mw_all.reserve(nmw);
+    }
     for (int c = 0; c < count; ++c) {
         const cfh_circuit_desc &d = circ[c];
-        if (d.n < 8 || d.n > 30) return set_error(CFH_E_UNSUPPORTED, "cfh_batch_create: circuit n must be in 8..30");
-        if ((d.m && (!d.rot || !d.theta)) || (d.mh && (!d.terms || !d.coeff)) || d.m < 0 || d.mh < 0)
-            return set_error(CFH_E_INVAL, "cfh_batch_create: null rotation or term arrays");
-        if (d.init_index >> d.n) return set_error(CFH_E_RANGE, "cfh_batch_create: init_index >= 2^n");
-        std::vector<Pauli> r(d.m);
-        for (int64_t i = 0; i < d.m; ++i) {
-            cfh_status st = check_pauli(d.rot[i], d.n, true, "cfh_batch_create");
-            if (st) return st;
-            r[i] = Pauli{d.rot[i].x, d.rot[i].z, d.rot[i].e & 3};
-        }
-        for (int64_t i = 0; i < d.mh; ++i) {
-            cfh_status st = check_pauli(d.terms[i], d.n, true, "cfh_batch_create");
-            if (st) return st;
-        }
-        cfh_tuning tc{};
-        tc.tile_bits = std::min(B->bmax, d.n);
-        tc.low_bits = tuning && tuning->low_bits > 0 ? tuning->low_bits : 4;
-        tc.max_run = tuning && tuning->max_run > 0 ? tuning->max_run : kMaxRun;
-        const TuningResolved tu = resolve_tuning(&tc, d.n, dtype, kTuneForward);
-        const int b = tu.tile_bits;
-        const uint64_t ntiles = 1ull << (d.n - b);
-        const int tpi = (int)std::max<uint64_t>(1, (ntiles + max_items - 1) / max_items);
-        const int nitems = (int)((ntiles + tpi - 1) / tpi);
-        const bool reg = B->reg_fwd && d.n >= B->reg_bits && d.m > 0;
-        if (B->persist && !reg)
-            return set_error(CFH_E_UNSUPPORTED, "cfh_batch_create: a persistent batch needs every circuit on register "
-                                                "tiles (n >= reg_tile_bits and at least one rotation)");
-        const uint64_t nt2 = reg ? 1ull << (d.n - B->reg_bits) : 1;
-        const int tpi2 = (int)std::max<uint64_t>(1, (nt2 + max_items - 1) / max_items);
-        const int nitems2 = (int)((nt2 + tpi2 - 1) / tpi2);
+        CircPlan &CP = plans[c];
+        if (CP.st) return set_error(CP.st, CP.msg);
+        const std::vector<Pauli> &r = CP.r;
+        const bool reg = CP.reg;
+        const int b = CP.b, tpi = CP.tpi, nitems = CP.nitems, tpi2 = CP.tpi2, nitems2 = CP.nitems2;
         BCirc &C = circs[c];
         C.psi_off = amp;
         C.init = d.init_index;
@@ -503,9 +715,7 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
             B->passes.push_back(P);
             return (int)B->passes.size() - 1;
         };
-        // LDS-staged plan of circuits below the register tile (or under tuning
-        // variant 2): forward passes and, walked backwards, adjoint passes
-        const std::vector<PassPlan> fw = reg ? std::vector<PassPlan>() : plan_rotations(d.n, r, tu);
+        const std::vector<PassPlan> &fw = CP.fw;
         std::vector<int> fw_lds;  // LDS-staged pass of fw[i]
         for (size_t i = 0; i < fw.size(); ++i) {
             const int first = (int)rots.size();
@@ -515,61 +725,21 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
         }
         std::vector<int> fwd_ids, adj_reg;
         if (reg) {
-            // forward passes on register tiles of 2^reg_bits amplitudes (128-byte chunks);
-            // a run needing more micro-groups than a pass carries is split in two
-            cfh_tuning t2{};
-            t2.tile_bits = B->reg_bits;
-            t2.max_run = tc.max_run;
-            const TuningResolved tu2 = resolve_tuning(&t2, d.n, dtype, kTuneForward);
-            std::vector<PassPlan> done;
-            std::vector<PassPlan> todo;
-            for (PassPlan &pp : plan_rotations(d.n, r, tu2)) todo.push_back(std::move(pp));
-            std::reverse(todo.begin(), todo.end());
-            PassArgs2 a2;
             bool first_pass = true;
-            while (!todo.empty()) {
-                PassPlan pp = std::move(todo.back());
-                todo.pop_back();
-                if (!build_pass_args2(pp, r, false, batch_fwd_half((int)ab), a2)) {
-                    if (pp.rots.size() < 2)
-                        return set_error(CFH_E_INVAL, "cfh_batch_create: a rotation does not fit the register tile");
-                    PassPlan hi = pp;
-                    const size_t half = pp.rots.size() / 2;
-                    hi.rots.assign(pp.rots.begin() + (std::ptrdiff_t)half, pp.rots.end());
-                    pp.rots.resize(half);
-                    todo.push_back(std::move(hi));
-                    todo.push_back(std::move(pp));
-                    continue;
-                }
-                if (a2.b != B->reg_bits) return set_error(CFH_E_INVAL, "cfh_batch_create: register tile size");
+            for (const auto &f : CP.fwd2) {
+                const PassPlan &pp = f.first;
                 const int id = new_pass(kPassFwd, B->reg_bits, pp.outer_mask, pp.v, 0, (int)pp.rots.size(),
                                         first_pass ? kFlagInit | kFlagStart : 0);
                 B->passes[id].p2 = (int)pa.size();
                 B->passes[id].nitems = nitems2;
                 B->passes[id].tiles_per_item = tpi2;
-                pa.push_back(a2);
+                pa.push_back(f.second);
                 fwd_ids.push_back(id);
-                done.push_back(std::move(pp));
                 first_pass = false;
             }
-            // adjoint passes: the same runs walked backwards (anchored
-            // micro-groups and half-tile transposes at complex128); a run that
-            // needs more micro-groups so is split, its later half walked first
-            std::vector<PassPlan> rtodo(done.begin(), done.end());
-            while (!rtodo.empty()) {
-                PassPlan pp = std::move(rtodo.back());
-                rtodo.pop_back();
-                if (!build_pass_args2(pp, r, true, batch_fwd_half((int)ab), a2)) {
-                    if (pp.rots.size() < 2)
-                        return set_error(CFH_E_INVAL, "cfh_batch_create: a rotation does not fit the register tile");
-                    PassPlan hi = pp;
-                    const size_t half = pp.rots.size() / 2;
-                    hi.rots.assign(pp.rots.begin() + (std::ptrdiff_t)half, pp.rots.end());
-                    pp.rots.resize(half);
-                    rtodo.push_back(std::move(pp));
-                    rtodo.push_back(std::move(hi));
-                    continue;
-                }
+            for (const auto &f : CP.adj2) {
+                const PassPlan &pp = f.first;
+                const PassArgs2 &a2 = f.second;
                 // gradient slot t of the pass belongs to rotation a2.rot[t].k
                 const int first = (int)rots.size();
                 const int nr = a2.mg[a2.nmg - 1].rot_begin + a2.mg[a2.nmg - 1].rot_count;
@@ -589,19 +759,9 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
             fwd_ids = fw_lds;
         }
         // Hamiltonian passes (lam = H psi, energy on the last)
-        std::map<uint64_t, int> gid;
-        std::vector<HamGroup> groups;
-        for (int64_t i = 0; i < d.mh; ++i) {
-            auto itg = gid.find(d.terms[i].x);
-            if (itg == gid.end()) {
-                gid[d.terms[i].x] = (int)groups.size();
-                groups.push_back(HamGroup{d.terms[i].x, {(int)i}});
-            } else {
-                groups[itg->second].terms.push_back((int)i);
-            }
-        }
+        const std::vector<HamGroup> &groups = CP.groups;
         std::vector<int> ham_ids;
-        const std::vector<HamPass> hp = reg ? std::vector<HamPass>() : plan_hamiltonian(d.n, groups, tu);
+        const std::vector<HamPass> &hp = CP.hp;
         for (size_t i = 0; i < hp.size(); ++i) {
             const int first = (int)gdev.size();
             for (int g : hp[i].groups) {
@@ -637,66 +797,22 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
         // measurement passes on register tiles instead of writing lam = H psi
         std::vector<int> meas_ids, ham2_ids;
         if (reg) {
-            // terms planned on register tiles: read-only measurement passes for
-            // forward runs, H psi passes (psi and lam in registers; anchored,
-            // half-tile transposes at complex128) for gradient runs
-            cfh_tuning t3{};
-            t3.tile_bits = B->reg_bits;
-            const TuningResolved tm = resolve_tuning(&t3, d.n, dtype, kTuneMeasure);
-            std::vector<HamGroup> mgr;
-            for (const HamGroup &g : groups)
-                for (size_t i = 0; i < g.terms.size(); i += kMaxRun)
-                    mgr.push_back(HamGroup{g.x, std::vector<int>(g.terms.begin() + (std::ptrdiff_t)i,
-                                                                 g.terms.begin() + (std::ptrdiff_t)std::min(
-                                                                                       g.terms.size(), i + kMaxRun))});
-            std::vector<Pauli> tp(d.mh);
-            for (int64_t i = 0; i < d.mh; ++i) tp[i] = Pauli{d.terms[i].x, d.terms[i].z, d.terms[i].e & 3};
-            const std::vector<HamPass> mps = plan_hamiltonian(d.n, mgr, tm, kMaxGroupsPerPass, kMaxRun);
             for (const bool ham : {false, true}) {
-                // measurement and H psi items use half-tile transposes where the forward items do
-                const bool anchored = batch_fwd_half((int)ab);
                 std::vector<int> &ids = ham ? ham2_ids : meas_ids;
-                std::vector<PassPlan> todo;
-                for (const HamPass &mp : mps) {
-                    std::vector<int> idx;
-                    for (int g : mp.groups) idx.insert(idx.end(), mgr[g].terms.begin(), mgr[g].terms.end());
-                    PassPlan pp;
-                    pp.b = mp.b;
-                    pp.outer_mask = mp.outer_mask;
-                    pp.v = mp.v;
-                    pp.rots = order_for_microgroups(mp.v, tp, idx, anchored);
-                    todo.push_back(std::move(pp));
-                }
-                std::reverse(todo.begin(), todo.end());
-                PassArgs2 a3;
-                while (!todo.empty()) {
-                    PassPlan pp = std::move(todo.back());
-                    todo.pop_back();
-                    if (!build_pass_args2(pp, tp, false, anchored, a3)) {
-                        if (pp.rots.size() < 2)
-                            return set_error(CFH_E_INVAL, "cfh_batch_create: a term does not fit the register tile");
-                        PassPlan hi = pp;
-                        const size_t half = pp.rots.size() / 2;
-                        hi.rots.assign(pp.rots.begin() + (std::ptrdiff_t)half, pp.rots.end());
-                        pp.rots.resize(half);
-                        todo.push_back(std::move(hi));
-                        todo.push_back(std::move(pp));
-                        continue;
-                    }
-                    if (a3.b != B->reg_bits) return set_error(CFH_E_INVAL, "cfh_batch_create: register tile size");
+                for (const auto &f : ham ? CP.ham2 : CP.meas2) {
+                    const PassPlan &pp = f.first;
                     const int id = new_pass(ham ? kPassHam : kPassMeas, B->reg_bits, pp.outer_mask, pp.v, 0,
                                             (int)pp.rots.size(), ids.empty() ? 0 : kFlagAccumulate);
                     B->passes[id].p2 = (int)pa.size();
                     B->passes[id].nitems = nitems2;
                     B->passes[id].tiles_per_item = tpi2;
-                    pa.push_back(a3);
+                    pa.push_back(f.second);
                     ids.push_back(id);
                 }
             }
             if (meas_ids.empty() || ham2_ids.empty())
                 return set_error(CFH_E_INVAL, "cfh_batch_create: every circuit needs an observable");
             B->passes[ham2_ids.back()].flags |= kFlagEnergy | kFlagEnd;
-            if (meas_ids.empty()) return set_error(CFH_E_INVAL, "cfh_batch_create: every circuit needs an observable");
             B->passes[meas_ids.back()].flags |= kFlagEnergy | kFlagEnd;
         }
         if (fwd_ids.empty()) return set_error(CFH_E_INVAL, "cfh_batch_create: every circuit needs rotations");
@@ -720,6 +836,7 @@ cfh_status cfh_batch_create(const cfh_circuit_desc *circ, int count, int dtype, 
             chain.insert(chain.end(), ham_ids.begin(), ham_ids.end());
         chain.insert(chain.end(), adj_ids.begin(), adj_ids.end());
         chain_grad[c] = chain;
+        CP = CircPlan();  // its descriptors are in the batch tables now
     }
     B->total_rot = (int64_t)theta_all.size();
     for (const auto &ch : chain_grad) B->n_passes += (int64_t)ch.size();
