@@ -131,6 +131,35 @@ def test_persistent_hipgraph_replays():
             (x * 2).sum().item()
 
 
+def test_persistent_config_replaces_captured_graphs():
+    """A captured graph holds the persistent kernel's arguments: changing the
+    wait limit or the hold drops the graphs, so the next graph launch captures
+    the new arguments (hold: the replay gives up; released: the eager results
+    again).  Bad arguments are rejected."""
+    ws = _batch(seed=16, count=5, n_range=(12, 13), r_range=(30, 80), n_ham=12)
+    B = hybrid.Batch(ws, torch.complex128, {"variant": 1, "batch_items": 4})
+    s = torch.cuda.Stream()
+    B.run(with_grad=True, stream=s)
+    ref = B.results(stream=s)
+    B.graph_launch(True, s)
+    assert np.array_equal(B.results(stream=s)["energy"], ref["energy"])
+    cfh.cfh_batch_persist_config(B.h, max_wait_s=0.005, hold=True)
+    B.graph_launch(True, s)
+    with pytest.raises(cfh.CfhError) as e:
+        B.results(stream=s)
+    assert e.value.code == cfh.CFH_E_TIMEOUT
+    cfh.cfh_batch_persist_config(B.h, max_wait_s=2.0, hold=False)
+    B.graph_launch(True, s)
+    got = B.results(stream=s)
+    assert np.array_equal(got["energy"], ref["energy"])
+    for a, b in zip(got["grad"], ref["grad"]):
+        assert np.array_equal(a, b)
+    for bad in ((0.0, False, 0), (601.0, False, 0), (1.0, False, -1)):
+        with pytest.raises(cfh.CfhError) as e:
+            cfh.cfh_batch_persist_config(B.h, *bad)
+        assert e.value.code == cfh.CFH_E_INVAL
+
+
 def test_persistent_rejects_circuits_below_the_register_tile():
     ws = _batch(seed=15, count=3, n_range=(11, 13))
     ws[0] = W.make_workload("small", 11, seed=1, n_rot=20, n_ham=5)
