@@ -108,3 +108,62 @@ def test_max_qubits_rotations_and_expval_vs_sparse_oracle(dtype, n):
     scale = np.abs(coeff).sum()
     assert abs(e.real - e_ref.real) <= tol * scale and abs(e.imag) <= tol * scale
     assert abs(e_ref.imag) <= 1e-12 * scale
+
+
+def _sparse_energy(n, init, rows, theta, terms, coeff):
+    """E(theta) = sum_k c_k <a|P_k|a> on the oracle's sparse state."""
+    io, ao = sim.sparse_rotations(n, np.array([init], np.uint64), np.array([1 + 0j]), rows, theta)
+    return float(np.real(sum(c * _sparse_expval(n, io, ao, r) for c, r in zip(coeff, terms))))
+
+
+@pytest.mark.parametrize("dtype,n", [(torch.complex64, 33), (torch.complex128, 32)])
+def test_max_qubits_adjoint_gradients_vs_sparse_parameter_shift(dtype, n):
+    """The adjoint sweep holds psi and lambda (2 x 64 GiB here).  Every
+    gradient against the parameter-shift rule on the sparse oracle,
+    dE/dtheta_j = (E(theta + pi/2 e_j) - E(theta - pi/2 e_j)) / 2 for
+    R_P(theta) = exp(-i theta P / 2); the sweep must also rewind psi to the
+    start state.  complex64: amplitude errors within 1e-4 on unit-norm states
+    move a gradient or the energy by at most about 1e-4 * sum |c_j|."""
+    torch.cuda.empty_cache()
+    need = 2 * (1 << n) * (8 if dtype == torch.complex64 else 16)
+    free, _ = torch.cuda.mem_get_info()
+    assert free >= need + (4 << 30), f"{free / 2**30:.1f} GiB free, {need / 2**30:.0f} GiB needed"
+    rows, theta, init, terms, coeff = _inputs(n)
+    e_ref = _sparse_energy(n, init, rows, theta, terms, coeff)
+    g_ref = np.zeros(len(theta))
+    for j in range(len(theta)):
+        tp, tm = theta.copy(), theta.copy()
+        tp[j] += np.pi / 2
+        tm[j] -= np.pi / 2
+        g_ref[j] = 0.5 * (_sparse_energy(n, init, rows, tp, terms, coeff) -
+                          _sparse_energy(n, init, rows, tm, terms, coeff))
+    assert np.count_nonzero(np.abs(g_ref) > 1e-3) >= len(theta) // 2
+
+    psi = hybrid.new_state(n, dtype, index=init)
+    lam = None
+    try:
+        plan = hybrid.Plan(n, dtype, cfh.cfh_pauli_encode(rows))
+        ham = hybrid.Hamiltonian(n, dtype, cfh.cfh_pauli_encode(terms), coeff)
+        th = torch.tensor(theta, device=DEV)
+        plan.apply(psi, th)
+        e = ham.expval(psi)
+        lam = torch.empty_like(psi)
+        grad = torch.empty_like(th)
+        cfh.cfh_adjoint_grad(plan.h, ham.h, psi, lam, th, grad)
+        g = grad.cpu().numpy()
+        back = psi[torch.tensor([init, init ^ 1, init ^ (1 << (n - 1))], device=DEV)].cpu()
+        back = back.to(torch.complex128).numpy()
+        norm = _norm2(psi)
+    finally:
+        del psi, lam
+        torch.cuda.empty_cache()
+    scale = np.abs(coeff).sum()
+    tol = (1e-10 if dtype == torch.complex128 else 1e-4 * scale)
+    etol = (1e-12 if dtype == torch.complex128 else 1e-4) * scale
+    print(f"n={n} {dtype}: max |g - shift| {np.abs(g - g_ref).max():.2e}, E {e.real:.12f} vs {e_ref:.12f}",
+          flush=True)
+    assert abs(e.real - e_ref) <= etol
+    assert np.abs(g - g_ref).max() <= tol
+    rtol = 1e-11 if dtype == torch.complex128 else 1e-4
+    assert abs(back[0] - 1) <= rtol and np.abs(back[1:]).max() <= rtol
+    assert abs(norm - 1) <= (1e-11 if dtype == torch.complex128 else 1e-5)
