@@ -57,12 +57,14 @@ __device__ __forceinline__ void st_amp(float2 *p, double2 v, bool nt)
 }
 
 // Thread i updates amplitude a(i): a = i (contiguous), or with the index
-// bits above the low cbits bit-reversed (scattered chunks).  The grid covers
-// exactly 2^nbits threads, so a(i) is a permutation of [0, 2^nbits).
+// bits above the low cbits bit-reversed (scattered chunks).  The launches
+// together cover i in [0, 2^nbits) exactly once (i0 is a launch's first i), so
+// a(i) is a permutation of [0, 2^nbits).
 template <typename Amp, bool NT, bool SCATTER>
-__global__ void __launch_bounds__(256) k_calib_rmw(Amp *__restrict__ p, int nbits, int cbits, double c, double s)
+__global__ void __launch_bounds__(256) k_calib_rmw(Amp *__restrict__ p, int nbits, int cbits, double c, double s,
+                                                   uint64_t i0)
 {
-    const uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+    const uint64_t i = i0 + (uint64_t)blockIdx.x * 256u + threadIdx.x;
     uint64_t a = i;
     if (SCATTER) {
         const int hb = nbits - cbits;
@@ -77,17 +79,24 @@ template <typename Amp>
 cfh_status launch_calib(Amp *p, int n, int cbits, bool nt, hipStream_t st)
 {
     const double c = std::cos(0.25), s = std::sin(0.25);
-    const unsigned grid = (unsigned)((1ull << n) / 256);
+    // one thread per amplitude, in launches of at most 2^31 threads (a launch
+    // holds fewer than 2^32 work-items)
+    const uint64_t N = 1ull << n, per = 1ull << 31;
     const bool sc = cbits >= 0;
-    if (nt && sc)
-        hipLaunchKernelGGL((k_calib_rmw<Amp, true, true>), dim3(grid), dim3(256), 0, st, p, n, cbits, c, s);
-    else if (nt)
-        hipLaunchKernelGGL((k_calib_rmw<Amp, true, false>), dim3(grid), dim3(256), 0, st, p, n, 0, c, s);
-    else if (sc)
-        hipLaunchKernelGGL((k_calib_rmw<Amp, false, true>), dim3(grid), dim3(256), 0, st, p, n, cbits, c, s);
-    else
-        hipLaunchKernelGGL((k_calib_rmw<Amp, false, false>), dim3(grid), dim3(256), 0, st, p, n, 0, c, s);
-    return last_launch("k_calib_rmw");
+    for (uint64_t i0 = 0; i0 < N; i0 += per) {
+        const unsigned grid = (unsigned)(std::min(per, N - i0) / 256);
+        if (nt && sc)
+            hipLaunchKernelGGL((k_calib_rmw<Amp, true, true>), dim3(grid), dim3(256), 0, st, p, n, cbits, c, s, i0);
+        else if (nt)
+            hipLaunchKernelGGL((k_calib_rmw<Amp, true, false>), dim3(grid), dim3(256), 0, st, p, n, 0, c, s, i0);
+        else if (sc)
+            hipLaunchKernelGGL((k_calib_rmw<Amp, false, true>), dim3(grid), dim3(256), 0, st, p, n, cbits, c, s, i0);
+        else
+            hipLaunchKernelGGL((k_calib_rmw<Amp, false, false>), dim3(grid), dim3(256), 0, st, p, n, 0, c, s, i0);
+        const cfh_status r = last_launch("k_calib_rmw");
+        if (r) return r;
+    }
+    return CFH_OK;
 }
 
 } // namespace

@@ -67,7 +67,8 @@ struct PassArgs {
     int32_t b;
     int32_t nrot;
     int32_t inverse;     // 1: apply R^dag (negated angles) in reverse order
-    int32_t tile_base;   // first coset handled by block 0 (for split launches)
+    int32_t pad;
+    uint64_t tile_base;  // first coset handled by block 0 (for split launches)
     RotDesc rot[kMaxRun];
 };
 

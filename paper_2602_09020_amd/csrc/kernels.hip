@@ -91,8 +91,8 @@ __global__ void k_set_basis(Amp *__restrict__ psi, uint64_t N, uint64_t index)
 
 __global__ void k_zero_d(double *__restrict__ p, int64_t cnt)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < cnt) p[i] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
 }
 
 // ---------------------------------------------- unfused rotation (one pass)
@@ -100,6 +100,9 @@ __global__ void k_zero_d(double *__restrict__ p, int64_t cnt)
 // Consecutive lanes take consecutive q, so both members stream contiguously.
 constexpr int kR1Threads = 256;
 constexpr int kR1Pairs = 4;
+// A launch holds fewer than 2^32 work-items; the single-rotation kernels loop
+// over chunks, so one launch of at most this many workgroups covers any state.
+constexpr uint64_t kR1MaxGrid = 1ull << 20;
 
 template <typename Amp>
 __global__ void __launch_bounds__(kR1Threads)
@@ -115,28 +118,31 @@ k_rot_pairs(Amp *__restrict__ psi, uint64_t x, uint64_t z, int hb, int w, int ds
     const double sr = (w & 2) ? -s : s;
     const bool imag = w & 1;
     const uint64_t lowm = (1ull << hb) - 1;
-    const uint64_t q0 = (uint64_t)blockIdx.x * (kR1Threads * kR1Pairs) + threadIdx.x;
-    double2 u[kR1Pairs], v[kR1Pairs];
-    uint64_t ya[kR1Pairs];
+    constexpr uint64_t per = (uint64_t)kR1Threads * kR1Pairs;
+    for (uint64_t q0 = (uint64_t)blockIdx.x * per + threadIdx.x; q0 - threadIdx.x < npairs;
+         q0 += (uint64_t)gridDim.x * per) {
+        double2 u[kR1Pairs], v[kR1Pairs];
+        uint64_t ya[kR1Pairs];
 #pragma unroll
-    for (int j = 0; j < kR1Pairs; ++j) {
-        const uint64_t q = q0 + (uint64_t)j * kR1Threads;
-        ya[j] = ((q & ~lowm) << 1) | (q & lowm);
-        if (q < npairs) {
-            u[j] = ld(psi[ya[j]]);
-            v[j] = ld(psi[ya[j] ^ x]);
+        for (int j = 0; j < kR1Pairs; ++j) {
+            const uint64_t q = q0 + (uint64_t)j * kR1Threads;
+            ya[j] = ((q & ~lowm) << 1) | (q & lowm);
+            if (q < npairs) {
+                u[j] = ld(psi[ya[j]]);
+                v[j] = ld(psi[ya[j] ^ x]);
+            }
         }
-    }
 #pragma unroll
-    for (int j = 0; j < kR1Pairs; ++j) {
-        const uint64_t q = q0 + (uint64_t)j * kR1Threads;
-        if (q < npairs) {
-            const int sg0 = par64(ya[j] & z);
-            const double s0 = sg0 ? -sr : sr;
-            const double s1 = (sg0 ^ dsign) ? -sr : sr;
-            rot_pair(u[j], v[j], c, s0, s1, imag);
-            st(psi[ya[j]], u[j]);
-            st(psi[ya[j] ^ x], v[j]);
+        for (int j = 0; j < kR1Pairs; ++j) {
+            const uint64_t q = q0 + (uint64_t)j * kR1Threads;
+            if (q < npairs) {
+                const int sg0 = par64(ya[j] & z);
+                const double s0 = sg0 ? -sr : sr;
+                const double s1 = (sg0 ^ dsign) ? -sr : sr;
+                rot_pair(u[j], v[j], c, s0, s1, imag);
+                st(psi[ya[j]], u[j]);
+                st(psi[ya[j] ^ x], v[j]);
+            }
         }
     }
 }
@@ -154,13 +160,16 @@ k_rot_diag(Amp *__restrict__ psi, uint64_t z, int w, double c_in, double s_in,
     }
     const double sr = (w & 2) ? -s : s;
     const bool imag = w & 1;
-    const uint64_t y0 = (uint64_t)blockIdx.x * (kR1Threads * kR1Pairs) + threadIdx.x;
+    constexpr uint64_t per = (uint64_t)kR1Threads * kR1Pairs;
+    for (uint64_t y0 = (uint64_t)blockIdx.x * per + threadIdx.x; y0 - threadIdx.x < N;
+         y0 += (uint64_t)gridDim.x * per) {
 #pragma unroll
-    for (int j = 0; j < kR1Pairs; ++j) {
-        const uint64_t y = y0 + (uint64_t)j * kR1Threads;
-        if (y < N) {
-            const double sj = par64(y & z) ? -sr : sr;
-            st(psi[y], rot_diag(ld(psi[y]), c, sj, imag));
+        for (int j = 0; j < kR1Pairs; ++j) {
+            const uint64_t y = y0 + (uint64_t)j * kR1Threads;
+            if (y < N) {
+                const double sj = par64(y & z) ? -sr : sr;
+                st(psi[y], rot_diag(ld(psi[y]), c, sj, imag));
+            }
         }
     }
 }
@@ -330,7 +339,8 @@ k_ham_expval(const Amp *__restrict__ psi, const HamPassArgs args, const HamGroup
 template <typename Amp, int B>
 __global__ void __launch_bounds__(threads_for(B))
 k_ham_apply(const Amp *__restrict__ psi, Amp *__restrict__ out, const HamPassArgs args,
-            const HamGroupDev *__restrict__ groups, const HamTermDev *__restrict__ terms, int accumulate)
+            const HamGroupDev *__restrict__ groups, const HamTermDev *__restrict__ terms, int accumulate,
+            uint64_t tile0)
 {
     constexpr int T = threads_for(B);
     constexpr int LT = ilog2c(T);
@@ -338,7 +348,7 @@ k_ham_apply(const Amp *__restrict__ psi, Amp *__restrict__ out, const HamPassArg
     constexpr int E = N / T;
     __shared__ Amp tile[N];
     const int t = threadIdx.x;
-    const uint64_t base = deposit((uint64_t)blockIdx.x, args.outer_mask);
+    const uint64_t base = deposit((uint64_t)blockIdx.x + tile0, args.outer_mask);
     uint64_t Lt = 0;
 #pragma unroll
     for (int i = 0; i < LT; ++i)
@@ -599,11 +609,13 @@ constexpr bool fits_lds(int tiles) { return (size_t)tiles * sizeof(Amp) * ((size
 template <typename Amp>
 cfh_status launch_pass(int b, uint64_t ntiles, hipStream_t s, Amp *psi, const double2 *coef, PassArgs a)
 {
-    // split grids larger than 2^30 blocks (never at supported sizes, kept for safety)
-    constexpr uint64_t kMaxGrid = 1ull << 30;
-    for (uint64_t off = 0; off < ntiles; off += kMaxGrid) {
-        a.tile_base = (int32_t)off;
-        const unsigned g = (unsigned)std::min<uint64_t>(kMaxGrid, ntiles - off);
+    // A launch holds fewer than 2^32 work-items: small tiles of a large state
+    // (2^(n-b) workgroups of threads_for(b) threads) take several launches.
+    if (b < 1 || b > 14) return set_error(CFH_E_UNSUPPORTED, "tile_bits outside 1..14");
+    const uint64_t max_grid = (1ull << 31) / (uint64_t)threads_for(b);
+    for (uint64_t off = 0; off < ntiles; off += max_grid) {
+        a.tile_base = off;
+        const unsigned g = (unsigned)std::min<uint64_t>(max_grid, ntiles - off);
         switch (b) {
 #define CFH_PASS_CASE(BB)                                                                        \
     case BB:                                                                                     \
@@ -633,10 +645,13 @@ cfh_status launch_ham(int b, uint64_t ntiles, unsigned grid, hipStream_t s, cons
 #define CFH_HAM_CASE(BB)                                                                                   \
     case BB:                                                                                               \
         if constexpr (fits_lds<Amp, BB>(1) && BB <= 13) {                                                  \
-            if (out)                                                                                       \
-                hipLaunchKernelGGL((k_ham_apply<Amp, BB>), dim3((unsigned)ntiles), dim3(threads_for(BB)), 0, s, \
-                                   psi, out, a, gr, tm, accumulate);                                       \
-            else                                                                                           \
+            if (out) {                                                                                     \
+                /* fewer than 2^32 work-items per launch */                                                \
+                constexpr uint64_t G = (1ull << 31) / threads_for(BB);                                     \
+                for (uint64_t t0 = 0; t0 < ntiles; t0 += G)                                                \
+                    hipLaunchKernelGGL((k_ham_apply<Amp, BB>), dim3((unsigned)std::min(G, ntiles - t0)),   \
+                                       dim3(threads_for(BB)), 0, s, psi, out, a, gr, tm, accumulate, t0);  \
+            } else                                                                                         \
                 hipLaunchKernelGGL((k_ham_expval<Amp, BB>), dim3(grid), dim3(threads_for(BB)), 0, s, psi, a, \
                                    gr, tm, partial, ntiles);                                               \
         } else                                                                                             \
@@ -697,14 +712,15 @@ cfh_status rot_one(Amp *psi, int n, uint64_t x, uint64_t z, int e, double c, dou
     const uint64_t per = (uint64_t)kR1Threads * kR1Pairs;
     if (x == 0) {
         const uint64_t N = 1ull << n;
-        hipLaunchKernelGGL((k_rot_diag<Amp>), dim3((unsigned)((N + per - 1) / per)), dim3(kR1Threads), 0, st,
-                           psi, z, w, c, s, coef, k, ssign, N);
+        const unsigned g = (unsigned)std::min<uint64_t>((N + per - 1) / per, kR1MaxGrid);
+        hipLaunchKernelGGL((k_rot_diag<Amp>), dim3(g), dim3(kR1Threads), 0, st, psi, z, w, c, s, coef, k, ssign, N);
         return last_launch("k_rot_diag");
     }
     const int hb = 63 - __builtin_clzll(x);
     const uint64_t np = 1ull << (n - 1);
-    hipLaunchKernelGGL((k_rot_pairs<Amp>), dim3((unsigned)((np + per - 1) / per)), dim3(kR1Threads), 0, st,
-                       psi, x, z, hb, w, popc(x & z) & 1, c, s, coef, k, ssign, np);
+    const unsigned g = (unsigned)std::min<uint64_t>((np + per - 1) / per, kR1MaxGrid);
+    hipLaunchKernelGGL((k_rot_pairs<Amp>), dim3(g), dim3(kR1Threads), 0, st, psi, x, z, hb, w, popc(x & z) & 1, c,
+                       s, coef, k, ssign, np);
     return last_launch("k_rot_pairs");
 }
 
@@ -1370,8 +1386,8 @@ cfh_status cfh_ham_apply(cfh_ham h, const void *psi, void *out, void *stream)
     hipStream_t s = (hipStream_t)stream;
     if (h->args.empty()) {
         const uint64_t cnt = (1ull << h->n) * amp_bytes(h->dtype) / 8;
-        hipLaunchKernelGGL(k_zero_d, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, (double *)out,
-                           (int64_t)cnt);
+        hipLaunchKernelGGL(k_zero_d, dim3((unsigned)std::min<uint64_t>((cnt + 255) / 256, 1u << 20)), dim3(256), 0, s,
+                           (double *)out, (int64_t)cnt);
         return last_launch("k_zero_d");
     }
     if (!h->hargs.empty()) {

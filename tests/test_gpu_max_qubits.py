@@ -167,3 +167,132 @@ def test_max_qubits_adjoint_gradients_vs_sparse_parameter_shift(dtype, n):
     rtol = 1e-11 if dtype == torch.complex128 else 1e-4
     assert abs(back[0] - 1) <= rtol and np.abs(back[1:]).max() <= rtol
     assert abs(norm - 1) <= (1e-11 if dtype == torch.complex128 else 1e-5)
+
+
+def _with_diagonal(n, rows, theta):
+    """The rotations with three diagonal (Z-only) rotations spliced in."""
+    rng = np.random.default_rng(77 + n)
+    diag = np.where(rng.integers(0, 2, size=(3, n)) == 1, 3, 0).astype(np.uint8)
+    diag[:, n - 1] = 3
+    r = np.concatenate([rows[:8], diag[:2], rows[8:16], diag[2:], rows[16:]])
+    t = np.concatenate([theta[:8], rng.uniform(-np.pi, np.pi, 2), theta[8:16], rng.uniform(-np.pi, np.pi, 1),
+                        theta[16:]])
+    return r, t
+
+
+@pytest.mark.parametrize("tuning", [{"unfused": 1}, {"variant": 1, "tile_bits": 10, "low_bits": 3}],
+                         ids=["unfused", "lds_b10"])
+def test_max_qubits_unfused_and_small_lds_tiles_vs_sparse_oracle(tuning):
+    """n = 34 at complex64 through the paths whose launches grow with the
+    state: one rotation per launch (2^34 amplitudes for a diagonal rotation),
+    and LDS-staged passes on 2^10 tiles (2^24 workgroups of 256 threads, more
+    work-items than one launch holds), with <H> on the same tiles.  The unfused
+    run then measures a Z-type Pauli and checks the collapsed state: the
+    amplitudes of the drawn eigenspace, divided by sqrt(P(s))."""
+    n, dtype = 34, torch.complex64
+    torch.cuda.empty_cache()
+    rows, theta, init, terms, coeff = _inputs(n)
+    rows, theta = _with_diagonal(n, rows, theta)
+    io, ao = sim.sparse_rotations(n, np.array([init], np.uint64), np.array([1 + 0j]), rows, theta)
+    e_ref = complex(np.dot(coeff, [_sparse_expval(n, io, ao, r) for r in terms]))
+    zrow = np.where(np.random.default_rng(5).integers(0, 2, size=n) == 1, 3, 0).astype(np.uint8)
+    zrow[n - 1] = zrow[0] = 3
+    zmask = sum(1 << j for j in range(n) if zrow[j] == 3)
+    ev_z = float(np.real(_sparse_expval(n, io, ao, zrow)))
+    assert abs(ev_z) < 0.9
+    psi = hybrid.new_state(n, dtype, index=init)
+    try:
+        plan = hybrid.Plan(n, dtype, cfh.cfh_pauli_encode(rows), tuning)
+        plan.apply(psi, torch.tensor(theta, device=DEV))
+        ham = hybrid.Hamiltonian(n, dtype, cfh.cfh_pauli_encode(terms), coeff,
+                                 None if "unfused" in tuning else tuning)
+        e = ham.expval(psi)
+        sel = torch.from_numpy(io.astype(np.int64)).to(DEV)
+        got = psi[sel].cpu().to(torch.complex128).numpy()
+        norm = _norm2(psi)
+        meas = None
+        if "unfused" in tuning:
+            s, pp = cfh.cfh_measure_pauli(psi, n, 0, zmask, 0, 0.5)
+            after = psi[sel].cpu().to(torch.complex128).numpy()
+            meas = (s, pp, after, _norm2(psi))
+    finally:
+        del psi
+        torch.cuda.empty_cache()
+    print(f"{tuning}: passes {plan.info()['n_passes']}, max |d| {np.abs(got - ao).max():.2e}, "
+          f"<H> {e.real:.9f} vs {e_ref.real:.9f}", flush=True)
+    scale = np.abs(coeff).sum()
+    assert np.abs(got - ao).max() <= 1e-4
+    assert abs(norm - 1) <= 1e-5 and abs(norm - float(np.sum(np.abs(got) ** 2))) <= 1e-5
+    assert abs(e.real - e_ref.real) <= 1e-4 * scale and abs(e.imag) <= 1e-4 * scale
+    if meas is not None:
+        s, pp, after, norm2 = meas
+        p_ref = 0.5 * (1 + ev_z)
+        assert abs(pp - p_ref) <= 1e-4 and s == (1 if 0.5 < p_ref else -1)
+        par = np.array([bin(int(y) & zmask).count("1") & 1 for y in io])
+        keep = (1 - 2 * par) == s
+        want = np.where(keep, ao / np.sqrt(pp if s == 1 else 1 - pp), 0)
+        assert np.abs(after - want).max() <= 1e-4 and abs(norm2 - 1) <= 1e-5
+
+
+@pytest.mark.parametrize("tuning", [None, {"variant": 1, "tile_bits": 9, "low_bits": 3}], ids=["reg", "lds_b9"])
+def test_max_qubits_ham_apply_vs_sparse_oracle(tuning):
+    """H psi at n = 33, complex64 (psi and the output 64 GiB each): the
+    register-tiled passes, and LDS-staged passes on 2^9 tiles (2^24 workgroups
+    of 256 threads: several launches).  Expected: sum_k c_k P_k a with
+    P_k a = i R_{P_k}(pi) a from the sparse oracle; the output must carry no
+    weight outside those amplitudes."""
+    n, dtype = 33, torch.complex64
+    torch.cuda.empty_cache()
+    rows, theta, init, terms, coeff = _inputs(n)
+    io, ao = sim.sparse_rotations(n, np.array([init], np.uint64), np.array([1 + 0j]), rows, theta)
+    parts_i, parts_a = [], []
+    for c, r in zip(coeff, terms):
+        i2, a2 = sim.sparse_rotations(n, io, ao, r[None, :], np.array([np.pi]))
+        parts_i.append(i2)
+        parts_a.append(1j * c * a2)
+    idx, inv = np.unique(np.concatenate(parts_i), return_inverse=True)
+    want = np.zeros(idx.size, np.complex128)
+    np.add.at(want, inv, np.concatenate(parts_a))
+    psi = hybrid.new_state(n, dtype, index=init)
+    out = None
+    try:
+        hybrid.Plan(n, dtype, cfh.cfh_pauli_encode(rows)).apply(psi, torch.tensor(theta, device=DEV))
+        ham = hybrid.Hamiltonian(n, dtype, cfh.cfh_pauli_encode(terms), coeff, tuning)
+        out = torch.empty_like(psi)
+        ham.apply(psi, out)
+        got = out[torch.from_numpy(idx.astype(np.int64)).to(DEV)].cpu().to(torch.complex128).numpy()
+        onorm = _norm2(out)
+    finally:
+        del psi, out
+        torch.cuda.empty_cache()
+    scale = np.abs(coeff).sum()
+    print(f"{tuning}: {idx.size} amplitudes, max |d| {np.abs(got - want).max():.2e}", flush=True)
+    assert np.abs(got - want).max() <= 1e-4 * scale
+    assert abs(onorm - float(np.sum(np.abs(want) ** 2))) <= 1e-4 * scale * scale
+
+
+def test_max_state_empty_observable_and_calibration_kernel():
+    """n = 32 at complex128 (64 GiB): H psi of an observable without terms
+    zeroes all 2^33 doubles of the output, and the calibration kernel, in
+    launches of at most 2^31 threads, turns every amplitude exactly once, in
+    index order and in the scattered order: two calls multiply each amplitude
+    by exp(0.5 i)."""
+    n, dtype = 32, torch.complex128
+    torch.cuda.empty_cache()
+    psi = hybrid.new_state(n, dtype, index=(1 << 31) + 5)
+    out = None
+    try:
+        h0 = hybrid.Hamiltonian(n, dtype, np.zeros(0, cfh.PAULI_DTYPE), np.zeros(0))
+        out = torch.ones_like(psi)
+        h0.apply(psi, out)
+        zmax = max(float(ch.abs().max().item()) for ch in out.split(1 << 28))
+        out.fill_(1.0)
+        cfh.cfh_calib_rmw(out, n, -1)
+        cfh.cfh_calib_rmw(out, n, 3)
+        want = torch.tensor(np.exp(0.5j), dtype=dtype, device=DEV)
+        dmax = max(float((ch - want).abs().max().item()) for ch in out.split(1 << 28))
+    finally:
+        del psi, out
+        torch.cuda.empty_cache()
+    assert zmax == 0
+    assert dmax <= 1e-15
