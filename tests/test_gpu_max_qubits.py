@@ -15,6 +15,9 @@ independent masks every <P> of this kind is exactly zero.)
 R_P(theta) = cos(theta/2) - i sin(theta/2) P, R_P(pi) = -i P (up to the
 rounding of cos(pi/2), about 6e-17), so <a|P|a> = i <a|R_P(pi) a>.
 """
+from functools import lru_cache
+from types import SimpleNamespace
+
 import numpy as np
 import pytest
 import torch
@@ -24,6 +27,8 @@ from paper_2602_09020_amd import cfh, hybrid
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
+# the runs stay on at most 2^10 amplitudes; the oracle raises past this bound
+_SUPPORT = 1 << 12
 
 
 def _letters(x, z, n):
@@ -37,7 +42,8 @@ def _letters(x, z, n):
 
 def _inputs(n):
     """Seeded rotations (x masks from a 10-dimensional span), angles, start
-    index (bits 31 and n - 2 set) and an observable with masks from the span."""
+    index (bits n - 2 and min(31, n - 1) set) and an observable with masks
+    from the span."""
     rng = np.random.default_rng(3400 + n)
     D, K, M = 10, 24, 16
     full = (1 << n) - 1
@@ -55,13 +61,14 @@ def _inputs(n):
     rows = np.array([_letters(comb(False), int(rng.integers(0, 1 << 62)) & full, n) for _ in range(K)])
     terms = np.array([_letters(comb(True), int(rng.integers(0, 1 << 62)) & full, n) for _ in range(M)])
     theta = rng.uniform(-np.pi, np.pi, size=K)
-    init = (1 << (n - 2)) | (1 << 31) | int(rng.integers(0, 1 << 31))
+    k = min(31, n - 1)
+    init = (1 << (n - 2)) | (1 << k) | int(rng.integers(0, 1 << k))
     return rows, theta, init, terms, rng.normal(size=M)
 
 
 def _sparse_expval(n, idx, amp, row):
     """<a|P|a> of the sparse state (idx, amp) by the oracle's R_P(pi)."""
-    io, ao = sim.sparse_rotations(n, idx, amp, row[None, :], np.array([np.pi]))
+    io, ao = sim.sparse_rotations(n, idx, amp, row[None, :], np.array([np.pi]), max_out=_SUPPORT)
     _, ia, ib = np.intersect1d(idx, io, assume_unique=True, return_indices=True)
     return 1j * np.sum(np.conj(amp[ia]) * ao[ib])
 
@@ -112,8 +119,22 @@ def test_max_qubits_rotations_and_expval_vs_sparse_oracle(dtype, n):
 
 def _sparse_energy(n, init, rows, theta, terms, coeff):
     """E(theta) = sum_k c_k <a|P_k|a> on the oracle's sparse state."""
-    io, ao = sim.sparse_rotations(n, np.array([init], np.uint64), np.array([1 + 0j]), rows, theta)
+    io, ao = sim.sparse_rotations(n, np.array([init], np.uint64), np.array([1 + 0j]), rows, theta, max_out=_SUPPORT)
     return float(np.real(sum(c * _sparse_expval(n, io, ao, r) for c, r in zip(coeff, terms))))
+
+
+@lru_cache(maxsize=None)
+def _sparse_reference(n):
+    """(energy, parameter-shift gradients) of the seeded circuit on n qubits."""
+    rows, theta, init, terms, coeff = _inputs(n)
+    e = _sparse_energy(n, init, rows, theta, terms, coeff)
+    g = np.zeros(len(theta))
+    for j in range(len(theta)):
+        tp, tm = theta.copy(), theta.copy()
+        tp[j] += np.pi / 2
+        tm[j] -= np.pi / 2
+        g[j] = 0.5 * (_sparse_energy(n, init, rows, tp, terms, coeff) - _sparse_energy(n, init, rows, tm, terms, coeff))
+    return e, g
 
 
 @pytest.mark.parametrize("dtype,n", [(torch.complex64, 33), (torch.complex128, 32)])
@@ -129,14 +150,7 @@ def test_max_qubits_adjoint_gradients_vs_sparse_parameter_shift(dtype, n):
     free, _ = torch.cuda.mem_get_info()
     assert free >= need + (4 << 30), f"{free / 2**30:.1f} GiB free, {need / 2**30:.0f} GiB needed"
     rows, theta, init, terms, coeff = _inputs(n)
-    e_ref = _sparse_energy(n, init, rows, theta, terms, coeff)
-    g_ref = np.zeros(len(theta))
-    for j in range(len(theta)):
-        tp, tm = theta.copy(), theta.copy()
-        tp[j] += np.pi / 2
-        tm[j] -= np.pi / 2
-        g_ref[j] = 0.5 * (_sparse_energy(n, init, rows, tp, terms, coeff) -
-                          _sparse_energy(n, init, rows, tm, terms, coeff))
+    e_ref, g_ref = _sparse_reference(n)
     assert np.count_nonzero(np.abs(g_ref) > 1e-3) >= len(theta) // 2
 
     psi = hybrid.new_state(n, dtype, index=init)
@@ -296,3 +310,35 @@ def test_max_state_empty_observable_and_calibration_kernel():
         torch.cuda.empty_cache()
     assert zmax == 0
     assert dmax <= 1e-15
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+@pytest.mark.parametrize("variant", [0, 1], ids=["levels", "persistent"])
+def test_batch_largest_circuits_vs_sparse_oracle(dtype, variant):
+    """A batch with the largest circuits it accepts (30 and 29 qubits, beside
+    a 12-qubit one; 48 GiB of states and lambda vectors at complex128), under
+    level launches and the persistent kernel: energies and every gradient
+    against the sparse oracle (parameter shift), within 1e-12 * sum |c_j|
+    and 1e-10 at complex128, 1e-4 * sum |c_j| at complex64."""
+    torch.cuda.empty_cache()
+    ws = []
+    for n in (30, 29, 12):
+        rows, theta, init, terms, coeff = _inputs(n)
+        ws.append(SimpleNamespace(n=n, prefix=np.zeros((0, 3), np.int32), init=init, rot=rows, theta=theta,
+                                  ham=terms, coeff=coeff, n_rot=len(theta)))
+    B = hybrid.Batch(ws, dtype, {"variant": 1} if variant else None)
+    try:
+        B.run(True)
+        r = B.results()
+    finally:
+        del B
+        torch.cuda.empty_cache()
+    for i, w in enumerate(ws):
+        e_ref, g_ref = _sparse_reference(w.n)
+        scale = np.abs(w.coeff).sum()
+        etol = (1e-12 if dtype == torch.complex128 else 1e-4) * scale
+        gtol = 1e-10 if dtype == torch.complex128 else 1e-4 * scale
+        print(f"n={w.n}: |dE| {abs(r['energy'][i] - e_ref):.2e}, max |dg| {np.abs(r['grad'][i] - g_ref).max():.2e}",
+              flush=True)
+        assert abs(r["energy"][i] - e_ref) <= etol, i
+        assert np.abs(r["grad"][i] - g_ref).max() <= gtol, i
