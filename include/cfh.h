@@ -101,7 +101,8 @@ typedef struct cfh_tuning {
                               also selects the register-tiled adjoint sweep (1: LDS-staged).
                               Batches: 0 = register-tiled passes on 2^12 tiles for circuits with
                               n >= 12 (LDS-staged for smaller ones), 2 = LDS-staged passes only */
-    int32_t batch_items;   /* batched runs: at most this many work items per pass (0 = 32) */
+    int32_t batch_items;   /* batched runs: work items per pass (0 = 32); a pass gets more when an item
+                              would cover more than 64 tiles */
     int32_t group_mib;     /* batched runs: circuits are scheduled in consecutive groups whose
                               state and lam vectors fit this many MiB (so the 256 MiB Infinity Cache
                               can keep a group resident across its levels); <= 0 = one group */
@@ -424,8 +425,10 @@ typedef struct cfh_circuit_desc {
  * and H psi and adjoint passes on register tiles (gradient runs); smaller
  * circuits, and every circuit under variant 2, use LDS-staged passes on tiles
  * of 2^min(n, tile_bits) amplitudes (default 2^10) only.  Passes are cut
- * into at most tuning->batch_items work items each and queued level by level
- * across circuits.  Variant 1 plans the same register-tiled passes and runs
+ * into tuning->batch_items work items each (fewer when a pass has fewer
+ * tiles; more when an item would cover more than 64 tiles, so that a large
+ * circuit's pass spreads over the GPU) and queued level by level across
+ * circuits.  Variant 1 plans the same register-tiled passes and runs
  * each run as one persistent kernel (see cfh_batch_run); it needs every
  * circuit to have n >= the register tile and at least one rotation.  States,
  * angles, gradients, partial sums and the work-item tables live in one

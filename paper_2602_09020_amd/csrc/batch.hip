@@ -452,7 +452,7 @@ void plan_circuit(const cfh_circuit_desc &d, const BatchSettings &S, CircPlan &o
     const TuningResolved &tu = out.tu;
     out.b = tu.tile_bits;
     const uint64_t ntiles = 1ull << (d.n - out.b);
-    out.tpi = (int)std::max<uint64_t>(1, (ntiles + S.max_items - 1) / S.max_items);
+    out.tpi = (int)std::clamp<uint64_t>((ntiles + S.max_items - 1) / S.max_items, 1, kBatchMaxTilesPerItem);
     out.nitems = (int)((ntiles + out.tpi - 1) / out.tpi);
     const bool reg = S.reg_fwd && d.n >= S.reg_bits && d.m > 0;
     out.reg = reg;
@@ -460,7 +460,7 @@ void plan_circuit(const cfh_circuit_desc &d, const BatchSettings &S, CircPlan &o
         return fail(set_error(CFH_E_UNSUPPORTED, "cfh_batch_create: a persistent batch needs every circuit on "
                                                  "register tiles (n >= reg_tile_bits and at least one rotation)"));
     const uint64_t nt2 = reg ? 1ull << (d.n - S.reg_bits) : 1;
-    out.tpi2 = (int)std::max<uint64_t>(1, (nt2 + S.max_items - 1) / S.max_items);
+    out.tpi2 = (int)std::clamp<uint64_t>((nt2 + S.max_items - 1) / S.max_items, 1, kBatchMaxTilesPerItem);
     out.nitems2 = (int)((nt2 + out.tpi2 - 1) / out.tpi2);
     // LDS-staged plan of circuits below the register tile (or under tuning
     // variant 2): forward passes and, walked backwards, adjoint passes

@@ -148,6 +148,12 @@ extern template cfh_status launch_batch_persist<float2>(int, bool, int, hipStrea
 // PassArgs2 is pa[passes[item.pass].p2].  The first pass of a circuit builds
 // its basis state instead of reading psi.
 constexpr int kBatchRegTile = 12;  // default register tile (tuning reg_tile_bits)
+// A work item covers at most this many tiles.  A pass is cut into the tuned
+// number of items (tuning batch_items), or into more when its tiles would
+// exceed this bound, so that the passes of large circuits spread over the GPU
+// even when such a circuit runs alone (a 30-qubit pass on 2^12 tiles: 4,096
+// items instead of 32).  Circuits of up to 20 qubits never reach it.
+constexpr uint64_t kBatchMaxTilesPerItem = 64;
 // Complex128 items transpose in two halves through half the LDS (anchored
 // micro-groups), so as many workgroups fit on a CU as complex64 ones do with
 // whole-tile transposes.

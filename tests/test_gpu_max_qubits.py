@@ -312,6 +312,13 @@ def test_max_state_empty_observable_and_calibration_kernel():
     assert dmax <= 1e-15
 
 
+def _circuit(n):
+    """The seeded circuit on n qubits as a batch workload (no Clifford prefix)."""
+    rows, theta, init, terms, coeff = _inputs(n)
+    return SimpleNamespace(n=n, prefix=np.zeros((0, 3), np.int32), init=init, rot=rows, theta=theta, ham=terms,
+                           coeff=coeff, n_rot=len(theta))
+
+
 @pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
 @pytest.mark.parametrize("variant", [0, 1], ids=["levels", "persistent"])
 def test_batch_largest_circuits_vs_sparse_oracle(dtype, variant):
@@ -321,11 +328,7 @@ def test_batch_largest_circuits_vs_sparse_oracle(dtype, variant):
     against the sparse oracle (parameter shift), within 1e-12 * sum |c_j|
     and 1e-10 at complex128, 1e-4 * sum |c_j| at complex64."""
     torch.cuda.empty_cache()
-    ws = []
-    for n in (30, 29, 12):
-        rows, theta, init, terms, coeff = _inputs(n)
-        ws.append(SimpleNamespace(n=n, prefix=np.zeros((0, 3), np.int32), init=init, rot=rows, theta=theta,
-                                  ham=terms, coeff=coeff, n_rot=len(theta)))
+    ws = [_circuit(n) for n in (30, 29, 12)]
     B = hybrid.Batch(ws, dtype, {"variant": 1} if variant else None)
     try:
         B.run(True)
@@ -342,3 +345,27 @@ def test_batch_largest_circuits_vs_sparse_oracle(dtype, variant):
               flush=True)
         assert abs(r["energy"][i] - e_ref) <= etol, i
         assert np.abs(r["grad"][i] - g_ref).max() <= gtol, i
+
+
+def test_batch_items_of_a_large_circuit_cover_at_most_64_tiles():
+    """A pass is cut into batch_items work items, or into more when an item
+    would cover more than 64 tiles, so a large circuit's passes spread over
+    the GPU.  One 26-qubit circuit (2^14 register tiles per pass): 256 items
+    per pass at batch_items = 8 and 4,096 at batch_items = 4,096, the same
+    passes, so exactly 16 times as many items in a gradient run; both against
+    the sparse oracle at the complex128 bounds."""
+    torch.cuda.empty_cache()
+    w = _circuit(26)
+    e_ref, g_ref = _sparse_reference(26)
+    scale = np.abs(w.coeff).sum()
+    items = {}
+    for k in (8, 4096):
+        B = hybrid.Batch([w], torch.complex128, {"batch_items": k})
+        items[k] = B.info()["n_items_grad"]
+        B.run(True)
+        r = B.results()
+        del B
+        assert abs(r["energy"][0] - e_ref) <= 1e-12 * scale
+        assert np.abs(r["grad"][0] - g_ref).max() <= 1e-10
+    torch.cuda.empty_cache()
+    assert items[8] * 16 == items[4096], items
