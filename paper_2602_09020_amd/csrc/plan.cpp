@@ -349,10 +349,12 @@ std::vector<HamPass> plan_hamiltonian(int n, const std::vector<HamGroup> &groups
     std::vector<HamPass> out;
     while (!rem.empty()) {
         int nterms = 0;
-        // Grow a b-dimensional subspace greedily.  Sparse x masks (JW strings)
-        // are covered best by whole qubits (unit vectors: one tile then holds
-        // every group inside those qubits); a dense x that would need too many
-        // qubits is added as one vector.  Every group fits some pass, since a
+        // Grow a b-dimensional subspace greedily: each step adds one group's
+        // reduced x as one new dimension, and every group whose x then lies in
+        // the span joins for free.  (Covering a group by whole qubits, one unit
+        // vector per new qubit, spends more dimensions per group; it packed
+        // fewer groups per pass both for JW strings and for the dense masks
+        // that a Clifford prefix leaves.)  Every group fits some pass, since a
         // single x adds at most one dimension.
         Span s;
         for (int j = 0; j < c; ++j) s.add(1ull << j);
@@ -389,9 +391,9 @@ std::vector<HamPass> plan_hamiltonian(int n, const std::vector<HamGroup> &groups
             newly.clear();
         };
         while ((int)chosen.size() < max_groups && nterms < max_terms && s.dim() < b) {
-            // the first group that costs the fewest new dimensions; a group
-            // that fits and costs none was taken by the sweep, so the first
-            // one costing one dimension ends the scan
+            // the first group whose reduced x has the fewest set bits; a group
+            // that fits and reduces to zero was taken by the sweep, so the
+            // first one with a single bit ends the scan
             int best = -1, best_cost = 1 << 30;
             uint64_t best_r = 0;
             for (const int g : rem) {
@@ -406,14 +408,7 @@ std::vector<HamPass> plan_hamiltonian(int n, const std::vector<HamGroup> &groups
                 }
             }
             if (best < 0) break;
-            if (best_cost <= b - s.dim()) {
-                for (uint64_t r = best_r; r; r &= r - 1) {
-                    const uint64_t e = s.reduce(r & (~r + 1));
-                    if (e) add(e);
-                }
-            } else {
-                add(best_r);
-            }
+            add(best_r);
             sweep();
         }
         if (chosen.empty()) {
