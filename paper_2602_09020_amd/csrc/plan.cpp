@@ -346,11 +346,24 @@ std::vector<HamPass> plan_hamiltonian(int n, const std::vector<HamGroup> &groups
     // red[g]: groups[g].x reduced against the current span (zero at every
     // pivot; unique), kept up to date as vectors join the span
     std::vector<uint64_t> red(G);
+    // open-addressing table: reduced mask -> number of candidate groups with
+    // that mask; only the slots used in a step are cleared after it
+    int lg = 4;
+    while ((1ll << lg) < 2ll * G) ++lg;
+    const size_t cap = (size_t)1 << lg;
+    std::vector<uint64_t> hkey(cap, 0);
+    std::vector<int32_t> hcnt(cap, 0);
+    std::vector<size_t> hused;
+    auto slot = [&](uint64_t r) {
+        size_t i = (size_t)((r * 0x9E3779B97F4A7C15ull) >> (64 - lg));
+        while (hkey[i] != 0 && hkey[i] != r) i = (i + 1) & (cap - 1);
+        return i;
+    };
     std::vector<HamPass> out;
     while (!rem.empty()) {
         int nterms = 0;
-        // Grow a b-dimensional subspace greedily: each step adds one group's
-        // reduced x as one new dimension, and every group whose x then lies in
+        // Grow a b-dimensional subspace greedily: each step adds one reduced
+        // x mask as one new dimension, and every group whose x then lies in
         // the span joins for free.  (Covering a group by whole qubits, one unit
         // vector per new qubit, spends more dimensions per group; it packed
         // fewer groups per pass both for JW strings and for the dense masks
@@ -391,22 +404,37 @@ std::vector<HamPass> plan_hamiltonian(int n, const std::vector<HamGroup> &groups
             newly.clear();
         };
         while ((int)chosen.size() < max_groups && nterms < max_terms && s.dim() < b) {
-            // the first group whose reduced x has the fewest set bits; a group
-            // that fits and reduces to zero was taken by the sweep, so the
-            // first one with a single bit ends the scan
-            int best = -1, best_cost = 1 << 30;
+            // The reduced mask shared by the most candidate groups (those not
+            // taken that still fit): adding it brings all of them into the
+            // span at the cost of one dimension.  Ties go to the mask with the
+            // fewest set bits, then to the first group in rem order.  (A
+            // candidate that reduces to zero was taken by the sweep.)
+            for (const int g : rem) {
+                if (in[g] || !fits(g) || !red[g]) continue;
+                const size_t i = slot(red[g]);
+                if (!hkey[i]) {
+                    hkey[i] = red[g];
+                    hused.push_back(i);
+                }
+                ++hcnt[i];
+            }
+            int best = -1, best_n = 0, best_cost = 1 << 30;
             uint64_t best_r = 0;
             for (const int g : rem) {
-                if (in[g] || !fits(g)) continue;
-                const uint64_t r = red[g];
-                const int cost = popc(r);
-                if (cost < best_cost) {
+                if (in[g] || !fits(g) || !red[g]) continue;
+                const int nn = hcnt[slot(red[g])], cost = popc(red[g]);
+                if (nn > best_n || (nn == best_n && cost < best_cost)) {
+                    best_n = nn;
                     best_cost = cost;
                     best = g;
-                    best_r = r;
-                    if (cost <= 1) break;
+                    best_r = red[g];
                 }
             }
+            for (const size_t i : hused) {
+                hkey[i] = 0;
+                hcnt[i] = 0;
+            }
+            hused.clear();
             if (best < 0) break;
             add(best_r);
             sweep();
