@@ -20,17 +20,19 @@ TuningResolved resolve_tuning(const cfh_tuning *t, int n, int dtype, int kind)
     // 2^13.  Small states keep at least 128 tiles per pass: their passes are
     // short and latency-bound, so fewer, larger passes win until the grid gets
     // too small (measured at 18-24 qubits).  The adjoint holds two tiles in LDS and uses 2^11 (c128) / 2^12
-    // (c64).  The read-only Hamiltonian passes use 2^12 / 2^13 tiles with
+    // (c64).  The LDS-staged Hamiltonian passes use 2^12 / 2^13 tiles with
     // 32-amplitude chunks.
     int b = c64 ? 13 : 14;
     if (kind == kTuneAdjoint) b = c64 ? 12 : 11;
     if (kind == kTuneHamiltonian) b = c64 ? 13 : 12;
     if (kind == kTuneAdjoint2) b = 13;
-    // read-only <H> passes at complex128: 2^13 tiles with half-tile
-    // transposes leave LDS for two workgroups per CU, which overlap one
-    // workgroup's loads with the other's term sums (28 qubits, 2,000 terms:
-    // 2^13 126 ms, 2^14 139 ms, 2^12 129 ms)
-    if (kind == kTuneMeasure && !c64) b = 13;
+    // read-only <H> passes (and the H psi passes, whose tile follows): 2^12
+    // tiles at both storage types.  Smaller tiles hold fewer terms per pass
+    // but need fewer micro-group transposes per term, and more workgroups fit
+    // a CU.  Measured on the 28-qubit, 2,000-term observable, complex128:
+    // <H> 2^12 103 ms, 2^13 110 ms, 2^14 132 ms; H psi 323 / 333 ms at 2^12 /
+    // 2^13; complex64 <H> 83 / 85 ms, H psi 265 / 332 ms.
+    if (kind == kTuneMeasure) b = 12;
     // the adjoint holds two vectors per workgroup (fewer workgroups per CU),
     // so it keeps at least 256 tiles
     b = std::max(std::min(b, n - (kind == kTuneAdjoint2 ? 8 : 7)), std::min(n, 10));
