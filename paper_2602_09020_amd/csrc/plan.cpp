@@ -26,13 +26,15 @@ TuningResolved resolve_tuning(const cfh_tuning *t, int n, int dtype, int kind)
     if (kind == kTuneAdjoint) b = c64 ? 12 : 11;
     if (kind == kTuneHamiltonian) b = c64 ? 13 : 12;
     if (kind == kTuneAdjoint2) b = 13;
-    // read-only <H> passes (and the H psi passes, whose tile follows): 2^12
-    // tiles at both storage types.  Smaller tiles hold fewer terms per pass
-    // but need fewer micro-group transposes per term, and more workgroups fit
-    // a CU.  Measured on the 28-qubit, 2,000-term observable, complex128:
-    // <H> 2^12 103 ms, 2^13 110 ms, 2^14 132 ms; H psi 323 / 333 ms at 2^12 /
-    // 2^13; complex64 <H> 83 / 85 ms, H psi 265 / 332 ms.
-    if (kind == kTuneMeasure) b = 12;
+    // read-only <H> passes (and the H psi passes, whose tile follows): 2^11
+    // tiles at complex128, 2^12 at complex64.  Smaller tiles hold fewer terms
+    // per pass but need fewer micro-group transposes per term, and more
+    // workgroups fit a CU, down to 2^11.  Measured on the 28-qubit,
+    // 2,000-term observable, complex128: <H> 2^10 135 ms, 2^11 99.6 ms, 2^12
+    // 103 ms, 2^13 110 ms, 2^14 132 ms; H psi 351 / 309 / 324 / 333 ms at
+    // 2^10..2^13; complex64 <H> 83.0 / 82.2 / 85.5 ms at 2^11..2^13, H psi
+    // 265 / 332 ms at 2^12 / 2^13.
+    if (kind == kTuneMeasure) b = c64 ? 12 : 11;
     // the adjoint holds two vectors per workgroup (fewer workgroups per CU),
     // so it keeps at least 256 tiles
     b = std::max(std::min(b, n - (kind == kTuneAdjoint2 ? 8 : 7)), std::min(n, 10));
