@@ -259,13 +259,27 @@ cfh_status cfh_apply_plan(cfh_plan p, void *psi, const double *theta_dev, int in
  * variant 5 moves the registers between micro-groups in two halves, as
  * 2^14 tiles always do).
  * H*psi runs on register-tiled passes that hold psi and H psi together
- * (tiles of at most 2^13 complex128 / 2^14 complex64 amplitudes, at least
- * 256 tiles per pass), or on LDS-staged passes where the register-tiled
- * <H> passes are not selected.  Allocates device memory.  Errors as
- * cfh_plan_create. */
+ * (the <H> tile capped at 2^13 amplitudes, at least 256 tiles per pass), or
+ * on LDS-staged passes where the register-tiled <H> passes are not
+ * selected.  Allocates device memory.  Errors as cfh_plan_create. */
 cfh_status cfh_ham_create(int n, int dtype, const cfh_pauli *terms, const double *coeff, size_t m,
                           const cfh_tuning *tuning, cfh_ham *out);
 cfh_status cfh_ham_destroy(cfh_ham h);
+
+/* Host-only planning (no device memory, usable without a GPU): the
+ * register-tiled <H> passes cfh_ham_create would build for these terms
+ * (Eq. chfsexp summed pass by pass: each pass reads the state once and adds
+ * the terms whose x masks lie in its tile's span).  Arrays are caller-owned:
+ * pass_start needs m+1 entries, order and pass_bits m, basis 16*m words.
+ * *n_passes receives the pass count P; pass_start[0..P] are prefix offsets
+ * into order, which lists term indices in evaluation order; pass p's tile
+ * is spanned by the pass_bits[p] index masks basis[16p .. 16p+pass_bits[p]-1]
+ * (the rest of its 16 words are zero).  Errors: CFH_E_INVAL (null
+ * argument), CFH_E_RANGE and CFH_E_NOT_HERMITIAN (a term), CFH_E_UNSUPPORTED
+ * (n outside 1..34, dtype, or a tuning that selects LDS-staged <H> passes). */
+cfh_status cfh_ham_dry_run(int n, int dtype, const cfh_pauli *terms, size_t m, const cfh_tuning *tuning,
+                           int64_t *n_passes, int64_t *pass_start, int64_t *order, int32_t *pass_bits,
+                           uint64_t *basis);
 /* Read passes of one <H>, distinct x masks, and the HBM bytes those passes
  * read (2^n * bytes per amplitude each).  Any pointer may be NULL. */
 cfh_status cfh_ham_info(cfh_ham h, int64_t *n_passes, int64_t *n_groups, double *hbm_bytes);

@@ -81,6 +81,8 @@ _SIGS = {
     "cfh_plan_create": (C.c_int32, [C.c_int, C.c_int, _vp, C.c_size_t, _P(cfh_tuning), _P(_vp)]),
     "cfh_plan_destroy": (C.c_int32, [_vp]),
     "cfh_plan_dry_run": (C.c_int32, [C.c_int, C.c_int, _vp, C.c_size_t, _P(cfh_tuning), _P(C.c_int64), _vp, _vp]),
+    "cfh_ham_dry_run": (C.c_int32, [C.c_int, C.c_int, _vp, C.c_size_t, _P(cfh_tuning), _P(C.c_int64), _vp, _vp,
+                                    _vp, _vp]),
     "cfh_plan_info": (C.c_int32, [_vp, _P(C.c_int64), _P(C.c_int64), _P(C.c_int32), _P(C.c_double),
                                   _P(C.c_int32)]),
     "cfh_plan_schedule": (C.c_int32, [_vp, _vp, _vp]),
@@ -326,6 +328,23 @@ def cfh_plan_create(n: int, dtype: int, rot: np.ndarray, tuning=None) -> int:
 
 def cfh_plan_destroy(p: int) -> None:
     _call("cfh_plan_destroy", p)
+
+
+def cfh_ham_dry_run(n: int, dtype: int, terms: np.ndarray, tuning=None):
+    """Host-only planning of the register-tiled <H> passes: returns
+    (pass_start, order, pass_bits, basis) with basis of shape (P, 16)."""
+    a = _paulis(terms)
+    m = a.shape[0]
+    ps = np.zeros(m + 1, np.int64)
+    order = np.zeros(max(m, 1), np.int64)
+    bits = np.zeros(max(m, 1), np.int32)
+    basis = np.zeros((max(m, 1), 16), np.uint64)
+    cnt = C.c_int64()
+    t = _tuning(tuning)
+    _call("cfh_ham_dry_run", n, dtype, a.ctypes.data if m else None, m, C.byref(t) if t is not None else None,
+          C.byref(cnt), ps.ctypes.data, order.ctypes.data, bits.ctypes.data, basis.ctypes.data)
+    P = cnt.value
+    return ps[:P + 1].copy(), order[:m].copy(), bits[:P].copy(), basis[:P].copy()
 
 
 def cfh_plan_dry_run(n: int, dtype: int, rot: np.ndarray, tuning=None):
