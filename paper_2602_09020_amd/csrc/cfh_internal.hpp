@@ -211,6 +211,23 @@ cfh_status set_error(cfh_status code, const std::string &msg);
 void clear_error();
 cfh_status check_pauli(const cfh_pauli &p, int n, bool need_hermitian, const char *what);
 
+// Observable planning (plan.cpp): the x-groups of the terms in first-appearance
+// order; how <H> runs (measurement tuning, register tiles or LDS-staged,
+// anchored half-tile transposes); the register-tiled term passes.
+// How <H> runs: the measurement tuning, whether it runs on register tiles
+// (tiles of 2^10..2^14 amplitudes, not tuning variant 1), and whether its
+// micro-groups share an anchor vector for half-tile transposes (required at
+// 2^14, the default at complex128, selectable by variant 5).
+struct MeasureSettings {
+    TuningResolved tm;
+    bool reg, anchor;
+};
+std::vector<HamGroup> group_terms(const cfh_pauli *terms, size_t m);
+MeasureSettings measure_settings(const cfh_tuning *tuning, int n, int dtype, size_t m);
+cfh_status term_passes(int n, int dtype, const std::vector<HamGroup> &groups, const std::vector<Pauli> &tp,
+                       const TuningResolved &tm, bool anchor, std::vector<PassArgs2> &out, const char *what);
+
+
 } // namespace cfh
 
 // Opaque handle bodies.

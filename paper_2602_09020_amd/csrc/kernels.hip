@@ -778,85 +778,6 @@ struct cfh_ham_s {
 
 namespace {
 
-// The x-groups of an observable's terms, in first-appearance order.
-std::vector<HamGroup> group_terms(const cfh_pauli *terms, size_t m)
-{
-    std::map<uint64_t, int> gid;
-    std::vector<HamGroup> groups;
-    for (size_t i = 0; i < m; ++i) {
-        auto it = gid.find(terms[i].x);
-        if (it == gid.end()) {
-            gid[terms[i].x] = (int)groups.size();
-            groups.push_back(HamGroup{terms[i].x, {(int)i}});
-        } else {
-            groups[it->second].terms.push_back((int)i);
-        }
-    }
-    return groups;
-}
-
-// How <H> runs: the measurement tuning, whether it runs on register tiles
-// (tiles of 2^10..2^14 amplitudes, not tuning variant 1), and whether its
-// micro-groups share an anchor vector for half-tile transposes (required at
-// 2^14, the default at complex128, selectable by variant 5).
-struct MeasureSettings {
-    TuningResolved tm;
-    bool reg, anchor;
-};
-MeasureSettings measure_settings(const cfh_tuning *tuning, int n, int dtype, size_t m)
-{
-    MeasureSettings ms;
-    ms.tm = resolve_tuning(tuning, n, dtype, kTuneMeasure);
-    ms.reg = ms.tm.variant != 1 && ms.tm.tile_bits >= 10 && ms.tm.tile_bits <= 14 && m > 0;
-    ms.anchor = ms.tm.tile_bits == 14 || ms.tm.variant == 5 || (ms.tm.variant == 0 && dtype == CFH_C128);
-    return ms;
-}
-
-// Register-tiled passes over the terms of an observable: the x-groups (split
-// to at most kMaxRun terms) planned onto tiles, each pass's terms ordered so
-// consecutive ones share register micro-groups (anchored for half-tile
-// transposes), runs that need more micro-groups split in two.
-cfh_status term_passes(int n, int dtype, const std::vector<HamGroup> &groups, const std::vector<Pauli> &tp,
-                       const TuningResolved &tm, bool anchor, std::vector<PassArgs2> &out, const char *what)
-{
-    std::vector<HamGroup> mg;
-    for (const HamGroup &g : groups)
-        for (size_t i = 0; i < g.terms.size(); i += kMaxRun)
-            mg.push_back(HamGroup{g.x, std::vector<int>(g.terms.begin() + (std::ptrdiff_t)i,
-                                                        g.terms.begin() +
-                                                            (std::ptrdiff_t)std::min(g.terms.size(), i + kMaxRun))});
-    std::vector<PassPlan> todo;
-    for (const HamPass &hp : plan_hamiltonian(n, mg, tm, kMaxGroupsPerPass, kMaxRun)) {
-        std::vector<int> idx;
-        for (int g : hp.groups) idx.insert(idx.end(), mg[g].terms.begin(), mg[g].terms.end());
-        PassPlan pp;
-        pp.b = hp.b;
-        pp.outer_mask = hp.outer_mask;
-        pp.v = hp.v;
-        pp.rots = order_for_microgroups(hp.v, tp, idx, anchor);
-        todo.push_back(std::move(pp));
-    }
-    std::reverse(todo.begin(), todo.end());
-    PassArgs2 a2;
-    while (!todo.empty()) {
-        PassPlan pp = std::move(todo.back());
-        todo.pop_back();
-        if (build_pass_args2(pp, tp, false, anchor, a2)) {
-            a2.xrot = line_share_bits(a2.outer_mask, n, a2.b, (int)amp_bytes(dtype), tm.tile_order);
-            out.push_back(a2);
-            continue;
-        }
-        if (pp.rots.size() < 2) return set_error(CFH_E_INVAL, std::string(what) + ": a term does not fit the tile");
-        PassPlan hi = pp;
-        const size_t half = pp.rots.size() / 2;
-        hi.rots.assign(pp.rots.begin() + (std::ptrdiff_t)half, pp.rots.end());
-        pp.rots.resize(half);
-        todo.push_back(std::move(hi));
-        todo.push_back(std::move(pp));
-    }
-    return CFH_OK;
-}
-
 // A planning task run on its own thread, or on the caller's if no thread can
 // be started.  finish() joins it and returns its status, with its error
 // message set again on the calling thread.  The destructor joins a task that
@@ -1344,46 +1265,6 @@ cfh_status cfh_ham_create(int n, int dtype, const cfh_pauli *terms, const double
     const size_t np = std::max<size_t>(h->grid, cfh_ham_s::kMeasureGrid);
     if (!hip_ok(hipMalloc(&h->partial, np * sizeof(double2)), "cfh_ham_create: hipMalloc", &st)) return st;
     *out = h.release();
-    return CFH_OK;
-}
-
-cfh_status cfh_ham_dry_run(int n, int dtype, const cfh_pauli *terms, size_t m, const cfh_tuning *tuning,
-                           int64_t *n_passes, int64_t *pass_start, int64_t *order, int32_t *pass_bits,
-                           uint64_t *basis)
-{
-    if (!n_passes || !pass_start || (m && (!terms || !order || !pass_bits || !basis)))
-        return set_error(CFH_E_INVAL, "cfh_ham_dry_run: null argument");
-    if (n < 1 || n > kMaxStateQubits) return set_error(CFH_E_UNSUPPORTED, "cfh_ham_dry_run: n must be in 1..34");
-    if (dtype != CFH_C64 && dtype != CFH_C128) return set_error(CFH_E_UNSUPPORTED, "cfh_ham_dry_run: dtype");
-    for (size_t i = 0; i < m; ++i) {
-        cfh_status st = check_pauli(terms[i], n, true, "cfh_ham_dry_run");
-        if (st) return st;
-    }
-    const MeasureSettings ms = measure_settings(tuning, n, dtype, m);
-    if (m && !ms.reg)
-        return set_error(CFH_E_UNSUPPORTED, "cfh_ham_dry_run: <H> does not run on register tiles under this tuning");
-    std::vector<PassArgs2> margs;
-    if (m) {
-        std::vector<Pauli> tp(m);
-        for (size_t i = 0; i < m; ++i) tp[i] = Pauli{terms[i].x, terms[i].z, terms[i].e & 3};
-        cfh_status st = term_passes(n, dtype, group_terms(terms, m), tp, ms.tm, ms.anchor, margs, "cfh_ham_dry_run");
-        if (st) return st;
-    }
-    // every pass holds at least one term and every term one place, so the
-    // caller's m-entry arrays suffice; checked before each write
-    int64_t o = 0;
-    pass_start[0] = 0;
-    for (size_t p = 0; p < margs.size(); ++p) {
-        const PassArgs2 &a = margs[p];
-        const int nt = a.nmg > 0 ? a.mg[a.nmg - 1].rot_begin + a.mg[a.nmg - 1].rot_count : 0;
-        if (p >= m || o + nt > (int64_t)m)
-            return set_error(CFH_E_INVAL, "cfh_ham_dry_run: the plan places more terms than given");
-        for (int j = 0; j < nt; ++j) order[o++] = a.rot[j].k;
-        pass_start[p + 1] = o;
-        pass_bits[p] = a.b;
-        for (int i = 0; i < kMaxTileBits; ++i) basis[p * kMaxTileBits + i] = i < a.b ? a.v[i] : 0;
-    }
-    *n_passes = (int64_t)margs.size();
     return CFH_OK;
 }
 
