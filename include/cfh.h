@@ -33,6 +33,13 @@
  *     pointers passed in stay owned by the caller, who keeps them alive until
  *     the enqueued work has finished.  Handles (frames, plans, Hamiltonians,
  *     batches) are owned by the library and freed by their destroy call.
+ *   - Calls may come from several host threads at once.  Calls that use the
+ *     same handle or the same device buffers must not overlap in time (the
+ *     caller orders them); calls on different handles and buffers are
+ *     independent.  The library's own shared state (per-kernel launch
+ *     settings, the occupancy cache) is set up under a lock or once; the
+ *     allocation-free cfh_expval_noalloc shares one scratch array per GPU
+ *     (see there).
  */
 #ifndef CFH_H
 #define CFH_H

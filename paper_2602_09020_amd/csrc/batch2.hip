@@ -8,6 +8,8 @@
 // Here every workgroup is one work item of a level: a range of cosets of one
 // pass of one circuit, whose PassArgs2 sits in device memory.  The first pass
 // of a circuit builds the initial basis state instead of reading psi.
+#include <atomic>
+
 #include "batch.hpp"
 #include "pass2.hpp"
 
@@ -632,10 +634,10 @@ cfh_status launch_batch_fwd2_b(unsigned grid, hipStream_t s, const BatchArgs &A,
     constexpr int T = 1 << (B - kRegDims);
     constexpr bool HALF = batch_fwd_half((int)sizeof(Amp));
     constexpr size_t lds = ((size_t)1 << (HALF ? B - 1 : B)) * sizeof(Amp);
-    static bool attr = false;
-    if (!attr) {
+    static std::atomic<bool> attr{false};  // LDS limit set once per kernel
+    if (!attr.load(std::memory_order_acquire)) {
         if (cfh_status st = set_lds_limit(&k_batch_fwd2<Amp, B, HALF>, "k_batch_fwd2: LDS limit")) return st;
-        attr = true;
+        attr.store(true, std::memory_order_release);
     }
     hipLaunchKernelGGL((k_batch_fwd2<Amp, B, HALF>), dim3(grid), dim3(T), lds, s, A, pa, items);
     return last_launch("k_batch_fwd2");
@@ -648,10 +650,10 @@ cfh_status launch_batch_meas2_b(unsigned grid, hipStream_t s, const BatchArgs &A
     constexpr int T = 1 << (B - kRegDims);
     constexpr bool HALF = batch_fwd_half((int)sizeof(Amp));
     constexpr size_t lds = ((size_t)1 << (HALF ? B - 1 : B)) * sizeof(Amp);
-    static bool attr = false;
-    if (!attr) {
+    static std::atomic<bool> attr{false};  // LDS limit set once per kernel
+    if (!attr.load(std::memory_order_acquire)) {
         if (cfh_status st = set_lds_limit(&k_batch_meas2<Amp, B, HALF>, "k_batch_meas2: LDS limit")) return st;
-        attr = true;
+        attr.store(true, std::memory_order_release);
     }
     hipLaunchKernelGGL((k_batch_meas2<Amp, B, HALF>), dim3(grid), dim3(T), lds, s, A, pa, items);
     return last_launch("k_batch_meas2");
@@ -665,10 +667,10 @@ cfh_status launch_batch_ham2_b(unsigned grid, hipStream_t s, const BatchArgs &A,
     constexpr bool HALF = batch_fwd_half((int)sizeof(Amp));
     // psi and lam buffers: half tiles at complex128, whole tiles at complex64
     constexpr size_t lds = 2 * ((size_t)1 << (HALF ? B - 1 : B)) * sizeof(Amp);
-    static bool attr = false;
-    if (!attr) {
+    static std::atomic<bool> attr{false};  // LDS limit set once per kernel
+    if (!attr.load(std::memory_order_acquire)) {
         if (cfh_status st = set_lds_limit(&k_batch_ham2<Amp, B, HALF>, "k_batch_ham2: LDS limit")) return st;
-        attr = true;
+        attr.store(true, std::memory_order_release);
     }
     hipLaunchKernelGGL((k_batch_ham2<Amp, B, HALF>), dim3(grid), dim3(T), lds, s, A, pa, items);
     return last_launch("k_batch_ham2");
@@ -682,10 +684,10 @@ cfh_status launch_batch_adj2_b(unsigned grid, hipStream_t s, const BatchArgs &A,
     constexpr bool HALF = batch_fwd_half((int)sizeof(Amp));
     // psi and lam buffers: half tiles at complex128, whole tiles at complex64
     constexpr size_t lds = 2 * ((size_t)1 << (HALF ? B - 1 : B)) * sizeof(Amp);
-    static bool attr = false;
-    if (!attr) {
+    static std::atomic<bool> attr{false};  // LDS limit set once per kernel
+    if (!attr.load(std::memory_order_acquire)) {
         if (cfh_status st = set_lds_limit(&k_batch_adj2<Amp, B, HALF>, "k_batch_adj2: LDS limit")) return st;
-        attr = true;
+        attr.store(true, std::memory_order_release);
     }
     hipLaunchKernelGGL((k_batch_adj2<Amp, B, HALF>), dim3(grid), dim3(T), lds, s, A, pa, items);
     return last_launch("k_batch_adj2");
@@ -757,10 +759,10 @@ cfh_status launch_batch_persist_b(int max_grid, hipStream_t s, const BatchArgs &
     constexpr int T = 1 << (B - kRegDims);
     constexpr size_t lds = persist_lds<Amp, B, GRAD>();
     auto kern = &k_batch_persist<Amp, B, GRAD>;
-    static bool attr = false;
-    if (!attr) {
+    static std::atomic<bool> attr{false};  // LDS limit set once per kernel
+    if (!attr.load(std::memory_order_acquire)) {
         if (cfh_status st = set_lds_limit(kern, "k_batch_persist: LDS limit")) return st;
-        attr = true;
+        attr.store(true, std::memory_order_release);
     }
     // the current device's CUs and the workgroups of this kernel that fit on one
     int per_cu = 0, cus = 0, dev = 0;

@@ -16,6 +16,7 @@
 #include <thread>
 #include <tuple>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -45,7 +46,11 @@ cfh_status last_launch(const char *what)
 // kernel, LDS size and device).
 unsigned resident_grid(const void *fn, int threads, size_t lds)
 {
+    // one cache for every thread that launches (the lock is uncontended after
+    // each kernel's first launch)
+    static std::mutex mu;
     static std::map<std::tuple<const void *, size_t, int>, unsigned> cache;
+    std::lock_guard<std::mutex> lock(mu);
     int dev = 0;
     (void)hipGetDevice(&dev);
     const auto key = std::make_tuple(fn, lds, dev);

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 
 #include "cfh_internal.hpp"
@@ -789,8 +790,8 @@ cfh_status launch_adj2_b(uint64_t ntiles, hipStream_t s, Amp *psi, Amp *lam, con
         constexpr int T = 1 << (B - kRegDims);
         const size_t lds = a.nmg > 1 ? 2 * ((size_t)1 << LB) * sizeof(Amp) : 0;
         const void *fn = reinterpret_cast<const void *>(&k_adj2<Amp, B, HALF>);
-        static bool attr = false;
-        if (!attr) {
+        static std::atomic<bool> attr{false};  // LDS limit set once per kernel
+        if (!attr.load(std::memory_order_acquire)) {
             hipFuncAttributes fa{};
             cfh_status st = CFH_OK;
             if (!hip_ok(hipFuncGetAttributes(&fa, fn), "k_adj2: hipFuncGetAttributes", &st)) return st;
@@ -798,7 +799,7 @@ cfh_status launch_adj2_b(uint64_t ntiles, hipStream_t s, Amp *psi, Amp *lam, con
                                             (int)(160 * 1024 - fa.sharedSizeBytes)),
                         "k_adj2: hipFuncSetAttribute", &st))
                 return st;
-            attr = true;
+            attr.store(true, std::memory_order_release);
         }
         unsigned grid = (unsigned)std::min<uint64_t>(ntiles, resident_grid(fn, T, lds));
         grid = std::min(grid, max_grid);
@@ -823,8 +824,8 @@ cfh_status launch_pass2_b(uint64_t ntiles, hipStream_t s, Amp *psi, const double
         constexpr int T = 1 << (B - kRegDims);
         const size_t lds = a.nmg > 1 ? ((size_t)1 << LB) * sizeof(Amp) : 0;
         const void *fn = reinterpret_cast<const void *>(&k_pass2<Amp, B, MODE>);
-        static bool attr = false;
-        if (!attr) {
+        static std::atomic<bool> attr{false};  // LDS limit set once per kernel
+        if (!attr.load(std::memory_order_acquire)) {
             // dynamic LDS may take what the kernel's static LDS leaves of the 160 KiB
             hipFuncAttributes fa{};
             cfh_status st = CFH_OK;
@@ -833,7 +834,7 @@ cfh_status launch_pass2_b(uint64_t ntiles, hipStream_t s, Amp *psi, const double
                                             (int)(160 * 1024 - fa.sharedSizeBytes)),
                         "k_pass2: hipFuncSetAttribute", &st))
                 return st;
-            attr = true;
+            attr.store(true, std::memory_order_release);
         }
         // read-only passes: four workgroups per resident slot, so workgroups
         // finish at different times and their load and term phases drift
@@ -871,8 +872,8 @@ cfh_status launch_ham2_b(uint64_t ntiles, hipStream_t s, const Amp *psi, Amp *la
         constexpr int T = 1 << (B - kRegDims);
         const size_t lds = a.nmg > 1 ? 2 * ((size_t)1 << (B - 1)) * sizeof(Amp) : 0;
         const void *fn = reinterpret_cast<const void *>(&k_ham2<Amp, B>);
-        static bool attr = false;
-        if (!attr) {
+        static std::atomic<bool> attr{false};  // LDS limit set once per kernel
+        if (!attr.load(std::memory_order_acquire)) {
             hipFuncAttributes fa{};
             cfh_status st = CFH_OK;
             if (!hip_ok(hipFuncGetAttributes(&fa, fn), "k_ham2: hipFuncGetAttributes", &st)) return st;
@@ -880,7 +881,7 @@ cfh_status launch_ham2_b(uint64_t ntiles, hipStream_t s, const Amp *psi, Amp *la
                                             (int)(160 * 1024 - fa.sharedSizeBytes)),
                         "k_ham2: hipFuncSetAttribute", &st))
                 return st;
-            attr = true;
+            attr.store(true, std::memory_order_release);
         }
         unsigned grid = (unsigned)std::min<uint64_t>(ntiles, resident_grid(fn, T, lds));
         if (a.xrot > 0) grid &= ~7u;  // coset_of: one line group per XCD
