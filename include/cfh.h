@@ -262,7 +262,7 @@ cfh_status cfh_apply_plan(cfh_plan p, void *psi, const double *theta_dev, int in
  * frame, e even) for expectation values and H*psi on n-qubit states.  Terms
  * are grouped by x mask.  For <H> the terms are packed into read-only passes
  * of the register-tiled kernel (at most 32 terms per pass on 2^b tiles,
- * b >= 10; tuning variant 1 or smaller tiles select LDS-staged passes;
+ * b >= 10, by default 11 at complex128 and 12 at complex64; tuning variant 1 or smaller tiles select LDS-staged passes;
  * variant 5 moves the registers between micro-groups in two halves, as
  * 2^14 tiles always do).
  * H*psi runs on register-tiled passes that hold psi and H psi together
