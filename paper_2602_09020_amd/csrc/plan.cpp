@@ -463,6 +463,76 @@ std::vector<HamPass> plan_hamiltonian(int n, const std::vector<HamGroup> &groups
     return out;
 }
 
+namespace {
+
+// Term order inside one pass for a given anchor (0 = none): every term whose
+// local x lies in the current micro-group span is taken at once; otherwise the
+// span grows by the dimension that brings the most remaining terms into it;
+// a full span (kRegDims dimensions) starts over from the anchor.  Returns
+// positions into xl.
+std::vector<int> microgroup_order(const std::vector<uint64_t> &xl, uint64_t anc)
+{
+    const int m = (int)xl.size();
+    std::vector<char> used(m, 0);
+    std::vector<uint64_t> red(m);
+    std::vector<int> out;
+    out.reserve(m);
+    Span s;
+    if (anc) s.add(anc);
+    int left = m;
+    while (left > 0) {
+        for (int i = 0; i < m; ++i)
+            if (!used[i] && (red[i] = s.reduce(xl[i])) == 0) {
+                used[i] = 1;
+                out.push_back(i);
+                --left;
+            }
+        if (!left) break;
+        if (s.dim() >= kRegDims) {
+            s = Span();
+            if (anc) s.add(anc);
+            continue;
+        }
+        // adding an unused term's reduced x r brings into the span exactly the
+        // unused terms whose reduced x is r (x is in span(s, r) iff its
+        // reduction against s is 0 or r, and 0 was taken above)
+        int best = -1, best_cov = -1;
+        for (int i = 0; i < m; ++i) {
+            if (used[i]) continue;
+            int cov = 0;
+            for (int j = 0; j < m; ++j) cov += !used[j] && red[j] == red[i];
+            if (cov > best_cov) {
+                best_cov = cov;
+                best = i;
+            }
+        }
+        s.add(red[best]);
+    }
+    return out;
+}
+
+// The micro-groups build_pass_args2 cuts from terms in this order: spans of
+// at most kRegDims dimensions, each seeded with the anchor.
+int count_microgroups(const std::vector<uint64_t> &xl, const std::vector<int> &order, uint64_t anc)
+{
+    int groups = 1;
+    Span s;
+    if (anc) s.add(anc);
+    for (const int i : order) {
+        uint64_t r = s.reduce(xl[i]);
+        if (r && s.dim() == kRegDims) {
+            ++groups;
+            s = Span();
+            if (anc) s.add(anc);
+            r = s.reduce(xl[i]);
+        }
+        if (r) s.add(r);
+    }
+    return groups;
+}
+
+} // namespace
+
 std::vector<int> order_for_microgroups(const std::vector<uint64_t> &basis, const std::vector<Pauli> &p,
                                       const std::vector<int> &idx, bool anchor)
 {
@@ -472,43 +542,33 @@ std::vector<int> order_for_microgroups(const std::vector<uint64_t> &basis, const
         bool ok = false;
         xl[i] = local_coords(basis, p[idx[i]].x, &ok);
     }
-    uint64_t anc = 0;
-    if (anchor)
-        for (int i = 0; i < m && !anc; ++i) anc = xl[i];
-    std::vector<char> used(m, 0);
-    std::vector<int> out;
-    out.reserve(m);
-    Span s;
-    if (anc) s.add(anc);
-    int left = m;
-    while (left > 0) {
-        for (int i = 0; i < m; ++i)
-            if (!used[i] && s.reduce(xl[i]) == 0) {
-                used[i] = 1;
-                out.push_back(idx[i]);
-                --left;
-            }
-        if (!left) break;
-        if (s.dim() >= kRegDims) {
-            s = Span();
-            if (anc) s.add(anc);
-            continue;
-        }
-        // the dimension that brings the most remaining terms into the span
-        int best = -1, best_cov = -1;
-        for (int i = 0; i < m; ++i) {
-            if (used[i]) continue;
-            Span t = s;
-            t.add(s.reduce(xl[i]));
-            int cov = 0;
-            for (int j = 0; j < m; ++j) cov += !used[j] && t.reduce(xl[j]) == 0;
-            if (cov > best_cov) {
-                best_cov = cov;
-                best = i;
+    std::vector<int> best;
+    if (!anchor) {
+        best = microgroup_order(xl, 0);
+    } else {
+        // The anchor is register dimension 0 of every micro-group, so it
+        // decides how many micro-groups (and LDS transposes) the pass needs:
+        // try each distinct local x as the anchor and keep the order with the
+        // fewest micro-groups (the first candidate on ties).  The chosen
+        // anchor's term comes first among the nonzero ones, as the
+        // descriptor builder expects.
+        int best_n = 1 << 30;
+        std::vector<uint64_t> tried;
+        for (int c = 0; c < m; ++c) {
+            const uint64_t a = xl[c];
+            if (!a || std::find(tried.begin(), tried.end(), a) != tried.end()) continue;
+            tried.push_back(a);
+            std::vector<int> o = microgroup_order(xl, a);
+            const int n_mg = count_microgroups(xl, o, a);
+            if (n_mg < best_n) {
+                best_n = n_mg;
+                best = std::move(o);
             }
         }
-        s.add(s.reduce(xl[best]));
+        if (best.empty()) best = microgroup_order(xl, 0);  // only diagonal terms
     }
+    std::vector<int> out(best.size());
+    for (size_t i = 0; i < best.size(); ++i) out[i] = idx[best[i]];
     return out;
 }
 
